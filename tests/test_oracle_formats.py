@@ -1,0 +1,101 @@
+"""Pins of the oracle's storage-format rounding (round-to-nearest-even straight
+from FP64, saturating e4m3fn) and of its vector-operand split.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "format_cases.txt")
+FMT = {"bf16": 2, "f16": 3, "e4m3": 4}
+
+
+def _parse_value(tok):
+    # sums of terms "a", "a*2^b" or "2^b"
+    total = 0.0
+    sign = 1.0
+    if tok.startswith("-"):
+        sign, tok = -1.0, tok[1:]
+    for term in tok.split("+"):
+        if "*" in term:
+            c, p = term.split("*")
+            total += float(c) * 2.0 ** int(p[2:])
+        elif term.startswith("2^"):
+            total += 2.0 ** int(term[2:])
+        else:
+            total += float(term)
+    return sign * total
+
+
+def _cases():
+    out = []
+    for line in open(GOLD):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        fmt, val, bits, *_ = line.split()
+        out.append((fmt, _parse_value(val), int(bits, 16)))
+    return out
+
+
+@pytest.mark.parametrize("fmt,x,bits", _cases())
+def test_golden_bit_patterns(orc, fmt, x, bits):
+    assert int(orc.encode_fmt(x, FMT[fmt])) == bits
+    r = float(orc.round_fmt(x, FMT[fmt]))
+    assert float(orc.decode_fmt(bits, FMT[fmt])) == r
+
+
+@pytest.mark.parametrize("fmt,nbits", [("bf16", 16), ("f16", 16), ("e4m3", 8)])
+def test_round_trip_every_pattern(orc, fmt, nbits):
+    f = FMT[fmt]
+    L = orc.lib()
+    for b in range(1 << nbits):
+        v = L.orc_decode_fmt(b, f)
+        if v != v:  # NaN patterns
+            continue
+        assert L.orc_encode_fmt(v, f) == b, hex(b)
+
+
+def test_float16_matches_numpy(orc):
+    # numpy converts float64 -> float16 in one correctly rounded step
+    g = np.random.default_rng(0)
+    x = np.concatenate([g.standard_normal(3000) * 10.0 ** g.integers(-8, 5, 3000),
+                        1.0 + (2 * g.integers(0, 1024, 500) + 1) * 2.0**-11])  # exact ties
+    ours = orc.round_fmt(x, FMT["f16"])
+    ref = x.astype(np.float16).astype(np.float64)
+    np.testing.assert_array_equal(ours, ref)
+
+
+def test_bf16_and_e4m3_match_torch_on_float_inputs(orc):
+    # on inputs exactly representable in FP32 a conversion through FP32 is exact,
+    # so torch's float32 -> bf16 / e4m3fn rounding is an independent reference
+    g = np.random.default_rng(1)
+    x32 = (g.standard_normal(4000) * 10.0 ** g.integers(-6, 3, 4000)).astype(np.float32)
+    x = x32.astype(np.float64)
+    ref_bf = torch.from_numpy(x32).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(orc.round_fmt(x, FMT["bf16"]), ref_bf)
+    xs = np.clip(x32, -448, 448)  # torch's e4m3fn cast does not saturate
+    ref_f8 = torch.from_numpy(xs).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    np.testing.assert_array_equal(orc.round_fmt(xs.astype(np.float64), FMT["e4m3"]), ref_f8)
+
+
+def test_split_terms(orc):
+    g = np.random.default_rng(2)
+    for fmt, shift, terms, bound in ((2, 8, 2, 2.0**-16), (3, 11, 2, 2.0**-22), (1, 24, 2, 2.0**-48),
+                                     (4, 4, 3, 2.0**-11)):
+        for v in g.uniform(-1, 1, 200):
+            parts = orc.split(v, fmt, terms, shift)
+            # each part is a format value times a power of two
+            for k, p in enumerate(parts):
+                q = p * 2.0 ** (k * shift)
+                assert orc.round_fmt(q, fmt) == q
+            assert abs(v - parts.sum()) <= bound * max(abs(v), 2.0**-6)
+
+
+def test_matrix_scale_power_of_two(orc):
+    A = np.random.default_rng(3).random((20, 20))
+    assert orc.matrix_scale(A, 2) == 1.0
+    s = orc.matrix_scale(A, 4)
+    assert s == 2.0**-8 and np.max(A) / s <= 448
+    assert orc.matrix_scale(A * 1000, 4) == 4.0
