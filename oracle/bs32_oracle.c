@@ -538,7 +538,8 @@ static double weighted_max(const double* err, const double* X, const double* Xn,
   for (int64_t k = 0; k < m; ++k) {
     double W = fmax(fmax(fabs(X[k]), fabs(Xn[k])), floor_w);
     double v = fabs(err[k]) / W;
-    if (!(v <= E)) E = v; /* propagates NaN */
+    if (isnan(v)) return v; /* a NaN anywhere makes the estimate NaN */
+    if (v > E) E = v;
   }
   return E;
 }
@@ -798,7 +799,8 @@ int orc_dp54_solve(const orc_system* s, const orc_options* o, const double* y0, 
       for (int q = 0; q < 7; ++q) acc += (DP_B[q] - DP_BT[q]) * K[q][k];
       double W = fmax(fmax(fabs(X[k]), fabs(Xn[k])), fw);
       double v = fabs(ha * acc) / W;
-      if (!(v <= E)) E = v;
+      if (isnan(v) || isnan(E)) E = NAN;
+      else if (v > E) E = v;
     }
     if (!isfinite(E)) { status = ORC_NONFINITE; break; }
     double fac = (E > 0.0) ? safety * pow(o->rtol / E, 0.2) : facmax;
