@@ -1,0 +1,159 @@
+/*
+ * bs32.h -- C ABI of the MI355X (gfx950) mixed-precision Bogacki-Shampine 3(2)
+ * solver for large, fully pairwise-coupled ODE systems.
+ *
+ * The problem is the paper's general model (Sec. 2.1, eq. (1)-(2)):
+ *     dX_i/dt = F_i(t, X_i) + sum_j M_ij (.) G_ij(t, X_i, X_j),   i = 1..N,
+ * with X in R^{dN} stored agent-major, X_i = (X_{(i-1)d+1}, ..., X_{id}), and the
+ * weights M_ij = A_ij / N given by a dense N x N matrix A (uniform weights
+ * M_ij = 1/N when A is NULL).  The integrator is the BS3(2) embedded pair with
+ * FSAL (Sec. 2.2, Table Butcher-O23), the weighted max error estimate of
+ * eq. (ERROR-O23), the accept rule "error smaller than Rel", and the failure
+ * conditions of Sec. 2.2.  The reduced-precision modes put the N^2 coupling
+ * contraction in FP32, BF16, FP16 or FP8 while every stage combination, the
+ * error estimate, time and step size stay FP64 (the cast rules of Sec. 2.3).
+ *
+ * Conventions
+ *  - Ownership: the caller owns every buffer it passes; the library copies what
+ *    it needs during the call and keeps no caller pointer afterwards.
+ *  - Pointers may be host or device (HIP) memory; the library tells them apart
+ *    with hipPointerGetAttributes.  Device pointers must be on the context's device.
+ *  - Every call returns a bs32_status.  Negative codes are argument or device
+ *    errors: the context is left as it was and bs32_last_error() explains.
+ *    Positive codes are solver terminations (Sec. 2.2): y_out then holds the last
+ *    accepted state and bs32_stats() reports the time reached.
+ *  - Calls on one context are synchronous with respect to the host and must not
+ *    overlap; use one context per host thread.  Contexts are independent.
+ */
+#ifndef BS32_H
+#define BS32_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bs32_ctx bs32_ctx; /* opaque; owns every device buffer it uses */
+
+typedef enum {
+  BS32_OK = 0,
+  BS32_MAX_STEPS = 1,     /* failed + accepted steps > I_max (Sec. 2.2) */
+  BS32_MAX_REJECTS = 2,   /* failed steps > 0.85 I_max (Sec. 2.2) */
+  BS32_H_TOO_SMALL = 3,   /* step size fell to h_min = 100 eps_m (Sec. 2.2) */
+  BS32_TIMEOUT = 4,       /* wall time over the limit (Sec. 2.2) */
+  BS32_TOO_SLOW = 5,      /* wall time over the slow limit with < 10% of [t0,t1] done (Sec. 2.2) */
+  BS32_NONFINITE = 6,     /* the error estimate is NaN or infinite */
+  BS32_EINVAL = -1,       /* invalid argument */
+  BS32_ENOMEM = -2,       /* device allocation failed */
+  BS32_EDEVICE = -3,      /* HIP runtime error */
+  BS32_ESTATE = -4,       /* call out of order (e.g. solve before set_system) */
+  BS32_EUNSUPPORTED = -5  /* valid but not supported combination */
+} bs32_status;
+
+/* System kinds.  d = components per agent; the coupled component is the first. */
+typedef enum {
+  BS32_SYS_OSC2 = 1,      /* x' = v, v' = -w_i^2 x + (1/N) sum_j A_ij (x_j - x_i)          d = 2 */
+  BS32_SYS_LCO_PAPER = 2, /* paper Benchmark 1, eq. (LCO): x' = v + (1/N) sum_j A_ij (x_j - x_i),
+                             v' = -x                                                       d = 2 */
+  BS32_SYS_KURAMOTO = 3,  /* paper Benchmark 2, eq. (Kuramoto):
+                             th' = w_i + (K/N) sum_j A_ij sin(th_j - th_i)                 d = 1 */
+  BS32_SYS_GOODWIN3 = 4   /* x' = 1/(1+z^10) - b_i x + (kappa/N) sum_j A_ij (x_j - x_i),
+                             y' = x - b_i y, z' = y - b_i z                                d = 3 */
+} bs32_system_kind;
+
+/* Precision of the coupling contraction.  The stage combinations, the error
+   estimate and its norm, t, h and the controller are FP64 in every mode. */
+typedef enum {
+  BS32_PREC_FP64 = 0,         /* the paper's "Double" */
+  BS32_PREC_RHS_FP32 = 1,     /* A stored FP32; vector operand split in two FP32 terms; FP32 products,
+                                 FP64 accumulation across 32-element chunks */
+  BS32_PREC_RHS_BF16 = 2,     /* A stored BF16 (power-of-two scale); vector split in two BF16 terms;
+                                 MFMA with FP32 accumulation, FP64 across chunks */
+  BS32_PREC_RHS_FP16 = 3,     /* as BF16 with IEEE binary16 storage */
+  BS32_PREC_RHS_FP8_E4M3 = 4, /* A stored OCP e4m3fn (power-of-two scale); FP32 vector terms */
+  BS32_PREC_PAPER_SINGLE = 5, /* the paper's recipes, Sec. 2.3 Table MP-Distrib */
+  BS32_PREC_PAPER_MIXED1 = 6,
+  BS32_PREC_PAPER_MIXED2 = 7
+} bs32_precision_mode;
+
+typedef struct {
+  int32_t kind;               /* bs32_system_kind */
+  int32_t coupling_on_device; /* ignored (pointers are classified by the runtime); kept for ABI stability */
+  int64_t n;                  /* number of agents N >= 1 */
+  const double* coupling;     /* N*N row-major FP64 A_ij, or NULL for uniform weights (all ones) */
+  const double* agent_param;  /* N values: w_i (OSC2, KURAMOTO), b_i (GOODWIN3); NULL = all ones */
+  double gain;                /* K (KURAMOTO), kappa (GOODWIN3); ignored by OSC2 and LCO_PAPER */
+} bs32_system_desc;
+
+typedef struct {
+  int64_t n_accept, n_reject, n_fev; /* accepted / rejected attempts; RHS evaluations */
+  double pair_interactions;          /* n_fev * N^2 */
+  double t_reached, h_last, h_min_seen, err_last;
+  double solve_ms;                   /* host wall time of the last solve */
+  double kernel_ms;                  /* device time between the first and last kernel of the solve */
+  int32_t status;                    /* bs32_status of the last solve */
+  int32_t mode;                      /* precision mode of the last solve */
+} bs32_stats_t;
+
+typedef struct {
+  int64_t i_max;         /* attempt limit (default 100000, Sec. 2.2) */
+  double time_limit_s;   /* wall-time limit (default 5400 s, Sec. 2.2); <= 0 disables */
+  double slow_limit_s;   /* "slow solver" time (default 2700 s, Sec. 2.2); <= 0 disables */
+  double h_max;          /* <= 0: 0.1 |t1 - t0| */
+  double h0;             /* > 0: initial step (skips the starting-step evaluation) */
+  double safety, facmin, facmax; /* controller constants (defaults 0.9, 0.2, 5) */
+  int32_t fixed_step;    /* 1: every step h0, all accepted (order studies) */
+  int32_t use_graph;     /* 1 (default): replay attempts from captured HIP graphs */
+  int32_t trace;         /* 1: record one bs32_trace_rec per attempt (ring of trace_cap) */
+  int32_t trace_cap;     /* ring capacity (default 65536) */
+  int32_t controller;    /* 0 standard, 1 learned proposer (needs bs32_set_controller) */
+  int32_t tile;          /* contraction tile configuration; -1 = autotuned default */
+} bs32_options;
+
+/* One record per step attempt of the last solve (when options.trace = 1). */
+typedef struct {
+  double t, h, err, fnorm; /* time, attempted step, weighted error, weighted max norm of K1 */
+  int32_t accepted, proposer; /* proposer: 1 if the learned proposer chose h */
+} bs32_trace_rec;
+
+/* Create a context on HIP device `device`.  hip_stream: a hipStream_t to run on, or
+   NULL for a library-owned stream (default priority). */
+bs32_status bs32_create(bs32_ctx** out, int device, void* hip_stream);
+
+/* Default options (the values quoted above). */
+bs32_status bs32_default_options(bs32_options* out);
+bs32_status bs32_set_options(bs32_ctx* ctx, const bs32_options* opt);
+
+/* Copy and pack the system: A into padded row-major storage (FP64 first, other
+   formats on first use by a solve), per-agent parameters, gain.  Replaces any
+   previous system. */
+bs32_status bs32_set_system(bs32_ctx* ctx, const bs32_system_desc* desc);
+
+/* Integrate from (t0, y0) to t1.  y0 and y_out: d*N FP64 agent-major (may be the
+   same buffer).  rtol > 0, atol >= 0, t1 >= t0 (t1 == t0 copies y0).
+   precision_mode: bs32_precision_mode. */
+bs32_status bs32_solve(bs32_ctx* ctx, const double* y0, double t0, double t1, double rtol, double atol,
+                       int precision_mode, double* y_out);
+
+/* Statistics of the last solve. */
+bs32_status bs32_stats(const bs32_ctx* ctx, bs32_stats_t* out);
+
+/* Evaluate the right-hand side once in a precision mode: f = F(X) + [M*G](X)
+   (agent-major, d*N values).  For kernel tests and roofline timing: `repeat` > 1
+   evaluates it that many times back to back and returns the last. */
+bs32_status bs32_rhs(bs32_ctx* ctx, const double* y, int precision_mode, int repeat, double* f_out);
+
+/* Trace records of the last solve, oldest first; *n_records receives the count copied. */
+bs32_status bs32_get_trace(bs32_ctx* ctx, bs32_trace_rec* buf, size_t cap, size_t* n_records);
+
+/* Message of the last negative status on this context (never NULL). */
+const char* bs32_last_error(const bs32_ctx* ctx);
+
+void bs32_destroy(bs32_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BS32_H */

@@ -1,0 +1,234 @@
+"""Python binding of ``libbs32.so``, the gfx950 mixed-precision BS3(2) solver.
+
+Argument marshalling only: every step of the solver runs in the library's HIP
+kernels.  Arrays may be numpy arrays (host) or torch tensors (host or device);
+torch is used for device memory and streams, nothing else.  The C ABI is
+declared in ``include/bs32.h``.
+
+If the shared library has not been built (``python -m
+paper_2605_23727_amd.build``) importing the binding's entry points raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbs32.so")
+
+# bs32_status
+OK, MAX_STEPS, MAX_REJECTS, H_TOO_SMALL, TIMEOUT, TOO_SLOW, NONFINITE = 0, 1, 2, 3, 4, 5, 6
+EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSUPPORTED = -1, -2, -3, -4, -5
+# bs32_system_kind
+OSC2, LCO_PAPER, KURAMOTO, GOODWIN3 = 1, 2, 3, 4
+DIM = {OSC2: 2, LCO_PAPER: 2, KURAMOTO: 1, GOODWIN3: 3}
+# bs32_precision_mode
+(PREC_FP64, PREC_RHS_FP32, PREC_RHS_BF16, PREC_RHS_FP16, PREC_RHS_FP8_E4M3,
+ PREC_PAPER_SINGLE, PREC_PAPER_MIXED1, PREC_PAPER_MIXED2) = range(8)
+MODE_NAMES = {0: "fp64", 1: "rhs_fp32", 2: "rhs_bf16", 3: "rhs_fp16", 4: "rhs_fp8_e4m3", 5: "paper_single",
+              6: "paper_mixed1", 7: "paper_mixed2"}
+
+
+class SystemDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("coupling_on_device", C.c_int32), ("n", C.c_int64),
+                ("coupling", C.c_void_p), ("agent_param", C.c_void_p), ("gain", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_accept", C.c_int64), ("n_reject", C.c_int64), ("n_fev", C.c_int64),
+                ("pair_interactions", C.c_double), ("t_reached", C.c_double), ("h_last", C.c_double),
+                ("h_min_seen", C.c_double), ("err_last", C.c_double), ("solve_ms", C.c_double),
+                ("kernel_ms", C.c_double), ("status", C.c_int32), ("mode", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Options(C.Structure):
+    _fields_ = [("i_max", C.c_int64), ("time_limit_s", C.c_double), ("slow_limit_s", C.c_double),
+                ("h_max", C.c_double), ("h0", C.c_double), ("safety", C.c_double), ("facmin", C.c_double),
+                ("facmax", C.c_double), ("fixed_step", C.c_int32), ("use_graph", C.c_int32),
+                ("trace", C.c_int32), ("trace_cap", C.c_int32), ("controller", C.c_int32),
+                ("tile", C.c_int32)]
+
+
+class TraceRec(C.Structure):
+    _fields_ = [("t", C.c_double), ("h", C.c_double), ("err", C.c_double), ("fnorm", C.c_double),
+                ("accepted", C.c_int32), ("proposer", C.c_int32)]
+
+
+class BS32Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"bs32 error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+# every entry point of include/bs32.h with its ctypes signature
+_SIGS = {
+    "bs32_create": ([C.c_void_p, C.c_int, C.c_void_p], C.c_int),
+    "bs32_default_options": ([C.c_void_p], C.c_int),
+    "bs32_set_options": ([C.c_void_p, C.c_void_p], C.c_int),
+    "bs32_set_system": ([C.c_void_p, C.c_void_p], C.c_int),
+    "bs32_solve": ([C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, C.c_void_p],
+                   C.c_int),
+    "bs32_stats": ([C.c_void_p, C.c_void_p], C.c_int),
+    "bs32_rhs": ([C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p], C.c_int),
+    "bs32_get_trace": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "bs32_last_error": ([C.c_void_p], C.c_char_p),
+    "bs32_destroy": ([C.c_void_p], None),
+}
+
+
+def lib():
+    """Load libbs32.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2605_23727_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+class _Buf:
+    """A pointer to float64 data: numpy array (host) or torch tensor (host/device)."""
+
+    def __init__(self, x, n=None, writable=False):
+        self.keep = None
+        if x is None:
+            self.ptr = None
+            return
+        try:
+            import torch
+            is_t = isinstance(x, torch.Tensor)
+        except ImportError:  # pragma: no cover
+            is_t = False
+        if is_t:
+            if x.dtype != torch.float64 or not x.is_contiguous():
+                if writable:
+                    raise ValueError("output tensor must be contiguous float64")
+                x = x.to(torch.float64).contiguous()
+            if n is not None and x.numel() != n:
+                raise ValueError(f"expected {n} values, got {x.numel()}")
+            self.keep = x
+            self.ptr = x.data_ptr()
+        else:
+            if writable:
+                if not (isinstance(x, np.ndarray) and x.dtype == np.float64 and x.flags.c_contiguous):
+                    raise ValueError("output array must be contiguous float64")
+                arr = x
+            else:
+                arr = np.ascontiguousarray(x, dtype=np.float64)
+            if n is not None and arr.size != n:
+                raise ValueError(f"expected {n} values, got {arr.size}")
+            self.keep = arr
+            self.ptr = arr.ctypes.data
+
+
+class Solver:
+    """One library context (device buffers, stream, packed system)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        L = lib()
+        self._ctx = C.c_void_p()
+        sp = None
+        if stream is not None:
+            sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        rc = L.bs32_create(C.byref(self._ctx), device, sp)
+        if rc != 0:
+            raise BS32Error(rc, "bs32_create failed")
+        self.kind = None
+        self.n = None
+        self._opt = Options()
+        L.bs32_default_options(C.byref(self._opt))
+
+    def _check(self, rc, allow_positive=False):
+        if rc < 0 or (rc > 0 and not allow_positive):
+            msg = lib().bs32_last_error(self._ctx)
+            raise BS32Error(rc, msg.decode() if msg else "")
+        return rc
+
+    def close(self):
+        if self._ctx:
+            lib().bs32_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- options
+    @property
+    def options(self):
+        return {f: getattr(self._opt, f) for f, _ in Options._fields_}
+
+    def set_options(self, **kw):
+        o = Options()
+        C.memmove(C.byref(o), C.byref(self._opt), C.sizeof(Options))
+        for k, v in kw.items():
+            if not hasattr(o, k):
+                raise KeyError(k)
+            setattr(o, k, v)
+        self._check(lib().bs32_set_options(self._ctx, C.byref(o)))
+        self._opt = o
+
+    # -- system
+    def set_system(self, kind, n, A=None, param=None, gain=1.0):
+        Ab = _Buf(A, n * n)
+        pb = _Buf(param, n)
+        d = SystemDesc(kind, 0, n, Ab.ptr, pb.ptr, float(gain))
+        self._check(lib().bs32_set_system(self._ctx, C.byref(d)))
+        self.kind, self.n = kind, n
+
+    def set_workload(self, w):
+        self.set_system(w["kind"], w["n"], w["A"], w["param"], w["gain"])
+
+    # -- solve
+    def solve(self, y0, t0, t1, rtol, atol=None, mode=PREC_FP64, out=None):
+        """Integrate; returns (y_out, stats dict).  Solver terminations (status > 0)
+        are reported in stats['status'], not raised."""
+        m = DIM[self.kind] * self.n
+        yb = _Buf(y0, m)
+        if out is None:
+            out = np.empty(m)
+        ob = _Buf(out, m, writable=True)
+        rc = lib().bs32_solve(self._ctx, yb.ptr, float(t0), float(t1), float(rtol),
+                              float(rtol if atol is None else atol), int(mode), ob.ptr)
+        self._check(rc, allow_positive=True)
+        return out, self.stats()
+
+    def stats(self):
+        s = Stats()
+        self._check(lib().bs32_stats(self._ctx, C.byref(s)))
+        return s.as_dict()
+
+    def rhs(self, y, mode=PREC_FP64, repeat=1, out=None):
+        m = DIM[self.kind] * self.n
+        yb = _Buf(y, m)
+        if out is None:
+            out = np.empty(m)
+        ob = _Buf(out, m, writable=True)
+        self._check(lib().bs32_rhs(self._ctx, yb.ptr, int(mode), int(repeat), ob.ptr))
+        return out
+
+    def trace(self, cap=1 << 20):
+        buf = (TraceRec * cap)()
+        n = C.c_size_t(0)
+        self._check(lib().bs32_get_trace(self._ctx, buf, cap, C.byref(n)))
+        return np.array([(r.t, r.h, r.err, r.fnorm, r.accepted, r.proposer) for r in buf[: n.value]],
+                        dtype=[("t", "f8"), ("h", "f8"), ("err", "f8"), ("fnorm", "f8"), ("accepted", "i4"),
+                               ("proposer", "i4")])

@@ -1,0 +1,644 @@
+// bs32_capi.cpp -- C ABI and host orchestration of the gfx950 BS3(2) solver.
+//
+// A solve runs entirely from device-resident state: the control block (t, h,
+// counters, status, FSAL and solution buffer indices) lives in device memory
+// and is updated by the last workgroup of each attempt's final contraction.
+// The host only enqueues attempts in chunks (replayed from captured HIP
+// graphs), reads the control block back once per chunk, and enforces the
+// wall-clock failure conditions of Sec. 2.2.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/bs32.h"
+#include "bs32_internal.hpp"
+
+using namespace bs32;
+
+struct bs32_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  bs32_options opt{};
+
+  // system
+  bool has_sys = false;
+  int kind = 0, d = 0, m = 0;
+  long long n = 0, np = 0, ld = 0;
+  double gain = 1.0;
+  double* A64 = nullptr;
+  double* param = nullptr;
+  double* rsum64 = nullptr;
+
+  // state buffers
+  long long st_np = 0;
+  int st_S = 0;
+  double* X[2] = {nullptr, nullptr};
+  double* Kf[2] = {nullptr, nullptr};
+  double* K2 = nullptr;
+  double* K3 = nullptr;
+  double* V64[2] = {nullptr, nullptr};
+  double* part = nullptr;
+  double* ep0 = nullptr;
+  double* ep1 = nullptr;
+  unsigned* rbcnt = nullptr;
+  unsigned* gcnt = nullptr;
+  double* stage_buf = nullptr;  // d*n staging for host <-> device copies
+  Ctl* ctl_d = nullptr;
+  Ctl* ctl_h[2] = {nullptr, nullptr};  // pinned host mirrors
+  TraceRec* trace_d = nullptr;
+  int trace_alloc = 0;
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_chunk[2] = {nullptr, nullptr};
+
+  // captured attempt chunks: key = (attempts) ; invalidated when the launch set changes
+  std::map<int, hipGraphExec_t> graphs;
+  std::string graph_key;
+
+  bs32_stats_t st{};
+};
+
+namespace {
+
+bs32_status fail(bs32_ctx* c, bs32_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                                          \
+  do {                                                                                             \
+    hipError_t e_ = (call);                                                                        \
+    if (e_ != hipSuccess) {                                                                        \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? BS32_ENOMEM : BS32_EDEVICE, "%s failed: %s", #call, \
+                  hipGetErrorString(e_));                                                          \
+    }                                                                                              \
+  } while (0)
+
+bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t at;
+  hipError_t e = hipPointerGetAttributes(&at, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+}
+
+long long roundup(long long x, long long m) { return (x + m - 1) / m * m; }
+
+void free_graphs(bs32_ctx* c) {
+  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) hipFree((void*)p);
+  p = nullptr;
+}
+
+void free_state(bs32_ctx* c) {
+  free_graphs(c);
+  for (int q = 0; q < 2; ++q) {
+    dfree(c->X[q]);
+    dfree(c->Kf[q]);
+    dfree(c->V64[q]);
+  }
+  dfree(c->K2);
+  dfree(c->K3);
+  dfree(c->part);
+  dfree(c->ep0);
+  dfree(c->ep1);
+  dfree(c->rbcnt);
+  dfree(c->gcnt);
+  dfree(c->stage_buf);
+  c->st_np = 0;
+  c->st_S = 0;
+}
+
+void free_system(bs32_ctx* c) {
+  free_state(c);
+  dfree(c->A64);
+  dfree(c->param);
+  dfree(c->rsum64);
+  c->has_sys = false;
+}
+
+// Contraction geometry of the current system for a tile configuration.
+struct Geom {
+  Tile t;
+  int RB, nrb, S, KS;
+};
+
+Tile default_tile(const bs32_ctx* c, int fmt) {
+  (void)fmt;
+  if (c->n <= 1024) return Tile{1, 4, 4, 0};
+  return Tile{2, 4, 2, 0};
+}
+
+Geom geometry(const bs32_ctx* c, int fmt, Tile t) {
+  Geom g;
+  g.t = t;
+  g.RB = tile_rows(fmt, t);
+  g.nrb = (int)((c->np + g.RB - 1) / g.RB);
+  const int kal = tile_kalign(fmt, t);
+  int S = t.S;
+  if (S <= 0) {
+    // enough workgroups to cover 256 CUs several times, slices of >= 1024 columns
+    S = (int)std::max(1LL, std::min((long long)((2048 + g.nrb - 1) / g.nrb), c->ld / 1024));
+  }
+  long long KS = roundup((c->ld + S - 1) / S, kal);
+  S = (int)((c->ld + KS - 1) / KS);
+  g.S = S;
+  g.KS = (int)KS;
+  return g;
+}
+
+bs32_status ensure_state(bs32_ctx* c, const Geom& g) {
+  const long long np = c->np;
+  if (c->st_np == np && c->st_S >= g.S && c->ep0) return BS32_OK;
+  free_state(c);
+  const size_t sv = sizeof(double) * (size_t)(c->d * np);
+  for (int q = 0; q < 2; ++q) {
+    HIPCHK(c, hipMalloc((void**)&c->X[q], sv));
+    HIPCHK(c, hipMalloc((void**)&c->Kf[q], sv));
+    HIPCHK(c, hipMalloc((void**)&c->V64[q], sizeof(double) * (size_t)(2 * c->ld)));
+    HIPCHK(c, hipMemset(c->X[q], 0, sv));
+    HIPCHK(c, hipMemset(c->Kf[q], 0, sv));
+    HIPCHK(c, hipMemset(c->V64[q], 0, sizeof(double) * (size_t)(2 * c->ld)));
+  }
+  HIPCHK(c, hipMalloc((void**)&c->K2, sv));
+  HIPCHK(c, hipMalloc((void**)&c->K3, sv));
+  HIPCHK(c, hipMemset(c->K2, 0, sv));
+  HIPCHK(c, hipMemset(c->K3, 0, sv));
+  const int Smax = std::max(g.S, 16);
+  HIPCHK(c, hipMalloc((void**)&c->part, sizeof(double) * (size_t)Smax * (size_t)np * 2));
+  const long long maxrb = np;  // at most one row per block
+  HIPCHK(c, hipMalloc((void**)&c->ep0, sizeof(double) * (size_t)maxrb));
+  HIPCHK(c, hipMalloc((void**)&c->ep1, sizeof(double) * (size_t)maxrb));
+  HIPCHK(c, hipMalloc((void**)&c->rbcnt, sizeof(unsigned) * (size_t)maxrb));
+  HIPCHK(c, hipMemset(c->rbcnt, 0, sizeof(unsigned) * (size_t)maxrb));
+  HIPCHK(c, hipMalloc((void**)&c->gcnt, sizeof(unsigned) * 4));
+  HIPCHK(c, hipMemset(c->gcnt, 0, sizeof(unsigned) * 4));
+  HIPCHK(c, hipMalloc((void**)&c->stage_buf, sv));
+  c->st_np = np;
+  c->st_S = Smax;
+  return BS32_OK;
+}
+
+Args make_args(bs32_ctx* c, const Geom& g, int stage) {
+  Args a{};
+  a.A = c->A64;
+  a.rsum = c->rsum64;
+  a.param = c->param;
+  for (int q = 0; q < 2; ++q) {
+    a.X[q] = c->X[q];
+    a.Kf[q] = c->Kf[q];
+    a.V64[q] = c->V64[q];
+    a.Vq[q] = nullptr;
+  }
+  a.K2 = c->K2;
+  a.K3 = c->K3;
+  a.part = c->part;
+  a.ep0 = c->ep0;
+  a.ep1 = c->ep1;
+  a.rbcnt = c->rbcnt;
+  a.gcnt = c->gcnt;
+  a.ctl = c->ctl_d;
+  a.trace = c->trace_d;
+  a.gain = c->gain;
+  a.invN = 1.0 / (double)c->n;
+  a.scale = 1.0;
+  a.n = c->n;
+  a.np = c->np;
+  a.ld = c->ld;
+  a.kind = c->kind;
+  a.d = c->d;
+  a.m = c->m;
+  a.stage = stage;
+  a.nrb = g.nrb;
+  a.S = g.S;
+  a.KS = g.KS;
+  a.RB = g.RB;
+  return a;
+}
+
+// upload an agent-major vector (host or device) into SoA buffer dst
+bs32_status upload_state(bs32_ctx* c, const double* y, double* dst) {
+  const size_t bytes = sizeof(double) * (size_t)(c->d * c->n);
+  const bool dev = is_device_ptr(y);
+  HIPCHK(c, hipMemcpyAsync(c->stage_buf, y, bytes, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, launch_to_soa(c->stage_buf, dst, c->n, c->d, c->np, c->stream));
+  return BS32_OK;
+}
+
+bs32_status download_state(bs32_ctx* c, const double* src, double* y) {
+  const size_t bytes = sizeof(double) * (size_t)(c->d * c->n);
+  HIPCHK(c, launch_from_soa(src, c->stage_buf, c->n, c->d, c->np, c->stream));
+  const bool dev = is_device_ptr(y);
+  HIPCHK(c, hipMemcpyAsync(y, c->stage_buf, bytes, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return BS32_OK;
+}
+
+__attribute__((unused)) int mode_fmt(int mode) {
+  switch (mode) {
+    case BS32_PREC_RHS_FP32: return F_F32;
+    case BS32_PREC_RHS_BF16: return F_BF16;
+    case BS32_PREC_RHS_FP16: return F_F16;
+    case BS32_PREC_RHS_FP8_E4M3: return F_E4M3;
+    default: return F_F64;
+  }
+}
+
+hipError_t enqueue_attempt(bs32_ctx* c, const Geom& g, int fmt) {
+  hipError_t e;
+  Args a = make_args(c, g, ST_S2);
+  if ((e = launch_prep(a, c->stream)) != hipSuccess) return e;
+  if ((e = launch_contract(a, fmt, g.t, c->stream)) != hipSuccess) return e;
+  a.stage = ST_S3;
+  if ((e = launch_contract(a, fmt, g.t, c->stream)) != hipSuccess) return e;
+  a.stage = ST_S4;
+  return launch_contract(a, fmt, g.t, c->stream);
+}
+
+bs32_status run_chunk(bs32_ctx* c, const Geom& g, int fmt, int attempts) {
+  if (!c->opt.use_graph) {
+    for (int q = 0; q < attempts; ++q) HIPCHK(c, enqueue_attempt(c, g, fmt));
+    return BS32_OK;
+  }
+  auto it = c->graphs.find(attempts);
+  if (it == c->graphs.end()) {
+    hipGraph_t graph;
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int q = 0; q < attempts && e == hipSuccess; ++q) e = enqueue_attempt(c, g, fmt);
+    hipError_t e2 = hipStreamEndCapture(c->stream, &graph);
+    if (e != hipSuccess) return fail(c, BS32_EDEVICE, "launch during capture failed: %s", hipGetErrorString(e));
+    if (e2 != hipSuccess) return fail(c, BS32_EDEVICE, "graph capture failed: %s", hipGetErrorString(e2));
+    hipGraphExec_t ex;
+    e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(c, BS32_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+    it = c->graphs.emplace(attempts, ex).first;
+  }
+  HIPCHK(c, hipGraphLaunch(it->second, c->stream));
+  return BS32_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bs32_status bs32_default_options(bs32_options* o) {
+  if (!o) return BS32_EINVAL;
+  std::memset(o, 0, sizeof(*o));
+  o->i_max = 100000;
+  o->time_limit_s = 5400.0;
+  o->slow_limit_s = 2700.0;
+  o->h_max = 0.0;
+  o->h0 = 0.0;
+  o->safety = 0.9;
+  o->facmin = 0.2;
+  o->facmax = 5.0;
+  o->fixed_step = 0;
+  o->use_graph = 1;
+  o->trace = 0;
+  o->trace_cap = 65536;
+  o->controller = 0;
+  o->tile = -1;
+  return BS32_OK;
+}
+
+bs32_status bs32_create(bs32_ctx** out, int device, void* hip_stream) {
+  if (!out) return BS32_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return BS32_EDEVICE;
+  if (device < 0 || device >= ndev) return BS32_EINVAL;
+  bs32_ctx* c = new bs32_ctx();
+  c->device = device;
+  bs32_default_options(&c->opt);
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return BS32_EDEVICE;
+  }
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return BS32_EDEVICE;
+    }
+    c->own_stream = true;
+  }
+  bool ok = hipMalloc((void**)&c->ctl_d, sizeof(Ctl)) == hipSuccess &&
+            hipHostMalloc((void**)&c->ctl_h[0], sizeof(Ctl), hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void**)&c->ctl_h[1], sizeof(Ctl), hipHostMallocDefault) == hipSuccess &&
+            hipEventCreate(&c->ev_start) == hipSuccess && hipEventCreate(&c->ev_stop) == hipSuccess &&
+            hipEventCreateWithFlags(&c->ev_chunk[0], hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&c->ev_chunk[1], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    bs32_destroy(c);
+    return BS32_ENOMEM;
+  }
+  std::memset(c->ctl_h[0], 0, sizeof(Ctl));
+  std::memset(c->ctl_h[1], 0, sizeof(Ctl));
+  *out = c;
+  return BS32_OK;
+}
+
+void bs32_destroy(bs32_ctx* c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  if (c->stream) hipStreamSynchronize(c->stream);
+  free_system(c);
+  dfree(c->ctl_d);
+  dfree(c->trace_d);
+  for (int q = 0; q < 2; ++q)
+    if (c->ctl_h[q]) hipHostFree(c->ctl_h[q]);
+  if (c->ev_start) hipEventDestroy(c->ev_start);
+  if (c->ev_stop) hipEventDestroy(c->ev_stop);
+  for (int q = 0; q < 2; ++q)
+    if (c->ev_chunk[q]) hipEventDestroy(c->ev_chunk[q]);
+  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* bs32_last_error(const bs32_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+bs32_status bs32_set_options(bs32_ctx* c, const bs32_options* o) {
+  if (!c || !o) return fail(c, BS32_EINVAL, "null argument");
+  if (o->i_max <= 0) return fail(c, BS32_EINVAL, "i_max must be positive");
+  if (!(o->safety > 0 && o->facmin > 0 && o->facmax >= 1.0 && o->facmin <= 1.0))
+    return fail(c, BS32_EINVAL, "controller constants out of range");
+  if (o->trace && (o->trace_cap <= 0 || o->trace_cap > (1 << 26))) return fail(c, BS32_EINVAL, "bad trace_cap");
+  if (o->fixed_step && !(o->h0 > 0)) return fail(c, BS32_EINVAL, "fixed_step needs h0 > 0");
+  c->opt = *o;
+  free_graphs(c);
+  return BS32_OK;
+}
+
+bs32_status bs32_set_system(bs32_ctx* c, const bs32_system_desc* sd) {
+  if (!c || !sd) return fail(c, BS32_EINVAL, "null argument");
+  const int d = dim_of(sd->kind);
+  if (d == 0) return fail(c, BS32_EINVAL, "unknown system kind %d", sd->kind);
+  if (sd->n < 1 || sd->n > (1LL << 20)) return fail(c, BS32_EINVAL, "n out of range: %lld", (long long)sd->n);
+  if (!std::isfinite(sd->gain)) return fail(c, BS32_EINVAL, "gain must be finite");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  free_system(c);
+  c->kind = sd->kind;
+  c->d = d;
+  c->m = vcols_of(sd->kind);
+  c->n = sd->n;
+  c->gain = sd->gain;
+  c->np = roundup(c->n, 256);
+  c->ld = roundup(c->n, 256);
+  const size_t abytes = sizeof(double) * (size_t)c->np * (size_t)c->ld;
+  HIPCHK(c, hipMalloc((void**)&c->A64, abytes));
+  HIPCHK(c, hipMemsetAsync(c->A64, 0, abytes, c->stream));
+  const double* src = sd->coupling;
+  double* tmp = nullptr;
+  if (src && !is_device_ptr(src)) {
+    HIPCHK(c, hipMalloc((void**)&tmp, sizeof(double) * (size_t)(c->n * c->n)));
+    HIPCHK(c, hipMemcpyAsync(tmp, src, sizeof(double) * (size_t)(c->n * c->n), hipMemcpyHostToDevice, c->stream));
+    src = tmp;
+  }
+  HIPCHK(c, launch_pack_f64(src, c->A64, c->n, c->ld, c->n, src == nullptr ? 1 : 0, c->stream));
+  HIPCHK(c, hipMalloc((void**)&c->rsum64, sizeof(double) * (size_t)c->np));
+  HIPCHK(c, hipMemsetAsync(c->rsum64, 0, sizeof(double) * (size_t)c->np, c->stream));
+  HIPCHK(c, launch_rowsum(c->A64, F_F64, 1.0, c->rsum64, c->n, c->ld, c->stream));
+  HIPCHK(c, hipMalloc((void**)&c->param, sizeof(double) * (size_t)c->np));
+  if (sd->agent_param) {
+    HIPCHK(c, hipMemcpyAsync(c->param, sd->agent_param, sizeof(double) * (size_t)c->n,
+                             is_device_ptr(sd->agent_param) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                             c->stream));
+  } else {
+    std::vector<double> ones((size_t)c->n, 1.0);
+    HIPCHK(c, hipMemcpyAsync(c->param, ones.data(), sizeof(double) * (size_t)c->n, hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (tmp) hipFree(tmp);
+  c->has_sys = true;
+  std::memset(&c->st, 0, sizeof(c->st));
+  return BS32_OK;
+}
+
+bs32_status bs32_stats(const bs32_ctx* c, bs32_stats_t* out) {
+  if (!c || !out) return BS32_EINVAL;
+  *out = c->st;
+  return BS32_OK;
+}
+
+static bs32_status prepare(bs32_ctx* c, int mode, Geom* g, int* fmt) {
+  if (!c->has_sys) return fail(c, BS32_ESTATE, "no system set");
+  if (mode < 0 || mode > 7) return fail(c, BS32_EINVAL, "unknown precision mode %d", mode);
+  if (mode != BS32_PREC_FP64) return fail(c, BS32_EUNSUPPORTED, "precision mode %d not built yet", mode);
+  *fmt = F_F64;
+  Tile t = default_tile(c, *fmt);
+  *g = geometry(c, *fmt, t);
+  bs32_status s = ensure_state(c, *g);
+  if (s != BS32_OK) return s;
+  const std::string key = std::to_string(mode) + "/" + std::to_string(g->t.R) + "/" + std::to_string(g->t.W) + "/" +
+                          std::to_string(g->t.U) + "/" + std::to_string(g->S);
+  if (key != c->graph_key) {
+    free_graphs(c);
+    c->graph_key = key;
+  }
+  return BS32_OK;
+}
+
+bs32_status bs32_rhs(bs32_ctx* c, const double* y, int mode, int repeat, double* f_out) {
+  if (!c || !y || !f_out) return fail(c, BS32_EINVAL, "null argument");
+  if (repeat < 1) return fail(c, BS32_EINVAL, "repeat must be >= 1");
+  HIPCHK(c, hipSetDevice(c->device));
+  Geom g;
+  int fmt;
+  bs32_status s = prepare(c, mode, &g, &fmt);
+  if (s != BS32_OK) return s;
+  Ctl* h = c->ctl_h[0];
+  std::memset(h, 0, sizeof(Ctl));
+  h->status = kRunning;
+  h->rtol = 1.0;
+  h->atol = 1.0;
+  HIPCHK(c, hipMemcpyAsync(c->ctl_d, h, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
+  s = upload_state(c, y, c->X[0]);
+  if (s != BS32_OK) return s;
+  Args a = make_args(c, g, ST_RHS);
+  for (int r = 0; r < repeat; ++r) {
+    HIPCHK(c, launch_prep(a, c->stream));
+    HIPCHK(c, launch_contract(a, fmt, g.t, c->stream));
+  }
+  return download_state(c, c->Kf[0], f_out);
+}
+
+bs32_status bs32_solve(bs32_ctx* c, const double* y0, double t0, double t1, double rtol, double atol, int mode,
+                       double* y_out) {
+  if (!c || !y0 || !y_out) return fail(c, BS32_EINVAL, "null argument");
+  if (!(rtol > 0.0) || !(atol >= 0.0) || !std::isfinite(rtol) || !std::isfinite(atol))
+    return fail(c, BS32_EINVAL, "need rtol > 0 and atol >= 0");
+  if (!std::isfinite(t0) || !std::isfinite(t1) || !(t1 >= t0)) return fail(c, BS32_EINVAL, "need t1 >= t0");
+  HIPCHK(c, hipSetDevice(c->device));
+  Geom g;
+  int fmt;
+  bs32_status s = prepare(c, mode, &g, &fmt);
+  if (s != BS32_OK) return s;
+  const auto wall0 = std::chrono::steady_clock::now();
+  std::memset(&c->st, 0, sizeof(c->st));
+  c->st.mode = mode;
+  if (t1 == t0) {
+    const size_t bytes = sizeof(double) * (size_t)(c->d * c->n);
+    if (y_out != y0) {
+      const bool di = is_device_ptr(y0), dout = is_device_ptr(y_out);
+      HIPCHK(c, hipMemcpyAsync(y_out, y0, bytes,
+                               di ? (dout ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost)
+                                  : (dout ? hipMemcpyHostToDevice : hipMemcpyHostToHost),
+                               c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    c->st.t_reached = t0;
+    c->st.status = BS32_OK;
+    return BS32_OK;
+  }
+  const bs32_options& o = c->opt;
+  // trace ring
+  if (o.trace && c->trace_alloc < o.trace_cap) {
+    dfree(c->trace_d);
+    HIPCHK(c, hipMalloc((void**)&c->trace_d, sizeof(TraceRec) * (size_t)o.trace_cap));
+    c->trace_alloc = o.trace_cap;
+    free_graphs(c);
+  }
+  Ctl* h = c->ctl_h[0];
+  std::memset(h, 0, sizeof(Ctl));
+  h->t = t0;
+  h->t0 = t0;
+  h->t1 = t1;
+  h->rtol = rtol;
+  h->atol = atol;
+  h->h_max = o.h_max > 0.0 ? o.h_max : 0.1 * std::fabs(t1 - t0);
+  h->h_min = 100.0 * 2.220446049250313e-16;  // 100 eps of the FP64 format holding h (Sec. 2.2)
+  h->snap = 4.0 * 2.220446049250313e-16 * std::fabs(t1);
+  h->safety = o.safety;
+  h->facmin = o.facmin;
+  h->facmax = o.facmax;
+  h->h_min_seen = INFINITY;
+  h->h0user = o.h0 > 0.0 ? o.h0 : 0.0;
+  h->i_max = o.i_max;
+  h->status = kRunning;
+  h->fixed_step = o.fixed_step;
+  h->trace_on = o.trace ? 1 : 0;
+  h->trace_cap = o.trace ? o.trace_cap : 1;
+  HIPCHK(c, hipMemcpyAsync(c->ctl_d, h, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
+  s = upload_state(c, y0, c->X[0]);
+  if (s != BS32_OK) return s;
+  HIPCHK(c, hipEventRecord(c->ev_start, c->stream));
+  {
+    Args a = make_args(c, g, ST_INIT);
+    HIPCHK(c, launch_prep(a, c->stream));
+    HIPCHK(c, launch_contract(a, fmt, g.t, c->stream));
+    if (!(o.h0 > 0.0)) {
+      a.stage = ST_H0;
+      HIPCHK(c, launch_prep(a, c->stream));
+      HIPCHK(c, launch_contract(a, fmt, g.t, c->stream));
+    }
+  }
+  // attempt chunks, one chunk always in flight ahead of the one being checked
+  int chunk = 2;
+  int k = 0;
+  s = run_chunk(c, g, fmt, chunk);
+  if (s != BS32_OK) return s;
+  HIPCHK(c, hipMemcpyAsync(c->ctl_h[0], c->ctl_d, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipEventRecord(c->ev_chunk[0], c->stream));
+  int final_status = kRunning;
+  while (true) {
+    // speculative next chunk (its kernels return at once if the solve is over)
+    s = run_chunk(c, g, fmt, chunk);
+    if (s != BS32_OK) return s;
+    HIPCHK(c, hipMemcpyAsync(c->ctl_h[(k + 1) & 1], c->ctl_d, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipEventRecord(c->ev_chunk[(k + 1) & 1], c->stream));
+    HIPCHK(c, hipEventSynchronize(c->ev_chunk[k & 1]));
+    const Ctl* cur = c->ctl_h[k & 1];
+    if (cur->status != kRunning) break;
+    const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();
+    const double frac = (cur->t - t0) / (t1 - t0);
+    if (o.time_limit_s > 0 && el > o.time_limit_s) { final_status = BS32_TIMEOUT; break; }
+    if (o.slow_limit_s > 0 && el > o.slow_limit_s && frac < 0.1) { final_status = BS32_TOO_SLOW; break; }
+    // size the next chunk from the remaining attempts the current step suggests
+    const double est = (cur->h > 0) ? (t1 - cur->t) / cur->h : 1e9;
+    int want = (int)std::min(64.0, std::max(2.0, std::ceil(0.5 * est)));
+    int p2 = 2;
+    while (p2 < want) p2 <<= 1;
+    chunk = std::min(64, std::max(2, std::min(p2, chunk * 2)));
+    ++k;
+  }
+  if (final_status != kRunning) {
+    HIPCHK(c, launch_set_status(c->ctl_d, final_status, c->stream));
+  }
+  HIPCHK(c, hipEventRecord(c->ev_stop, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->ctl_h[0], c->ctl_d, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const Ctl fin = *c->ctl_h[0];
+  s = download_state(c, c->X[fin.xi], y_out);
+  if (s != BS32_OK) return s;
+  float kms = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&kms, c->ev_start, c->ev_stop));
+  c->st.n_accept = fin.n_accept;
+  c->st.n_reject = fin.n_reject;
+  c->st.n_fev = fin.n_fev;
+  c->st.pair_interactions = (double)fin.n_fev * (double)c->n * (double)c->n;
+  c->st.t_reached = fin.t;
+  c->st.h_last = fin.h_last;
+  c->st.h_min_seen = fin.h_min_seen;
+  c->st.err_last = fin.err;
+  c->st.kernel_ms = kms;
+  c->st.status = fin.status;
+  c->st.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
+  return (bs32_status)fin.status;
+}
+
+bs32_status bs32_get_trace(bs32_ctx* c, bs32_trace_rec* buf, size_t cap, size_t* n_records) {
+  if (!c || !n_records || (cap && !buf)) return fail(c, BS32_EINVAL, "null argument");
+  *n_records = 0;
+  if (!c->trace_d || !c->opt.trace) return BS32_OK;
+  const Ctl* h = c->ctl_h[0];
+  const long long total = h->trace_n;
+  const long long ring = c->opt.trace_cap;
+  const long long have = std::min(total, ring);
+  const long long first = total - have;
+  std::vector<TraceRec> tmp((size_t)ring);
+  HIPCHK(c, hipMemcpy(tmp.data(), c->trace_d, sizeof(TraceRec) * (size_t)ring, hipMemcpyDeviceToHost));
+  size_t outn = 0;
+  for (long long q = first; q < total && outn < cap; ++q) {
+    const TraceRec& r = tmp[(size_t)(q % ring)];
+    buf[outn].t = r.t;
+    buf[outn].h = r.h;
+    buf[outn].err = r.err;
+    buf[outn].fnorm = r.fnorm;
+    buf[outn].accepted = r.accepted;
+    buf[outn].proposer = r.proposer;
+    ++outn;
+  }
+  *n_records = outn;
+  return BS32_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,109 @@
+// bs32_internal.hpp -- shared declarations of the gfx950 BS3(2) library
+// (host orchestration in bs32_capi.cpp, kernels in bs32_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bs32 {
+
+// ---- BS3(2) tableau (Sec. 2.2, Table Butcher-O23) --------------------------
+constexpr double kA21 = 1.0 / 2.0;
+constexpr double kA32 = 3.0 / 4.0;
+constexpr double kB1 = 2.0 / 9.0, kB2 = 1.0 / 3.0, kB3 = 4.0 / 9.0;
+constexpr double kBt1 = 7.0 / 24.0, kBt2 = 1.0 / 4.0, kBt3 = 1.0 / 3.0, kBt4 = 1.0 / 8.0;
+constexpr double kC2 = 1.0 / 2.0, kC3 = 3.0 / 4.0;
+
+// internal solver status (public codes are bs32_status values >= 0)
+constexpr int kRunning = 100;
+
+// stages of one contraction launch
+enum Stage : int { ST_INIT = 0, ST_H0 = 1, ST_S2 = 2, ST_S3 = 3, ST_S4 = 4, ST_RHS = 5 };
+
+// storage formats of the coupling matrix
+enum Fmt : int { F_F64 = 0, F_F32 = 1, F_BF16 = 2, F_F16 = 3, F_E4M3 = 4 };
+
+// Device-resident control block of one solve: the step-size state lives on the
+// GPU so that attempts run back to back without host round trips.
+struct Ctl {
+  double t, h, ha;        // time, proposed step, step of the current attempt (clipped to t1)
+  double t0, t1, rtol, atol;
+  double h_max, h_min, snap;
+  double safety, facmin, facmax;
+  double err, h_last, h_min_seen;
+  double h0probe;         // starting-step probe size (Hairer-Norsett-Wanner)
+  double h0user;          // > 0: user initial step
+  double d0, d1;          // starting-step norms of y0 and f0
+  long long n_accept, n_reject, n_fev, i_max;
+  int status;             // kRunning or a final bs32_status
+  int xi;                 // current solution buffer (X^n = X[xi], X^{n+1} -> X[1-xi])
+  int ki;                 // current first-stage buffer (K1 = Kf[ki], K4 -> Kf[1-ki])
+  int last_rejected;
+  int fixed_step;
+  int trace_on;
+  int trace_cap;
+  int pad0;
+  long long trace_n;      // attempts recorded so far (ring index = trace_n % cap)
+};
+
+struct TraceRec {
+  double t, h, err, fnorm;
+  int accepted, proposer;
+};
+
+// Arguments of the contraction / prep kernels (passed by value).
+struct Args {
+  const void* A;          // packed coupling, rows_pad x ld, format-dependent
+  const double* rsum;     // row sums of the stored (dequantized) A, length n
+  const double* param;    // per-agent parameter (omega or b), length n
+  double* X[2];           // SoA state ping-pong, d x np each
+  double* Kf[2];          // first/last stage ping-pong (FSAL)
+  double* K2;
+  double* K3;
+  double* V64[2];         // FP64 vector operand ping-pong, [np][m]
+  void* Vq[2];            // split vector operand terms for reduced formats
+  double* part;           // split-K partials [S][np][m]
+  double* ep0;            // per-row-block partial maxima
+  double* ep1;
+  unsigned* rbcnt;        // per-row-block arrival counters (split-K fixup)
+  unsigned* gcnt;         // grid arrival counter (norm reduction / controller)
+  Ctl* ctl;
+  TraceRec* trace;
+  double gain, invN, scale; // coupling gain, 1/N, per-tensor scale of A
+  long long n, np, ld;    // agents, padded rows, leading dimension (elements)
+  int kind, d, m;         // system kind, components per agent, vector columns
+  int stage;
+  int nrb, S, KS;         // row blocks, k-slices, columns per slice
+  int RB;                 // rows per block
+  int vterms;             // split terms of the vector operand (reduced formats)
+  int vshift;             // exponent shift between consecutive terms
+  int ldv;                // leading dimension of one Vq column (elements)
+};
+
+// tile configuration of the contraction
+struct Tile {
+  int R;   // rows per wave (VALU kernels) or 16-row MFMA tiles per wave
+  int W;   // waves per workgroup
+  int U;   // k-unroll
+  int S;   // split-K slices (0 = choose from N)
+};
+
+// host launchers (bs32_kernels.hip)
+int dim_of(int kind);
+int vcols_of(int kind);
+hipError_t launch_prep(const Args& a, hipStream_t s);
+hipError_t launch_set_status(Ctl* c, int code, hipStream_t s);
+hipError_t launch_contract(const Args& a, int fmt, const Tile& t, hipStream_t s);
+hipError_t launch_to_soa(const double* src, double* dst, long long n, int d, long long np, hipStream_t s);
+hipError_t launch_from_soa(const double* src, double* dst, long long n, int d, long long np, hipStream_t s);
+hipError_t launch_pack_f64(const double* src, double* dst, long long n, long long ld, long long rows, int uniform,
+                           hipStream_t s);
+hipError_t launch_pack_fmt(const double* A64, void* dst, int fmt, double inv_scale, long long n, long long ld,
+                           long long rows, hipStream_t s);
+hipError_t launch_rowsum(const void* A, int fmt, double scale, double* rsum, long long n, long long ld,
+                         hipStream_t s);
+hipError_t launch_absmax(const double* A64, long long n, long long ld, double* out, hipStream_t s);
+int tile_rows(int fmt, const Tile& t);
+int tile_kalign(int fmt, const Tile& t);
+size_t fmt_bytes(int fmt);
+
+}  // namespace bs32
