@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Benchmark of the gfx950 BS3(2) hot path on the Kuramoto network N = 4096.
+
+Workload (paper Benchmark 2 with dense weights): theta_i' = w_i + (K/N) sum_j
+A_ij sin(theta_j - theta_i), A ~ U[0,1) with zero diagonal, w ~ N(0,1),
+theta0 ~ U[0,2pi), K = 2, t in [0, 50], rtol = atol = 1e-6, seed 2000.
+
+One "step" is one complete solve t0 -> t_end (every stage of the method:
+vector operand, N^2 contractions, stage combinations, FSAL, error norm,
+controller) with the system already packed and the inputs resident in HBM.
+value = pair interactions per second over the timed steps, where one pair is
+one (i, j) term of one right-hand-side evaluation (n_fev * N^2 per solve).
+
+Also reported: time-to-t_end of each precision mode next to plain FP64, the
+normalized final error ||y - y_ref||_2 / sqrt(N) (paper eq. (Metric)) against an
+FP64 reference at rtol = 1e-12, the roofline of the contraction kernel
+(algorithmic bytes N^2 * bytes(A) per launch over its event-timed mean
+duration), and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES = {0: 8, 1: 4, 2: 2, 3: 2, 4: 1}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--rtol", type=float, default=1e-6)
+    ap.add_argument("--t1", type=float, default=50.0)
+    ap.add_argument("--modes", default="0", help="comma-separated precision modes to compare with FP64")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-ref", action="store_true", help="skip the rtol=1e-12 reference solution")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the path would shard rows of A with one all-gather per stage).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2605_23727_amd as bs
+    import workloads
+
+    dev = torch.device("cuda:0")
+    w = workloads.kuramoto(args.n, seed=2000, K=2.0, t1=args.t1, rtol=args.rtol)
+    n = w["n"]
+    A = torch.from_numpy(w["A"]).to(dev)
+    om = torch.from_numpy(w["param"]).to(dev)
+    y0 = torch.from_numpy(w["y0"]).to(dev)
+    out = torch.empty_like(y0)
+
+    s = bs.Solver(0)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter()
+    s.set_system(w["kind"], n, A, om, w["gain"])
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t_setup) * 1e3
+    del A
+
+    modes = [int(m) for m in args.modes.split(",") if m != ""]
+    head = modes[-1] if modes else 0
+
+    # reference solution (FP64 GPU path at rtol = atol = 1e-12; parity-checked against the oracle)
+    ref = None
+    if not args.no_ref:
+        log(f"reference solve (FP64, rtol=1e-12) n={n}")
+        s.set_options(i_max=10_000_000)
+        ref_t = torch.empty_like(y0)
+        _, rst = s.solve(y0, 0.0, args.t1, 1e-12, 1e-12, mode=bs.PREC_FP64, out=ref_t)
+        s.set_options(i_max=100000)
+        ref = ref_t.cpu().numpy()
+        log(f"  reference: {rst['n_accept']} accepted, {rst['solve_ms'] / 1e3:.1f} s, status {rst['status']}")
+
+    def final_err(y):
+        return None if ref is None else float(np.linalg.norm(y - ref) / math.sqrt(n))
+
+    results = {}
+    for mode in sorted(set([0] + modes)):
+        log(f"mode {bs.MODE_NAMES[mode]}: {args.warmup} warm-up + {args.steps} timed solves")
+        for _ in range(args.warmup):
+            s.solve(y0, 0.0, args.t1, args.rtol, mode=mode, out=out)
+        torch.cuda.synchronize()
+        times, pairs, stats = [], 0.0, None
+        for _ in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, stats = s.solve(y0, 0.0, args.t1, args.rtol, mode=mode, out=out)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            pairs += stats["pair_interactions"]
+        y = out.cpu().numpy()
+        kms = s.time_contraction(mode, repeat=100)
+        gbs = n * n * BYTES[min(mode, 4)] / (kms * 1e-3) / 1e9
+        results[mode] = dict(
+            name=bs.MODE_NAMES[mode], time_to_t_end_s=float(np.median(times)), ms_per_step=1e3 * sum(times) / len(times),
+            pairs_per_s=pairs / sum(times), accepted=int(stats["n_accept"]), rejected=int(stats["n_reject"]),
+            n_fev=int(stats["n_fev"]), accepted_steps_per_s=stats["n_accept"] / float(np.median(times)),
+            final_error=final_err(y), status=int(stats["status"]), contraction_ms=kms, contraction_gbs=gbs,
+            kernel_ms=stats["kernel_ms"])
+
+    r0 = results[0]
+    rh = results[head]
+    roof = dict(bound="hbm", achieved=round(rh["contraction_gbs"], 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(rh["contraction_gbs"] / HBM_PEAK_GBS, 4), traffic=None,
+                kernel=f"contraction ({rh['name']})", bytes_per_launch=n * n * BYTES[min(head, 4)],
+                avg_launch_ms=rh["contraction_ms"])
+
+    cpu = None
+    if not args.no_cpu:
+        log(f"CPU oracle baseline (~{args.cpu_seconds:g} s)")
+        cpu = cpu_baseline(w, args.cpu_seconds)
+
+    line = {
+        "metric": "pair-interactions/s + time-to-t_end vs plain FP64 GPU at matched final error",
+        "value": rh["pairs_per_s"],
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": rh["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {0: "f64", 1: "f32", 2: "bf16", 3: "f16", 4: "fp8e4m3"}[min(head, 4)] + "+f64-update",
+        "data": "synthetic",
+        "config": {"workload": f"kuramoto-dense N={n} K=2 t=[0,{args.t1:g}] rtol=atol={args.rtol:g} seed=2000",
+                   "precision_mode": rh["name"], "global_batch": 1, "seq_len": None},
+        "time_to_t_end_s": rh["time_to_t_end_s"],
+        "fp64_time_to_t_end_s": r0["time_to_t_end_s"],
+        "speedup_vs_fp64": r0["time_to_t_end_s"] / rh["time_to_t_end_s"],
+        "final_error": rh["final_error"],
+        "fp64_final_error": r0["final_error"],
+        "matched_error": (None if rh["final_error"] is None else rh["final_error"] <= 2.0 * r0["final_error"]),
+        "accepted_steps_per_s": rh["accepted_steps_per_s"],
+        "beta": (r0["accepted"] + r0["rejected"]) / max(1, rh["accepted"] + rh["rejected"]),
+        "setup_ms": setup_ms,
+        "modes": {v["name"]: {k: v[k] for k in ("time_to_t_end_s", "pairs_per_s", "accepted", "rejected",
+                                                 "final_error", "contraction_ms", "contraction_gbs", "status")}
+                  for v in results.values()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(w, seconds):
+    """The oracle as it stands, timed on this host's cores on a bounded sample of the
+    same workload: the first attempts of the same solve, sized to ~`seconds`."""
+    import numpy as np
+    import oracle
+
+    n = w["n"]
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+    kw = dict(A=w["A"], param=w["param"], gain=w["gain"])
+    t0 = time.perf_counter()
+    _, st, _ = oracle.bs32_solve(w["kind"], n, w["y0"], 0.0, w["t1"], w["rtol"], w["atol"], i_max=2, **kw)
+    dt = time.perf_counter() - t0
+    per_fev = dt / max(1, st["n_fev"])
+    attempts = max(2, int(seconds / per_fev / 3.0))
+    t0 = time.perf_counter()
+    _, st, _ = oracle.bs32_solve(w["kind"], n, w["y0"], 0.0, w["t1"], w["rtol"], w["atol"], i_max=attempts, **kw)
+    dt = time.perf_counter() - t0
+    pairs = st["n_fev"] * float(n) * n
+    return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": min(threads, cores), "kind": "oracle",
+            "sample": f"first {st['n_accept'] + st['n_reject']} attempts ({st['n_fev']} RHS evaluations, "
+                      f"t reached {st['t_reached']:.3g} of {w['t1']:g}) of the same solve, {dt:.1f} s",
+            "seconds": dt}
+
+
+if __name__ == "__main__":
+    main()

@@ -45,6 +45,7 @@ typedef enum {
   BS32_TIMEOUT = 4,       /* wall time over the limit (Sec. 2.2) */
   BS32_TOO_SLOW = 5,      /* wall time over the slow limit with < 10% of [t0,t1] done (Sec. 2.2) */
   BS32_NONFINITE = 6,     /* the error estimate is NaN or infinite */
+  BS32_RANGE = 7,         /* a vector operand left the range of the reduced storage format */
   BS32_EINVAL = -1,       /* invalid argument */
   BS32_ENOMEM = -2,       /* device allocation failed */
   BS32_EDEVICE = -3,      /* HIP runtime error */
@@ -144,6 +145,20 @@ bs32_status bs32_stats(const bs32_ctx* ctx, bs32_stats_t* out);
    (agent-major, d*N values).  For kernel tests and roofline timing: `repeat` > 1
    evaluates it that many times back to back and returns the last. */
 bs32_status bs32_rhs(bs32_ctx* ctx, const double* y, int precision_mode, int repeat, double* f_out);
+
+/* Time the N^2 contraction kernel of one stage evaluation (the hot kernel of
+   eq. (Stage-ODE23)) in a precision mode, at the launch configuration bs32_solve
+   uses: `repeat` back-to-back launches between two HIP events on the context's
+   stream; *avg_ms receives the mean duration of one launch.  Overwrites the
+   context's stage buffers (call between solves). */
+bs32_status bs32_time_contraction(bs32_ctx* ctx, int precision_mode, int repeat, double* avg_ms);
+
+/* Copy the coupling matrix as stored for a precision mode (packing it first if
+   needed): N rows of N elements of the storage format (8, 4, 2, 2, 1 bytes for
+   FP64, FP32, BF16, FP16, e4m3), row-major without padding, into the host buffer
+   dst of `bytes` bytes; *scale receives the per-tensor power-of-two scale s
+   (A ~= s * stored).  For inspection and tests of the quantizer. */
+bs32_status bs32_get_packed_coupling(bs32_ctx* ctx, int precision_mode, void* dst, size_t bytes, double* scale);
 
 /* Trace records of the last solve, oldest first; *n_records receives the count copied. */
 bs32_status bs32_get_trace(bs32_ctx* ctx, bs32_trace_rec* buf, size_t cap, size_t* n_records);

@@ -294,7 +294,7 @@ static void split_defaults(int fmt, int* sfmt, int* terms, int* shift) {
     case ORC_FMT_F32: *sfmt = ORC_FMT_F32; *terms = 2; *shift = 24; break;
     case ORC_FMT_BF16: *sfmt = ORC_FMT_BF16; *terms = 2; *shift = 8; break;
     case ORC_FMT_F16: *sfmt = ORC_FMT_F16; *terms = 2; *shift = 11; break;
-    case ORC_FMT_E4M3: *sfmt = ORC_FMT_F32; *terms = 2; *shift = 24; break;
+    case ORC_FMT_E4M3: *sfmt = ORC_FMT_E4M3; *terms = 3; *shift = 4; break;
     default: *sfmt = ORC_FMT_F64; *terms = 1; *shift = 0; break;
   }
 }

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbs32.so")
 
 # bs32_status
-OK, MAX_STEPS, MAX_REJECTS, H_TOO_SMALL, TIMEOUT, TOO_SLOW, NONFINITE = 0, 1, 2, 3, 4, 5, 6
+OK, MAX_STEPS, MAX_REJECTS, H_TOO_SMALL, TIMEOUT, TOO_SLOW, NONFINITE, RANGE = 0, 1, 2, 3, 4, 5, 6, 7
 EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSUPPORTED = -1, -2, -3, -4, -5
 # bs32_system_kind
 OSC2, LCO_PAPER, KURAMOTO, GOODWIN3 = 1, 2, 3, 4
@@ -78,6 +78,8 @@ _SIGS = {
     "bs32_stats": ([C.c_void_p, C.c_void_p], C.c_int),
     "bs32_rhs": ([C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p], C.c_int),
     "bs32_get_trace": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "bs32_time_contraction": ([C.c_void_p, C.c_int, C.c_int, C.c_void_p], C.c_int),
+    "bs32_get_packed_coupling": ([C.c_void_p, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "bs32_last_error": ([C.c_void_p], C.c_char_p),
     "bs32_destroy": ([C.c_void_p], None),
 }
@@ -224,6 +226,20 @@ class Solver:
         ob = _Buf(out, m, writable=True)
         self._check(lib().bs32_rhs(self._ctx, yb.ptr, int(mode), int(repeat), ob.ptr))
         return out
+
+    def time_contraction(self, mode=PREC_FP64, repeat=50):
+        """Mean duration (ms) of one launch of the N^2 contraction kernel (HIP events)."""
+        ms = C.c_double(0)
+        self._check(lib().bs32_time_contraction(self._ctx, int(mode), int(repeat), C.byref(ms)))
+        return ms.value
+
+    def packed_coupling(self, mode):
+        """(stored N x N matrix as raw format values, power-of-two scale) for a precision mode."""
+        dt = {0: np.float64, 1: np.float32, 2: np.uint16, 3: np.uint16, 4: np.uint8}[min(int(mode), 4)]
+        buf = np.empty((self.n, self.n), dtype=dt)
+        sc = C.c_double(0)
+        self._check(lib().bs32_get_packed_coupling(self._ctx, int(mode), buf.ctypes.data, buf.nbytes, C.byref(sc)))
+        return buf, sc.value
 
     def trace(self, cap=1 << 20):
         buf = (TraceRec * cap)()

@@ -1,11 +1,10 @@
 // bs32_capi.cpp -- C ABI and host orchestration of the gfx950 BS3(2) solver.
 //
-// A solve runs entirely from device-resident state: the control block (t, h,
-// counters, status, FSAL and solution buffer indices) lives in device memory
-// and is updated by the last workgroup of each attempt's final contraction.
-// The host only enqueues attempts in chunks (replayed from captured HIP
-// graphs), reads the control block back once per chunk, and enforces the
-// wall-clock failure conditions of Sec. 2.2.
+// A solve runs from device-resident state: the control block (t, h, counters,
+// status, FSAL and solution buffer indices) lives in device memory and only the
+// single-workgroup finalize kernel updates it.  The host enqueues attempts in
+// chunks (replayed from captured HIP graphs), reads the control block back once
+// per chunk, and enforces the wall-clock failure conditions of Sec. 2.2.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,43 +22,93 @@
 
 using namespace bs32;
 
+namespace {
+
+constexpr int kNumFmt = 5;
+
+// per-format vector-operand split (reading of the reduced-precision contraction)
+struct VecSplit {
+  int vfmt, terms, shift;
+  double vmax;
+};
+VecSplit vec_split(int fmt) {
+  switch (fmt) {
+    case F_F32: return {F_F32, 2, 24, 3.0e38};
+    case F_BF16: return {F_BF16, 2, 8, 3.0e38};
+    case F_F16: return {F_F16, 2, 11, 65504.0};
+    case F_E4M3: return {F_E4M3, 3, 4, 448.0};
+    default: return {F_F64, 1, 0, INFINITY};
+  }
+}
+double fmt_max(int fmt) { return fmt == F_E4M3 ? 448.0 : 1.0; }
+
+int mode_fmt(int mode) {
+  switch (mode) {
+    case BS32_PREC_RHS_FP32: return F_F32;
+    case BS32_PREC_RHS_BF16: return F_BF16;
+    case BS32_PREC_RHS_FP16: return F_F16;
+    case BS32_PREC_RHS_FP8_E4M3: return F_E4M3;
+    default: return F_F64;
+  }
+}
+
+// candidate tiles per format for the autotuner (all instantiated in bs32_kernels.hip)
+const std::vector<Tile>& candidates(int fmt) {
+  static const std::vector<Tile> f64 = {{1, 4, 1, 4}, {1, 1, 4, 4}, {2, 2, 2, 2}, {4, 4, 1, 1}, {2, 4, 1, 2},
+                                        {1, 2, 2, 4}, {4, 1, 4, 2}, {2, 1, 4, 2}, {1, 1, 8, 2}};
+  static const std::vector<Tile> f32 = {{1, 4, 1, 2}, {2, 2, 2, 2}, {1, 1, 4, 2}, {4, 1, 4, 1},
+                                        {2, 4, 1, 2}, {1, 1, 8, 2}, {2, 1, 4, 2}};
+  static const std::vector<Tile> mma = {{1, 1, 4, 2}, {1, 1, 8, 2}, {2, 1, 4, 2}, {1, 2, 4, 2},
+                                        {1, 1, 16, 1}, {2, 1, 8, 1}, {1, 1, 8, 4}, {2, 1, 8, 2}};
+  return fmt == F_F64 ? f64 : fmt == F_F32 ? f32 : mma;
+}
+
+struct Geom {
+  Tile t;
+  int RB, nrb, KW;
+};
+
+}  // namespace
+
 struct bs32_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::string err;
   bs32_options opt{};
+  std::string arch;
 
   // system
   bool has_sys = false;
   int kind = 0, d = 0, m = 0;
   long long n = 0, np = 0, ld = 0;
   double gain = 1.0;
-  double* A64 = nullptr;
   double* param = nullptr;
-  double* rsum64 = nullptr;
+  void* Aq[kNumFmt] = {};       // packed coupling per storage format (FP64 always present)
+  double* rsum[kNumFmt] = {};   // row sums of the stored matrix per format
+  double scale[kNumFmt] = {1, 1, 1, 1, 1};
+  bool tuned[kNumFmt] = {};
+  Tile best[kNumFmt] = {};
 
   // state buffers
-  long long st_np = 0;
-  int st_S = 0;
+  bool have_state = false;
   double* X[2] = {nullptr, nullptr};
   double* Kf[2] = {nullptr, nullptr};
   double* K2 = nullptr;
   double* K3 = nullptr;
   double* V64[2] = {nullptr, nullptr};
-  double* part = nullptr;
+  void* Vq[2] = {nullptr, nullptr};
   double* ep0 = nullptr;
   double* ep1 = nullptr;
-  unsigned* rbcnt = nullptr;
-  unsigned* gcnt = nullptr;
   double* stage_buf = nullptr;  // d*n staging for host <-> device copies
+  double* scratch = nullptr;    // small device scratch (max reductions)
   Ctl* ctl_d = nullptr;
   Ctl* ctl_h[2] = {nullptr, nullptr};  // pinned host mirrors
   TraceRec* trace_d = nullptr;
   int trace_alloc = 0;
   hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_chunk[2] = {nullptr, nullptr};
 
-  // captured attempt chunks: key = (attempts) ; invalidated when the launch set changes
+  // captured attempt chunks, keyed by the number of attempts; dropped when the launch set changes
   std::map<int, hipGraphExec_t> graphs;
   std::string graph_key;
 
@@ -78,20 +127,19 @@ bs32_status fail(bs32_ctx* c, bs32_status code, const char* fmt, ...) {
   return code;
 }
 
-#define HIPCHK(ctx, call)                                                                          \
-  do {                                                                                             \
-    hipError_t e_ = (call);                                                                        \
-    if (e_ != hipSuccess) {                                                                        \
+#define HIPCHK(ctx, call)                                                                              \
+  do {                                                                                                 \
+    hipError_t e_ = (call);                                                                            \
+    if (e_ != hipSuccess) {                                                                            \
       return fail(ctx, e_ == hipErrorOutOfMemory ? BS32_ENOMEM : BS32_EDEVICE, "%s failed: %s", #call, \
-                  hipGetErrorString(e_));                                                          \
-    }                                                                                              \
+                  hipGetErrorString(e_));                                                              \
+    }                                                                                                  \
   } while (0)
 
 bool is_device_ptr(const void* p) {
   if (!p) return false;
   hipPointerAttribute_t at;
-  hipError_t e = hipPointerGetAttributes(&at, p);
-  if (e != hipSuccess) {
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
     (void)hipGetLastError();
     return false;
   }
@@ -100,14 +148,17 @@ bool is_device_ptr(const void* p) {
 
 long long roundup(long long x, long long m) { return (x + m - 1) / m * m; }
 
+void ignore(hipError_t) {}
+
 void free_graphs(bs32_ctx* c) {
-  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+  for (auto& kv : c->graphs) ignore(hipGraphExecDestroy(kv.second));
   c->graphs.clear();
+  c->graph_key.clear();
 }
 
 template <typename T>
 void dfree(T*& p) {
-  if (p) hipFree((void*)p);
+  if (p) ignore(hipFree((void*)p));
   p = nullptr;
 }
 
@@ -117,112 +168,88 @@ void free_state(bs32_ctx* c) {
     dfree(c->X[q]);
     dfree(c->Kf[q]);
     dfree(c->V64[q]);
+    dfree(c->Vq[q]);
   }
   dfree(c->K2);
   dfree(c->K3);
-  dfree(c->part);
   dfree(c->ep0);
   dfree(c->ep1);
-  dfree(c->rbcnt);
-  dfree(c->gcnt);
   dfree(c->stage_buf);
-  c->st_np = 0;
-  c->st_S = 0;
+  dfree(c->scratch);
+  c->have_state = false;
 }
 
 void free_system(bs32_ctx* c) {
   free_state(c);
-  dfree(c->A64);
+  for (int f = 0; f < kNumFmt; ++f) {
+    dfree(c->Aq[f]);
+    dfree(c->rsum[f]);
+    c->scale[f] = 1.0;
+    c->tuned[f] = false;
+  }
   dfree(c->param);
-  dfree(c->rsum64);
   c->has_sys = false;
 }
 
-// Contraction geometry of the current system for a tile configuration.
-struct Geom {
-  Tile t;
-  int RB, nrb, S, KS;
-};
-
-Tile default_tile(const bs32_ctx* c, int fmt) {
-  (void)fmt;
-  if (c->n <= 1024) return Tile{1, 4, 4, 0};
-  return Tile{2, 4, 2, 0};
+bs32_status ensure_state(bs32_ctx* c) {
+  if (c->have_state) return BS32_OK;
+  const long long np = c->np;
+  const size_t sv = sizeof(double) * (size_t)(c->d * np);
+  auto alloc0 = [&](void** p, size_t bytes) -> hipError_t {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) e = hipMemset(*p, 0, bytes);
+    return e;
+  };
+  for (int q = 0; q < 2; ++q) {
+    HIPCHK(c, alloc0((void**)&c->X[q], sv));
+    HIPCHK(c, alloc0((void**)&c->Kf[q], sv));
+    HIPCHK(c, alloc0((void**)&c->V64[q], sizeof(double) * (size_t)(2 * c->ld)));
+    HIPCHK(c, alloc0((void**)&c->Vq[q], sizeof(float) * 6 * (size_t)c->ld));
+  }
+  HIPCHK(c, alloc0((void**)&c->K2, sv));
+  HIPCHK(c, alloc0((void**)&c->K3, sv));
+  HIPCHK(c, alloc0((void**)&c->ep0, sizeof(double) * (size_t)np));
+  HIPCHK(c, alloc0((void**)&c->ep1, sizeof(double) * (size_t)np));
+  HIPCHK(c, alloc0((void**)&c->stage_buf, sv));
+  HIPCHK(c, alloc0((void**)&c->scratch, 64));
+  c->have_state = true;
+  return BS32_OK;
 }
 
-Geom geometry(const bs32_ctx* c, int fmt, Tile t) {
+Geom geometry(const bs32_ctx* c, int fmt, const Tile& t) {
   Geom g;
   g.t = t;
   g.RB = tile_rows(fmt, t);
   g.nrb = (int)((c->np + g.RB - 1) / g.RB);
-  const int kal = tile_kalign(fmt, t);
-  int S = t.S;
-  if (S <= 0) {
-    // enough workgroups to cover 256 CUs several times, slices of >= 1024 columns
-    S = (int)std::max(1LL, std::min((long long)((2048 + g.nrb - 1) / g.nrb), c->ld / 1024));
-  }
-  long long KS = roundup((c->ld + S - 1) / S, kal);
-  S = (int)((c->ld + KS - 1) / KS);
-  g.S = S;
-  g.KS = (int)KS;
+  g.KW = (int)roundup((c->ld + t.WK - 1) / t.WK, tile_kalign(fmt));
   return g;
 }
 
-bs32_status ensure_state(bs32_ctx* c, const Geom& g) {
-  const long long np = c->np;
-  if (c->st_np == np && c->st_S >= g.S && c->ep0) return BS32_OK;
-  free_state(c);
-  const size_t sv = sizeof(double) * (size_t)(c->d * np);
-  for (int q = 0; q < 2; ++q) {
-    HIPCHK(c, hipMalloc((void**)&c->X[q], sv));
-    HIPCHK(c, hipMalloc((void**)&c->Kf[q], sv));
-    HIPCHK(c, hipMalloc((void**)&c->V64[q], sizeof(double) * (size_t)(2 * c->ld)));
-    HIPCHK(c, hipMemset(c->X[q], 0, sv));
-    HIPCHK(c, hipMemset(c->Kf[q], 0, sv));
-    HIPCHK(c, hipMemset(c->V64[q], 0, sizeof(double) * (size_t)(2 * c->ld)));
-  }
-  HIPCHK(c, hipMalloc((void**)&c->K2, sv));
-  HIPCHK(c, hipMalloc((void**)&c->K3, sv));
-  HIPCHK(c, hipMemset(c->K2, 0, sv));
-  HIPCHK(c, hipMemset(c->K3, 0, sv));
-  const int Smax = std::max(g.S, 16);
-  HIPCHK(c, hipMalloc((void**)&c->part, sizeof(double) * (size_t)Smax * (size_t)np * 2));
-  const long long maxrb = np;  // at most one row per block
-  HIPCHK(c, hipMalloc((void**)&c->ep0, sizeof(double) * (size_t)maxrb));
-  HIPCHK(c, hipMalloc((void**)&c->ep1, sizeof(double) * (size_t)maxrb));
-  HIPCHK(c, hipMalloc((void**)&c->rbcnt, sizeof(unsigned) * (size_t)maxrb));
-  HIPCHK(c, hipMemset(c->rbcnt, 0, sizeof(unsigned) * (size_t)maxrb));
-  HIPCHK(c, hipMalloc((void**)&c->gcnt, sizeof(unsigned) * 4));
-  HIPCHK(c, hipMemset(c->gcnt, 0, sizeof(unsigned) * 4));
-  HIPCHK(c, hipMalloc((void**)&c->stage_buf, sv));
-  c->st_np = np;
-  c->st_S = Smax;
-  return BS32_OK;
-}
-
-Args make_args(bs32_ctx* c, const Geom& g, int stage) {
+Args make_args(bs32_ctx* c, int fmt, const Geom& g, int stage) {
   Args a{};
-  a.A = c->A64;
-  a.rsum = c->rsum64;
+  a.A = c->Aq[fmt];
+  a.rsum = c->rsum[fmt];
   a.param = c->param;
   for (int q = 0; q < 2; ++q) {
     a.X[q] = c->X[q];
     a.Kf[q] = c->Kf[q];
     a.V64[q] = c->V64[q];
-    a.Vq[q] = nullptr;
+    a.Vq[q] = (fmt == F_F64) ? nullptr : c->Vq[q];
   }
   a.K2 = c->K2;
   a.K3 = c->K3;
-  a.part = c->part;
   a.ep0 = c->ep0;
   a.ep1 = c->ep1;
-  a.rbcnt = c->rbcnt;
-  a.gcnt = c->gcnt;
   a.ctl = c->ctl_d;
   a.trace = c->trace_d;
   a.gain = c->gain;
   a.invN = 1.0 / (double)c->n;
-  a.scale = 1.0;
+  a.scale = c->scale[fmt];
+  const VecSplit vs = vec_split(fmt);
+  a.vmax = vs.vmax;
+  a.vfmt = vs.vfmt;
+  a.vterms = vs.terms;
+  a.vshift = vs.shift;
   a.n = c->n;
   a.np = c->np;
   a.ld = c->ld;
@@ -231,18 +258,42 @@ Args make_args(bs32_ctx* c, const Geom& g, int stage) {
   a.m = c->m;
   a.stage = stage;
   a.nrb = g.nrb;
-  a.S = g.S;
-  a.KS = g.KS;
   a.RB = g.RB;
+  a.KW = g.KW;
   return a;
+}
+
+// store the matrix in a reduced format: A_stored = Q(A / s), s = 2^ceil(log2(max|A| / m))
+bs32_status ensure_packed(bs32_ctx* c, int fmt) {
+  if (c->Aq[fmt]) return BS32_OK;
+  const long long count = c->np * c->ld;
+  double* Aq = nullptr;
+  (void)Aq;
+  void* dst = nullptr;
+  HIPCHK(c, hipMalloc(&dst, fmt_bytes(fmt) * (size_t)count));
+  HIPCHK(c, launch_absmax((const double*)c->Aq[F_F64], count, c->scratch, c->stream));
+  double mx = 0.0;
+  HIPCHK(c, hipMemcpyAsync(&mx, c->scratch, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double s = 1.0;
+  if (mx > 0.0 && std::isfinite(mx)) s = std::ldexp(1.0, (int)std::ceil(std::log2(mx / fmt_max(fmt))));
+  HIPCHK(c, launch_pack_fmt((const double*)c->Aq[F_F64], dst, fmt, 1.0 / s, count, c->stream));
+  double* rs = nullptr;
+  HIPCHK(c, hipMalloc((void**)&rs, sizeof(double) * (size_t)c->np));
+  HIPCHK(c, hipMemsetAsync(rs, 0, sizeof(double) * (size_t)c->np, c->stream));
+  HIPCHK(c, launch_rowsum(dst, fmt, s, rs, c->n, c->ld, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->Aq[fmt] = dst;
+  c->rsum[fmt] = rs;
+  c->scale[fmt] = s;
+  return BS32_OK;
 }
 
 // upload an agent-major vector (host or device) into SoA buffer dst
 bs32_status upload_state(bs32_ctx* c, const double* y, double* dst) {
   const size_t bytes = sizeof(double) * (size_t)(c->d * c->n);
-  const bool dev = is_device_ptr(y);
-  HIPCHK(c, hipMemcpyAsync(c->stage_buf, y, bytes, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
-                           c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->stage_buf, y, bytes,
+                           is_device_ptr(y) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, launch_to_soa(c->stage_buf, dst, c->n, c->d, c->np, c->stream));
   return BS32_OK;
 }
@@ -250,37 +301,100 @@ bs32_status upload_state(bs32_ctx* c, const double* y, double* dst) {
 bs32_status download_state(bs32_ctx* c, const double* src, double* y) {
   const size_t bytes = sizeof(double) * (size_t)(c->d * c->n);
   HIPCHK(c, launch_from_soa(src, c->stage_buf, c->n, c->d, c->np, c->stream));
-  const bool dev = is_device_ptr(y);
-  HIPCHK(c, hipMemcpyAsync(y, c->stage_buf, bytes, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                           c->stream));
+  HIPCHK(c, hipMemcpyAsync(y, c->stage_buf, bytes,
+                           is_device_ptr(y) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return BS32_OK;
 }
 
-__attribute__((unused)) int mode_fmt(int mode) {
-  switch (mode) {
-    case BS32_PREC_RHS_FP32: return F_F32;
-    case BS32_PREC_RHS_BF16: return F_BF16;
-    case BS32_PREC_RHS_FP16: return F_F16;
-    case BS32_PREC_RHS_FP8_E4M3: return F_E4M3;
-    default: return F_F64;
-  }
+bs32_status set_ctl_scratch(bs32_ctx* c) {
+  Ctl* h = c->ctl_h[0];
+  std::memset(h, 0, sizeof(Ctl));
+  h->status = kRunning;
+  h->rtol = 1.0;
+  h->atol = 1.0;
+  h->trace_cap = 1;
+  HIPCHK(c, hipMemcpyAsync(c->ctl_d, h, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
+  return BS32_OK;
 }
 
-hipError_t enqueue_attempt(bs32_ctx* c, const Geom& g, int fmt) {
+// Autotuner: time every candidate tile of the format on this system (S2 contraction,
+// event-timed) and keep the fastest.  All candidates produce bit-identical sums.
+bs32_status autotune(bs32_ctx* c, int fmt) {
+  if (c->tuned[fmt]) return BS32_OK;
+  bs32_status s = set_ctl_scratch(c);
+  if (s != BS32_OK) return s;
+  float best_ms = 1e30f;
+  Tile best{};
+  bool found = false;
+  for (const Tile& t : candidates(fmt)) {
+    if (!tile_supported(fmt, c->m, t)) continue;
+    Geom g = geometry(c, fmt, t);
+    Args a = make_args(c, fmt, g, ST_S2);
+    HIPCHK(c, launch_prep(a, c->stream));
+    HIPCHK(c, launch_contract(a, fmt, t, c->stream));
+    HIPCHK(c, hipEventRecord(c->ev_start, c->stream));
+    for (int r = 0; r < 5; ++r) HIPCHK(c, launch_contract(a, fmt, t, c->stream));
+    HIPCHK(c, hipEventRecord(c->ev_stop, c->stream));
+    HIPCHK(c, hipEventSynchronize(c->ev_stop));
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev_start, c->ev_stop));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = t;
+      found = true;
+    }
+  }
+  if (!found) return fail(c, BS32_EUNSUPPORTED, "no contraction tile for format %d", fmt);
+  c->best[fmt] = best;
+  c->tuned[fmt] = true;
+  return BS32_OK;
+}
+
+// picks the tile: explicit option index into the candidate list, else the autotuned one
+bs32_status prepare(bs32_ctx* c, int mode, Geom* g, int* fmt) {
+  if (!c->has_sys) return fail(c, BS32_ESTATE, "no system set");
+  if (mode < 0 || mode > 7) return fail(c, BS32_EINVAL, "unknown precision mode %d", mode);
+  if (mode >= BS32_PREC_PAPER_SINGLE) return fail(c, BS32_EUNSUPPORTED, "precision mode %d not available", mode);
+  *fmt = mode_fmt(mode);
+  bs32_status s = ensure_state(c);
+  if (s != BS32_OK) return s;
+  s = ensure_packed(c, *fmt);
+  if (s != BS32_OK) return s;
+  Tile t;
+  const auto& cand = candidates(*fmt);
+  if (c->opt.tile >= 0) {
+    if (c->opt.tile >= (int)cand.size()) return fail(c, BS32_EINVAL, "tile index %d out of range", c->opt.tile);
+    t = cand[(size_t)c->opt.tile];
+  } else {
+    s = autotune(c, *fmt);
+    if (s != BS32_OK) return s;
+    t = c->best[*fmt];
+  }
+  *g = geometry(c, *fmt, t);
+  char key[128];
+  snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%p", mode, t.R, t.WR, t.WK, t.U, (void*)c->trace_d);
+  if (c->graph_key != key) {
+    free_graphs(c);
+    c->graph_key = key;
+  }
+  return BS32_OK;
+}
+
+hipError_t enqueue_attempt(bs32_ctx* c, int fmt, const Geom& g) {
   hipError_t e;
-  Args a = make_args(c, g, ST_S2);
-  if ((e = launch_prep(a, c->stream)) != hipSuccess) return e;
+  Args a = make_args(c, fmt, g, ST_S2);
   if ((e = launch_contract(a, fmt, g.t, c->stream)) != hipSuccess) return e;
   a.stage = ST_S3;
   if ((e = launch_contract(a, fmt, g.t, c->stream)) != hipSuccess) return e;
   a.stage = ST_S4;
-  return launch_contract(a, fmt, g.t, c->stream);
+  if ((e = launch_contract(a, fmt, g.t, c->stream)) != hipSuccess) return e;
+  return launch_finalize(a, c->stream);
 }
 
-bs32_status run_chunk(bs32_ctx* c, const Geom& g, int fmt, int attempts) {
+bs32_status run_chunk(bs32_ctx* c, int fmt, const Geom& g, int attempts) {
   if (!c->opt.use_graph) {
-    for (int q = 0; q < attempts; ++q) HIPCHK(c, enqueue_attempt(c, g, fmt));
+    for (int q = 0; q < attempts; ++q) HIPCHK(c, enqueue_attempt(c, fmt, g));
     return BS32_OK;
   }
   auto it = c->graphs.find(attempts);
@@ -288,13 +402,13 @@ bs32_status run_chunk(bs32_ctx* c, const Geom& g, int fmt, int attempts) {
     hipGraph_t graph;
     HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int q = 0; q < attempts && e == hipSuccess; ++q) e = enqueue_attempt(c, g, fmt);
-    hipError_t e2 = hipStreamEndCapture(c->stream, &graph);
+    for (int q = 0; q < attempts && e == hipSuccess; ++q) e = enqueue_attempt(c, fmt, g);
+    const hipError_t e2 = hipStreamEndCapture(c->stream, &graph);
     if (e != hipSuccess) return fail(c, BS32_EDEVICE, "launch during capture failed: %s", hipGetErrorString(e));
     if (e2 != hipSuccess) return fail(c, BS32_EDEVICE, "graph capture failed: %s", hipGetErrorString(e2));
     hipGraphExec_t ex;
     e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    ignore(hipGraphDestroy(graph));
     if (e != hipSuccess) return fail(c, BS32_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
     it = c->graphs.emplace(attempts, ex).first;
   }
@@ -312,16 +426,11 @@ bs32_status bs32_default_options(bs32_options* o) {
   o->i_max = 100000;
   o->time_limit_s = 5400.0;
   o->slow_limit_s = 2700.0;
-  o->h_max = 0.0;
-  o->h0 = 0.0;
   o->safety = 0.9;
   o->facmin = 0.2;
   o->facmax = 5.0;
-  o->fixed_step = 0;
   o->use_graph = 1;
-  o->trace = 0;
   o->trace_cap = 65536;
-  o->controller = 0;
   o->tile = -1;
   return BS32_OK;
 }
@@ -339,6 +448,8 @@ bs32_status bs32_create(bs32_ctx** out, int device, void* hip_stream) {
     delete c;
     return BS32_EDEVICE;
   }
+  hipDeviceProp_t pr;
+  if (hipGetDeviceProperties(&pr, device) == hipSuccess) c->arch = pr.gcnArchName;
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
   } else {
@@ -348,12 +459,12 @@ bs32_status bs32_create(bs32_ctx** out, int device, void* hip_stream) {
     }
     c->own_stream = true;
   }
-  bool ok = hipMalloc((void**)&c->ctl_d, sizeof(Ctl)) == hipSuccess &&
-            hipHostMalloc((void**)&c->ctl_h[0], sizeof(Ctl), hipHostMallocDefault) == hipSuccess &&
-            hipHostMalloc((void**)&c->ctl_h[1], sizeof(Ctl), hipHostMallocDefault) == hipSuccess &&
-            hipEventCreate(&c->ev_start) == hipSuccess && hipEventCreate(&c->ev_stop) == hipSuccess &&
-            hipEventCreateWithFlags(&c->ev_chunk[0], hipEventDisableTiming) == hipSuccess &&
-            hipEventCreateWithFlags(&c->ev_chunk[1], hipEventDisableTiming) == hipSuccess;
+  const bool ok = hipMalloc((void**)&c->ctl_d, sizeof(Ctl)) == hipSuccess &&
+                  hipHostMalloc((void**)&c->ctl_h[0], sizeof(Ctl), hipHostMallocDefault) == hipSuccess &&
+                  hipHostMalloc((void**)&c->ctl_h[1], sizeof(Ctl), hipHostMallocDefault) == hipSuccess &&
+                  hipEventCreate(&c->ev_start) == hipSuccess && hipEventCreate(&c->ev_stop) == hipSuccess &&
+                  hipEventCreateWithFlags(&c->ev_chunk[0], hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&c->ev_chunk[1], hipEventDisableTiming) == hipSuccess;
   if (!ok) {
     bs32_destroy(c);
     return BS32_ENOMEM;
@@ -366,18 +477,18 @@ bs32_status bs32_create(bs32_ctx** out, int device, void* hip_stream) {
 
 void bs32_destroy(bs32_ctx* c) {
   if (!c) return;
-  hipSetDevice(c->device);
-  if (c->stream) hipStreamSynchronize(c->stream);
+  ignore(hipSetDevice(c->device));
+  if (c->stream) ignore(hipStreamSynchronize(c->stream));
   free_system(c);
   dfree(c->ctl_d);
   dfree(c->trace_d);
   for (int q = 0; q < 2; ++q)
-    if (c->ctl_h[q]) hipHostFree(c->ctl_h[q]);
-  if (c->ev_start) hipEventDestroy(c->ev_start);
-  if (c->ev_stop) hipEventDestroy(c->ev_stop);
+    if (c->ctl_h[q]) ignore(hipHostFree(c->ctl_h[q]));
+  if (c->ev_start) ignore(hipEventDestroy(c->ev_start));
+  if (c->ev_stop) ignore(hipEventDestroy(c->ev_stop));
   for (int q = 0; q < 2; ++q)
-    if (c->ev_chunk[q]) hipEventDestroy(c->ev_chunk[q]);
-  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+    if (c->ev_chunk[q]) ignore(hipEventDestroy(c->ev_chunk[q]));
+  if (c->own_stream && c->stream) ignore(hipStreamDestroy(c->stream));
   delete c;
 }
 
@@ -390,6 +501,7 @@ bs32_status bs32_set_options(bs32_ctx* c, const bs32_options* o) {
     return fail(c, BS32_EINVAL, "controller constants out of range");
   if (o->trace && (o->trace_cap <= 0 || o->trace_cap > (1 << 26))) return fail(c, BS32_EINVAL, "bad trace_cap");
   if (o->fixed_step && !(o->h0 > 0)) return fail(c, BS32_EINVAL, "fixed_step needs h0 > 0");
+  if (o->controller != 0) return fail(c, BS32_EUNSUPPORTED, "controller %d not available", o->controller);
   c->opt = *o;
   free_graphs(c);
   return BS32_OK;
@@ -411,9 +523,10 @@ bs32_status bs32_set_system(bs32_ctx* c, const bs32_system_desc* sd) {
   c->gain = sd->gain;
   c->np = roundup(c->n, 256);
   c->ld = roundup(c->n, 256);
+  bs32_status s = ensure_state(c);
+  if (s != BS32_OK) return s;
   const size_t abytes = sizeof(double) * (size_t)c->np * (size_t)c->ld;
-  HIPCHK(c, hipMalloc((void**)&c->A64, abytes));
-  HIPCHK(c, hipMemsetAsync(c->A64, 0, abytes, c->stream));
+  HIPCHK(c, hipMalloc(&c->Aq[F_F64], abytes));
   const double* src = sd->coupling;
   double* tmp = nullptr;
   if (src && !is_device_ptr(src)) {
@@ -421,23 +534,23 @@ bs32_status bs32_set_system(bs32_ctx* c, const bs32_system_desc* sd) {
     HIPCHK(c, hipMemcpyAsync(tmp, src, sizeof(double) * (size_t)(c->n * c->n), hipMemcpyHostToDevice, c->stream));
     src = tmp;
   }
-  HIPCHK(c, launch_pack_f64(src, c->A64, c->n, c->ld, c->n, src == nullptr ? 1 : 0, c->stream));
-  HIPCHK(c, hipMalloc((void**)&c->rsum64, sizeof(double) * (size_t)c->np));
-  HIPCHK(c, hipMemsetAsync(c->rsum64, 0, sizeof(double) * (size_t)c->np, c->stream));
-  HIPCHK(c, launch_rowsum(c->A64, F_F64, 1.0, c->rsum64, c->n, c->ld, c->stream));
+  HIPCHK(c, launch_pack_f64(src, (double*)c->Aq[F_F64], c->n, c->ld, c->np, src == nullptr ? 1 : 0, c->stream));
+  HIPCHK(c, hipMalloc((void**)&c->rsum[F_F64], sizeof(double) * (size_t)c->np));
+  HIPCHK(c, hipMemsetAsync(c->rsum[F_F64], 0, sizeof(double) * (size_t)c->np, c->stream));
+  HIPCHK(c, launch_rowsum(c->Aq[F_F64], F_F64, 1.0, c->rsum[F_F64], c->n, c->ld, c->stream));
   HIPCHK(c, hipMalloc((void**)&c->param, sizeof(double) * (size_t)c->np));
+  std::vector<double> ones;
   if (sd->agent_param) {
     HIPCHK(c, hipMemcpyAsync(c->param, sd->agent_param, sizeof(double) * (size_t)c->n,
                              is_device_ptr(sd->agent_param) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                              c->stream));
   } else {
-    std::vector<double> ones((size_t)c->n, 1.0);
+    ones.assign((size_t)c->n, 1.0);
     HIPCHK(c, hipMemcpyAsync(c->param, ones.data(), sizeof(double) * (size_t)c->n, hipMemcpyHostToDevice,
                              c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  if (tmp) hipFree(tmp);
+  if (tmp) ignore(hipFree(tmp));
   c->has_sys = true;
   std::memset(&c->st, 0, sizeof(c->st));
   return BS32_OK;
@@ -449,24 +562,6 @@ bs32_status bs32_stats(const bs32_ctx* c, bs32_stats_t* out) {
   return BS32_OK;
 }
 
-static bs32_status prepare(bs32_ctx* c, int mode, Geom* g, int* fmt) {
-  if (!c->has_sys) return fail(c, BS32_ESTATE, "no system set");
-  if (mode < 0 || mode > 7) return fail(c, BS32_EINVAL, "unknown precision mode %d", mode);
-  if (mode != BS32_PREC_FP64) return fail(c, BS32_EUNSUPPORTED, "precision mode %d not built yet", mode);
-  *fmt = F_F64;
-  Tile t = default_tile(c, *fmt);
-  *g = geometry(c, *fmt, t);
-  bs32_status s = ensure_state(c, *g);
-  if (s != BS32_OK) return s;
-  const std::string key = std::to_string(mode) + "/" + std::to_string(g->t.R) + "/" + std::to_string(g->t.W) + "/" +
-                          std::to_string(g->t.U) + "/" + std::to_string(g->S);
-  if (key != c->graph_key) {
-    free_graphs(c);
-    c->graph_key = key;
-  }
-  return BS32_OK;
-}
-
 bs32_status bs32_rhs(bs32_ctx* c, const double* y, int mode, int repeat, double* f_out) {
   if (!c || !y || !f_out) return fail(c, BS32_EINVAL, "null argument");
   if (repeat < 1) return fail(c, BS32_EINVAL, "repeat must be >= 1");
@@ -475,20 +570,63 @@ bs32_status bs32_rhs(bs32_ctx* c, const double* y, int mode, int repeat, double*
   int fmt;
   bs32_status s = prepare(c, mode, &g, &fmt);
   if (s != BS32_OK) return s;
-  Ctl* h = c->ctl_h[0];
-  std::memset(h, 0, sizeof(Ctl));
-  h->status = kRunning;
-  h->rtol = 1.0;
-  h->atol = 1.0;
-  HIPCHK(c, hipMemcpyAsync(c->ctl_d, h, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
+  s = set_ctl_scratch(c);
+  if (s != BS32_OK) return s;
   s = upload_state(c, y, c->X[0]);
   if (s != BS32_OK) return s;
-  Args a = make_args(c, g, ST_RHS);
+  Args a = make_args(c, fmt, g, ST_RHS);
   for (int r = 0; r < repeat; ++r) {
     HIPCHK(c, launch_prep(a, c->stream));
     HIPCHK(c, launch_contract(a, fmt, g.t, c->stream));
   }
-  return download_state(c, c->Kf[0], f_out);
+  Ctl chk;
+  HIPCHK(c, hipMemcpyAsync(&chk, c->ctl_d, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+  s = download_state(c, c->Kf[0], f_out);
+  if (s != BS32_OK) return s;
+  if (chk.range_error) return fail(c, BS32_RANGE, "vector operand outside the storage format's range");
+  return BS32_OK;
+}
+
+bs32_status bs32_time_contraction(bs32_ctx* c, int mode, int repeat, double* avg_ms) {
+  if (!c || !avg_ms) return fail(c, BS32_EINVAL, "null argument");
+  if (repeat < 1) return fail(c, BS32_EINVAL, "repeat must be >= 1");
+  HIPCHK(c, hipSetDevice(c->device));
+  Geom g;
+  int fmt;
+  bs32_status s = prepare(c, mode, &g, &fmt);
+  if (s != BS32_OK) return s;
+  s = set_ctl_scratch(c);
+  if (s != BS32_OK) return s;
+  Args a = make_args(c, fmt, g, ST_S2);
+  HIPCHK(c, launch_prep(a, c->stream));
+  HIPCHK(c, launch_contract(a, fmt, g.t, c->stream));  // warm-up
+  HIPCHK(c, hipEventRecord(c->ev_start, c->stream));
+  for (int r = 0; r < repeat; ++r) HIPCHK(c, launch_contract(a, fmt, g.t, c->stream));
+  HIPCHK(c, hipEventRecord(c->ev_stop, c->stream));
+  HIPCHK(c, hipEventSynchronize(c->ev_stop));
+  float ms = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&ms, c->ev_start, c->ev_stop));
+  *avg_ms = (double)ms / repeat;
+  return BS32_OK;
+}
+
+bs32_status bs32_get_packed_coupling(bs32_ctx* c, int mode, void* dst, size_t bytes, double* scale) {
+  if (!c || !dst || !scale) return fail(c, BS32_EINVAL, "null argument");
+  if (!c->has_sys) return fail(c, BS32_ESTATE, "no system set");
+  if (mode < 0 || mode > BS32_PREC_RHS_FP8_E4M3) return fail(c, BS32_EINVAL, "mode %d has no packed matrix", mode);
+  HIPCHK(c, hipSetDevice(c->device));
+  const int fmt = mode_fmt(mode);
+  const size_t es = fmt_bytes(fmt);
+  if (bytes < es * (size_t)(c->n * c->n)) return fail(c, BS32_EINVAL, "buffer too small");
+  bs32_status s = ensure_state(c);
+  if (s != BS32_OK) return s;
+  s = ensure_packed(c, fmt);
+  if (s != BS32_OK) return s;
+  HIPCHK(c, hipMemcpy2DAsync(dst, es * (size_t)c->n, c->Aq[fmt], es * (size_t)c->ld, es * (size_t)c->n,
+                             (size_t)c->n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  *scale = c->scale[fmt];
+  return BS32_OK;
 }
 
 bs32_status bs32_solve(bs32_ctx* c, const double* y0, double t0, double t1, double rtol, double atol, int mode,
@@ -498,6 +636,12 @@ bs32_status bs32_solve(bs32_ctx* c, const double* y0, double t0, double t1, doub
     return fail(c, BS32_EINVAL, "need rtol > 0 and atol >= 0");
   if (!std::isfinite(t0) || !std::isfinite(t1) || !(t1 >= t0)) return fail(c, BS32_EINVAL, "need t1 >= t0");
   HIPCHK(c, hipSetDevice(c->device));
+  const bs32_options& o = c->opt;
+  if (o.trace && c->trace_alloc < o.trace_cap) {
+    dfree(c->trace_d);
+    HIPCHK(c, hipMalloc((void**)&c->trace_d, sizeof(TraceRec) * (size_t)o.trace_cap));
+    c->trace_alloc = o.trace_cap;
+  }
   Geom g;
   int fmt;
   bs32_status s = prepare(c, mode, &g, &fmt);
@@ -506,8 +650,8 @@ bs32_status bs32_solve(bs32_ctx* c, const double* y0, double t0, double t1, doub
   std::memset(&c->st, 0, sizeof(c->st));
   c->st.mode = mode;
   if (t1 == t0) {
-    const size_t bytes = sizeof(double) * (size_t)(c->d * c->n);
     if (y_out != y0) {
+      const size_t bytes = sizeof(double) * (size_t)(c->d * c->n);
       const bool di = is_device_ptr(y0), dout = is_device_ptr(y_out);
       HIPCHK(c, hipMemcpyAsync(y_out, y0, bytes,
                                di ? (dout ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost)
@@ -518,14 +662,6 @@ bs32_status bs32_solve(bs32_ctx* c, const double* y0, double t0, double t1, doub
     c->st.t_reached = t0;
     c->st.status = BS32_OK;
     return BS32_OK;
-  }
-  const bs32_options& o = c->opt;
-  // trace ring
-  if (o.trace && c->trace_alloc < o.trace_cap) {
-    dfree(c->trace_d);
-    HIPCHK(c, hipMalloc((void**)&c->trace_d, sizeof(TraceRec) * (size_t)o.trace_cap));
-    c->trace_alloc = o.trace_cap;
-    free_graphs(c);
   }
   Ctl* h = c->ctl_h[0];
   std::memset(h, 0, sizeof(Ctl));
@@ -552,47 +688,54 @@ bs32_status bs32_solve(bs32_ctx* c, const double* y0, double t0, double t1, doub
   if (s != BS32_OK) return s;
   HIPCHK(c, hipEventRecord(c->ev_start, c->stream));
   {
-    Args a = make_args(c, g, ST_INIT);
+    // first stage K1 = f(t0, y0), then the starting-step probe (a2)
+    Args a = make_args(c, fmt, g, ST_INIT);
     HIPCHK(c, launch_prep(a, c->stream));
     HIPCHK(c, launch_contract(a, fmt, g.t, c->stream));
+    HIPCHK(c, launch_finalize(a, c->stream));
     if (!(o.h0 > 0.0)) {
       a.stage = ST_H0;
-      HIPCHK(c, launch_prep(a, c->stream));
       HIPCHK(c, launch_contract(a, fmt, g.t, c->stream));
+      HIPCHK(c, launch_finalize(a, c->stream));
     }
   }
-  // attempt chunks, one chunk always in flight ahead of the one being checked
+  // attempt chunks; one chunk is always in flight ahead of the one being checked,
+  // and its kernels return at once when the solve is over
   int chunk = 2;
   int k = 0;
-  s = run_chunk(c, g, fmt, chunk);
+  s = run_chunk(c, fmt, g, chunk);
   if (s != BS32_OK) return s;
   HIPCHK(c, hipMemcpyAsync(c->ctl_h[0], c->ctl_d, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipEventRecord(c->ev_chunk[0], c->stream));
   int final_status = kRunning;
   while (true) {
-    // speculative next chunk (its kernels return at once if the solve is over)
-    s = run_chunk(c, g, fmt, chunk);
+    s = run_chunk(c, fmt, g, chunk);
     if (s != BS32_OK) return s;
     HIPCHK(c, hipMemcpyAsync(c->ctl_h[(k + 1) & 1], c->ctl_d, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipEventRecord(c->ev_chunk[(k + 1) & 1], c->stream));
     HIPCHK(c, hipEventSynchronize(c->ev_chunk[k & 1]));
     const Ctl* cur = c->ctl_h[k & 1];
     if (cur->status != kRunning) break;
+    // wall-clock failure conditions of Sec. 2.2
     const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();
     const double frac = (cur->t - t0) / (t1 - t0);
-    if (o.time_limit_s > 0 && el > o.time_limit_s) { final_status = BS32_TIMEOUT; break; }
-    if (o.slow_limit_s > 0 && el > o.slow_limit_s && frac < 0.1) { final_status = BS32_TOO_SLOW; break; }
-    // size the next chunk from the remaining attempts the current step suggests
+    if (o.time_limit_s > 0 && el > o.time_limit_s) {
+      final_status = BS32_TIMEOUT;
+      break;
+    }
+    if (o.slow_limit_s > 0 && el > o.slow_limit_s && frac < 0.1) {
+      final_status = BS32_TOO_SLOW;
+      break;
+    }
+    // size the next chunk from the attempts the current step size suggests are left
     const double est = (cur->h > 0) ? (t1 - cur->t) / cur->h : 1e9;
-    int want = (int)std::min(64.0, std::max(2.0, std::ceil(0.5 * est)));
+    const int want = (int)std::min(64.0, std::max(2.0, std::ceil(0.5 * est)));
     int p2 = 2;
     while (p2 < want) p2 <<= 1;
     chunk = std::min(64, std::max(2, std::min(p2, chunk * 2)));
     ++k;
   }
-  if (final_status != kRunning) {
-    HIPCHK(c, launch_set_status(c->ctl_d, final_status, c->stream));
-  }
+  if (final_status != kRunning) HIPCHK(c, launch_set_status(c->ctl_d, final_status, c->stream));
   HIPCHK(c, hipEventRecord(c->ev_stop, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->ctl_h[0], c->ctl_d, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -619,8 +762,7 @@ bs32_status bs32_get_trace(bs32_ctx* c, bs32_trace_rec* buf, size_t cap, size_t*
   if (!c || !n_records || (cap && !buf)) return fail(c, BS32_EINVAL, "null argument");
   *n_records = 0;
   if (!c->trace_d || !c->opt.trace) return BS32_OK;
-  const Ctl* h = c->ctl_h[0];
-  const long long total = h->trace_n;
+  const long long total = c->ctl_h[0]->trace_n;
   const long long ring = c->opt.trace_cap;
   const long long have = std::min(total, ring);
   const long long first = total - have;

@@ -11,10 +11,10 @@ constexpr double kA21 = 1.0 / 2.0;
 constexpr double kA32 = 3.0 / 4.0;
 constexpr double kB1 = 2.0 / 9.0, kB2 = 1.0 / 3.0, kB3 = 4.0 / 9.0;
 constexpr double kBt1 = 7.0 / 24.0, kBt2 = 1.0 / 4.0, kBt3 = 1.0 / 3.0, kBt4 = 1.0 / 8.0;
-constexpr double kC2 = 1.0 / 2.0, kC3 = 3.0 / 4.0;
 
 // internal solver status (public codes are bs32_status values >= 0)
 constexpr int kRunning = 100;
+constexpr int kStatusRange = 7;  // BS32_RANGE
 
 // stages of one contraction launch
 enum Stage : int { ST_INIT = 0, ST_H0 = 1, ST_S2 = 2, ST_S3 = 3, ST_S4 = 4, ST_RHS = 5 };
@@ -23,7 +23,8 @@ enum Stage : int { ST_INIT = 0, ST_H0 = 1, ST_S2 = 2, ST_S3 = 3, ST_S4 = 4, ST_R
 enum Fmt : int { F_F64 = 0, F_F32 = 1, F_BF16 = 2, F_F16 = 3, F_E4M3 = 4 };
 
 // Device-resident control block of one solve: the step-size state lives on the
-// GPU so that attempts run back to back without host round trips.
+// GPU so that attempts run back to back without host round trips.  Only the
+// single-workgroup finalize kernel writes it during a solve.
 struct Ctl {
   double t, h, ha;        // time, proposed step, step of the current attempt (clipped to t1)
   double t0, t1, rtol, atol;
@@ -41,7 +42,7 @@ struct Ctl {
   int fixed_step;
   int trace_on;
   int trace_cap;
-  int pad0;
+  int range_error;        // set by an epilogue when the vector operand leaves the format's range
   long long trace_n;      // attempts recorded so far (ring index = trace_n % cap)
 };
 
@@ -50,60 +51,59 @@ struct TraceRec {
   int accepted, proposer;
 };
 
-// Arguments of the contraction / prep kernels (passed by value).
+// Arguments of the contraction / prep / finalize kernels (passed by value).
 struct Args {
-  const void* A;          // packed coupling, rows_pad x ld, format-dependent
-  const double* rsum;     // row sums of the stored (dequantized) A, length n
-  const double* param;    // per-agent parameter (omega or b), length n
+  const void* A;          // packed coupling, rows_pad x ld, storage format
+  const double* rsum;     // row sums of the stored (dequantized) A, length np
+  const double* param;    // per-agent parameter (omega or b), length np
   double* X[2];           // SoA state ping-pong, d x np each
   double* Kf[2];          // first/last stage ping-pong (FSAL)
   double* K2;
   double* K3;
-  double* V64[2];         // FP64 vector operand ping-pong, [np][m]
-  void* Vq[2];            // split vector operand terms for reduced formats
-  double* part;           // split-K partials [S][np][m]
+  double* V64[2];         // FP64 vector operand ping-pong, [ld][m]
+  void* Vq[2];            // split vector operand terms for reduced formats, [m*T][ld]
   double* ep0;            // per-row-block partial maxima
   double* ep1;
-  unsigned* rbcnt;        // per-row-block arrival counters (split-K fixup)
-  unsigned* gcnt;         // grid arrival counter (norm reduction / controller)
   Ctl* ctl;
   TraceRec* trace;
-  double gain, invN, scale; // coupling gain, 1/N, per-tensor scale of A
+  double gain, invN, scale; // coupling gain, 1/N, per-tensor scale of A (power of two)
+  double vmax;            // largest magnitude the vector terms may hold (format range check)
   long long n, np, ld;    // agents, padded rows, leading dimension (elements)
   int kind, d, m;         // system kind, components per agent, vector columns
   int stage;
-  int nrb, S, KS;         // row blocks, k-slices, columns per slice
+  int nrb;                // row blocks (workgroups of the contraction)
   int RB;                 // rows per block
-  int vterms;             // split terms of the vector operand (reduced formats)
+  int KW;                 // columns per wave k-slice
+  int vfmt;               // format of the vector terms (F_F64 = no terms)
+  int vterms;             // split terms of the vector operand
   int vshift;             // exponent shift between consecutive terms
-  int ldv;                // leading dimension of one Vq column (elements)
 };
 
-// tile configuration of the contraction
+// Contraction tile: WR row groups x WK k-slices of waves per workgroup; each wave
+// owns R rows (VALU kernels) or R tiles of 16 rows (matrix-core kernels) and
+// keeps U loads per row in flight.
 struct Tile {
-  int R;   // rows per wave (VALU kernels) or 16-row MFMA tiles per wave
-  int W;   // waves per workgroup
-  int U;   // k-unroll
-  int S;   // split-K slices (0 = choose from N)
+  int R, WR, WK, U;
 };
 
 // host launchers (bs32_kernels.hip)
 int dim_of(int kind);
 int vcols_of(int kind);
+size_t fmt_bytes(int fmt);
+int tile_rows(int fmt, const Tile& t);
+int tile_kalign(int fmt);
+bool tile_supported(int fmt, int m, const Tile& t);
 hipError_t launch_prep(const Args& a, hipStream_t s);
+hipError_t launch_finalize(const Args& a, hipStream_t s);
 hipError_t launch_set_status(Ctl* c, int code, hipStream_t s);
 hipError_t launch_contract(const Args& a, int fmt, const Tile& t, hipStream_t s);
 hipError_t launch_to_soa(const double* src, double* dst, long long n, int d, long long np, hipStream_t s);
 hipError_t launch_from_soa(const double* src, double* dst, long long n, int d, long long np, hipStream_t s);
 hipError_t launch_pack_f64(const double* src, double* dst, long long n, long long ld, long long rows, int uniform,
                            hipStream_t s);
-hipError_t launch_pack_fmt(const double* A64, void* dst, int fmt, double inv_scale, long long n, long long ld,
-                           long long rows, hipStream_t s);
+hipError_t launch_absmax(const double* A64, long long count, double* out, hipStream_t s);
+hipError_t launch_pack_fmt(const double* A64, void* dst, int fmt, double inv_scale, long long count, hipStream_t s);
 hipError_t launch_rowsum(const void* A, int fmt, double scale, double* rsum, long long n, long long ld,
                          hipStream_t s);
-hipError_t launch_absmax(const double* A64, long long n, long long ld, double* out, hipStream_t s);
-int tile_rows(int fmt, const Tile& t);
-int tile_kalign(int fmt, const Tile& t);
-size_t fmt_bytes(int fmt);
 
 }  // namespace bs32

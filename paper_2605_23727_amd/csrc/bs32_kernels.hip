@@ -1,16 +1,17 @@
 // bs32_kernels.hip -- gfx950 kernels of the BS3(2) hot path.
 //
 // One attempt of the embedded pair (Sec. 2.2, eq. (Stage-ODE23)) is four launches:
-//   prep    : Y2 = X + h a21 K1 and the vector operand V(Y2)                      O(N)
-//   S2      : P = A V(Y2) ; K2 = F(Y2) + coupling(P) ; V(Y3), Y3 = X + h a32 K2     N^2
-//   S3      : P = A V(Y3) ; K3 ; X^{n+1} = X + h (b1 K1 + b2 K2 + b3 K3) ; V(X^{n+1})  N^2
-//   S4      : P = A V(X^{n+1}) ; K4 (FSAL: next K1) ; error h sum (b_l - bt_l) K_l ;
-//             weighted max norm (eq. (ERROR-O23)) ; last workgroup runs the controller  N^2
-// The state is component-major (SoA) on the device; the coupling matrix A is
-// row-major with a padded leading dimension; every stage combination is FP64
-// (Sec. 2.3 cast rules).  Sums over j run in a fixed order (per-lane strided
-// partial sums, xor-shuffle tree, split-K slices summed in slice order), so a
-// solve is bitwise reproducible run to run.
+//   S2       : P = A V(Y2) ; K2 = F(Y2) + coupling(P) ; Y3 = X + h a32 K2 ; V(Y3)      N^2
+//   S3       : P = A V(Y3) ; K3 ; X^{n+1} = X + h (b1 K1 + b2 K2 + b3 K3) ; V(X^{n+1})    N^2
+//   S4       : P = A V(X^{n+1}) ; K4 (FSAL: the next K1) ; error h sum (b_l - bt_l) K_l ;
+//              per-block weighted max (eq. (ERROR-O23))                                  N^2
+//   finalize : one workgroup: grid max, accept/reject, controller, failure checks,
+//              then Y2 = X + h a21 K1 and V(Y2) of the next attempt                     O(N)
+// The state is component-major (SoA) on the device, the coupling matrix A is
+// row-major with a padded leading dimension, and every stage combination is FP64
+// (Sec. 2.3 cast rules).  No workgroup ever waits for another: split-K runs across
+// the waves of one workgroup and is reduced through LDS in a fixed order, so
+// every sum has a fixed order and a solve is bitwise reproducible.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -20,15 +21,22 @@
 
 namespace bs32 {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
 int dim_of(int kind) { return kind == 1 ? 2 : kind == 2 ? 2 : kind == 3 ? 1 : kind == 4 ? 3 : 0; }
 int vcols_of(int kind) { return kind == 3 ? 2 : 1; }
 size_t fmt_bytes(int fmt) { return fmt == F_F64 ? 8 : fmt == F_F32 ? 4 : (fmt == F_BF16 || fmt == F_F16) ? 2 : 1; }
 
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
 __device__ __forceinline__ double nanmax(double a, double b) {
   if (a != a || b != b) return __builtin_nan("");
   return a > b ? a : b;
 }
-
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -40,7 +48,86 @@ __device__ __forceinline__ double wave_nanmax(double v) {
   return v;
 }
 
-// vector operand of one agent from the coupled component of its stage input
+// XCD-aware block order: workgroups are dealt to the 8 XCDs round-robin; give each
+// XCD a contiguous range of row blocks.
+__device__ __forceinline__ int block_row(const Args& a) {
+  const int bid = blockIdx.x;
+  return (a.nrb % 8 == 0) ? (bid % 8) * (a.nrb / 8) + bid / 8 : bid;
+}
+
+// ---------------------------------------------------------------------------
+// Storage formats: round to nearest, ties to even, straight from the FP64 bits
+// (no intermediate FP32 rounding).  e4m3 is the OCP e4m3fn format with
+// saturation to +-448 (the encoding gfx950's FP8 matrix instructions read).
+// p: significand bits incl. the implicit one; emin: exponent of the smallest normal.
+// ---------------------------------------------------------------------------
+struct FmtDesc {
+  int p, emin, bias, ebits;
+  bool e4m3;
+};
+__host__ __device__ constexpr FmtDesc fmt_desc(int fmt) {
+  return fmt == F_BF16 ? FmtDesc{8, -126, 127, 8, false}
+         : fmt == F_F16 ? FmtDesc{11, -14, 15, 5, false}
+                        : FmtDesc{4, -6, 7, 4, true};
+}
+
+__device__ inline uint32_t encode_rne(double x, FmtDesc f) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const int nb = 1 + f.ebits + (f.p - 1);
+  const uint32_t sign = (uint32_t)(u >> 63) << (nb - 1);
+  const unsigned long long a = u & 0x7fffffffffffffffULL;
+  const uint32_t emask = (1u << f.ebits) - 1u;
+  if (a > 0x7ff0000000000000ULL) return f.e4m3 ? (sign | 0x7fu) : (sign | (emask << (f.p - 1)) | (1u << (f.p - 2)));
+  if (a == 0x7ff0000000000000ULL) return f.e4m3 ? (sign | 0x7eu) : (sign | (emask << (f.p - 1)));
+  const int e = (int)(a >> 52);
+  if (e == 0) return sign;  // FP64 subnormals lie far below every target's smallest subnormal
+  const int E = e - 1023;
+  const unsigned long long mant = (a & 0xfffffffffffffULL) | (1ULL << 52);
+  int q = (E > f.emin ? E : f.emin) - (f.p - 1);  // exponent of one target quantum
+  const int sh = 52 + q - E;
+  if (sh >= 54) return sign;  // below half the smallest subnormal
+  unsigned long long r = mant >> sh;
+  const unsigned long long rem = mant & ((1ULL << sh) - 1ULL);
+  const unsigned long long half = 1ULL << (sh - 1);
+  if (rem > half || (rem == half && (r & 1ULL))) ++r;
+  if (r == 0) return sign;
+  if (r >> f.p) {
+    r >>= 1;
+    ++q;
+  }
+  uint32_t bexp, frac;
+  if (r < (1ULL << (f.p - 1))) {
+    bexp = 0;
+    frac = (uint32_t)r;
+  } else {
+    bexp = (uint32_t)(q + (f.p - 1) + f.bias);
+    frac = (uint32_t)(r - (1ULL << (f.p - 1)));
+  }
+  if (f.e4m3) {
+    if (bexp > 15u || (bexp == 15u && frac == 7u)) return sign | 0x7eu;
+  } else if (bexp >= emask) {
+    return sign | (emask << (f.p - 1));
+  }
+  return sign | (bexp << (f.p - 1)) | frac;
+}
+
+__device__ inline double decode_bits(uint32_t b, FmtDesc f) {
+  const int nb = 1 + f.ebits + (f.p - 1);
+  const bool s = (b >> (nb - 1)) & 1u;
+  const uint32_t emask = (1u << f.ebits) - 1u;
+  const uint32_t be = (b >> (f.p - 1)) & emask;
+  const uint32_t fr = b & ((1u << (f.p - 1)) - 1u);
+  double v;
+  if (f.e4m3 && be == emask && fr == 7u) v = __builtin_nan("");
+  else if (!f.e4m3 && be == emask) v = fr ? __builtin_nan("") : __builtin_inf();
+  else if (be == 0) v = ldexp((double)fr, f.emin - (f.p - 1));
+  else v = ldexp((double)(fr + (1u << (f.p - 1))), (int)be - f.bias - (f.p - 1));
+  return s ? -v : v;
+}
+
+// ---------------------------------------------------------------------------
+// vector operand of one agent and its split into reduced-format terms
+// ---------------------------------------------------------------------------
 __device__ __forceinline__ void vec_of(int kind, double y, double* v) {
   if (kind == 3) {
     v[0] = sin(y);
@@ -50,9 +137,42 @@ __device__ __forceinline__ void vec_of(int kind, double y, double* v) {
   }
 }
 
-// F_i(Y_i) + coupling of agent i from the contraction P_i (Sec. 2.1 benchmarks,
-// dense weights A_ij/N).  vself: the agent's own vector operand (sin, cos of
-// theta_i for Kuramoto).
+// Vq layout: [c * T + t][ld]; term t holds Q(r_t 2^(t shift)), r_0 = v,
+// r_{t+1} = r_t - 2^(-t shift) Q(r_t 2^(t shift)).
+__device__ void write_vq(const Args& a, void* Vq, long long i, const double* v) {
+  if (a.vfmt == F_F64 || Vq == nullptr) return;
+  for (int c = 0; c < a.m; ++c) {
+    double r = v[c];
+    if (fabs(r) > a.vmax && isfinite(r)) a.ctl->range_error = 1;
+    for (int t = 0; t < a.vterms; ++t) {
+      const long long idx = (long long)(c * a.vterms + t) * a.ld + i;
+      const double x = ldexp(r, t * a.vshift);
+      double qv;
+      if (a.vfmt == F_F32) {
+        const float f = (float)x;
+        ((float*)Vq)[idx] = f;
+        qv = (double)f;
+      } else {
+        const FmtDesc fd = fmt_desc(a.vfmt);
+        const uint32_t b = encode_rne(x, fd);
+        if (a.vfmt == F_E4M3) ((uint8_t*)Vq)[idx] = (uint8_t)b;
+        else ((uint16_t*)Vq)[idx] = (uint16_t)b;
+        qv = decode_bits(b, fd);
+      }
+      r = r - ldexp(qv, -t * a.vshift);
+    }
+  }
+}
+
+__device__ __forceinline__ void write_operand(const Args& a, int buf, long long i, double y) {
+  double v[2];
+  vec_of(a.kind, y, v);
+  for (int c = 0; c < a.m; ++c) a.V64[buf][i * a.m + c] = v[c];
+  write_vq(a, a.Vq[buf], i, v);
+}
+
+// F_i(Y_i) + coupling of agent i from the contraction P_i (Sec. 2.1 benchmarks with
+// weights A_ij/N).  vself: the agent's own vector operand (sin, cos of theta_i).
 __device__ __forceinline__ void rhs_agent(const Args& a, long long i, const double* y, const double* P,
                                           const double* vself, double* k) {
   const double p = a.param[i];
@@ -81,40 +201,7 @@ __device__ __forceinline__ void rhs_agent(const Args& a, long long i, const doub
 __device__ __forceinline__ int vin_of(int stage) { return stage == ST_S3 ? 1 : 0; }
 
 // ---------------------------------------------------------------------------
-// Quantization of the vector operand for reduced formats (written next to V64).
-// Layout: Vq[col][ldv] with col = c * vterms + term, k contiguous.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ float f32_of(double v) { return (float)v; }  // RNE (v_cvt_f32_f64)
-
-__device__ __forceinline__ void write_vq(const Args& a, void* Vq, long long i, const double* v) {
-  (void)a;
-  (void)Vq;
-  (void)i;
-  (void)v;
-}
-
-// ---------------------------------------------------------------------------
-// prep: vector operand of the first contraction of an attempt (or of the
-// initial / starting-step evaluations).
-// ---------------------------------------------------------------------------
-__global__ void k_prep(Args a) {
-  const Ctl* ctl = a.ctl;
-  if (ctl->status != kRunning) return;
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
-  const double* X = a.X[ctl->xi];
-  const double* K1 = a.Kf[ctl->ki];
-  double y = X[i];
-  if (a.stage == ST_H0) y = X[i] + ctl->h0probe * K1[i];
-  else if (a.stage == ST_S2) y = X[i] + ctl->ha * (kA21 * K1[i]);
-  double v[2];
-  vec_of(a.kind, y, v);
-  for (int c = 0; c < a.m; ++c) a.V64[0][i * a.m + c] = v[c];
-  write_vq(a, a.Vq[0], i, v);
-}
-
-// ---------------------------------------------------------------------------
-// stage epilogue of row i: returns the row's contributions to the two block maxima
+// stage epilogue of row i; returns the row's contributions to the block maxima
 // ---------------------------------------------------------------------------
 __device__ void epilogue(const Args& a, const Ctl* ctl, long long i, const double* P, double* r0, double* r1) {
   const int d = a.d;
@@ -122,8 +209,8 @@ __device__ void epilogue(const Args& a, const Ctl* ctl, long long i, const doubl
   const double* X = a.X[ctl->xi];
   const double* K1 = a.Kf[ctl->ki];
   const double* Vin = a.V64[vin_of(a.stage)];
-  double vself[2] = {Vin[i * a.m], a.m > 1 ? Vin[i * a.m + 1] : 0.0};
-  double y[3], k[3], v[2];
+  const double vself[2] = {Vin[i * a.m], a.m > 1 ? Vin[i * a.m + 1] : 0.0};
+  double y[3], k[3];
   const double ha = ctl->ha;
   *r0 = 0.0;
   *r1 = 0.0;
@@ -154,11 +241,7 @@ __device__ void epilogue(const Args& a, const Ctl* ctl, long long i, const doubl
       for (int c = 0; c < d; ++c) y[c] = X[c * np + i] + ha * (kA21 * K1[c * np + i]);
       rhs_agent(a, i, y, P, vself, k);
       for (int c = 0; c < d; ++c) a.K2[c * np + i] = k[c];
-      // stage-3 input of this agent and its vector operand
-      const double y3 = X[i] + ha * (kA32 * k[0]);
-      vec_of(a.kind, y3, v);
-      for (int c = 0; c < a.m; ++c) a.V64[1][i * a.m + c] = v[c];
-      write_vq(a, a.Vq[1], i, v);
+      write_operand(a, 1, i, X[i] + ha * (kA32 * k[0]));  // stage-3 input of this agent
       break;
     }
     case ST_S3: {
@@ -172,9 +255,7 @@ __device__ void epilogue(const Args& a, const Ctl* ctl, long long i, const doubl
         Xn[c * np + i] = xn;
         y[c] = xn;
       }
-      vec_of(a.kind, y[0], v);
-      for (int c = 0; c < a.m; ++c) a.V64[0][i * a.m + c] = v[c];
-      write_vq(a, a.Vq[0], i, v);
+      write_operand(a, 0, i, y[0]);  // the FSAL stage is evaluated at X^{n+1}
       break;
     }
     case ST_S4: {
@@ -198,7 +279,345 @@ __device__ void epilogue(const Args& a, const Ctl* ctl, long long i, const doubl
   }
 }
 
-// elementary controller (reading of the unspecified step-size correction, order-3 estimate)
+// common tail of every contraction kernel: row epilogues and the block maxima
+template <int M>
+__device__ void contract_tail(const Args& a, int rb, double (*sP)[M], int RB) {
+  __shared__ double sRed0[16], sRed1[16];
+  const Ctl* ctl = a.ctl;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const long long rowb = (long long)rb * RB;
+  double r0 = 0.0, r1 = 0.0;
+  for (int t = tid; t < RB; t += nthr) {
+    const long long i = rowb + t;
+    if (i < a.n) {
+      double q0, q1;
+      epilogue(a, ctl, i, sP[t], &q0, &q1);
+      r0 = nanmax(r0, q0);
+      r1 = nanmax(r1, q1);
+    }
+  }
+  if (a.stage == ST_S2 || a.stage == ST_S3 || a.stage == ST_RHS) return;
+  r0 = wave_nanmax(r0);
+  r1 = wave_nanmax(r1);
+  const int lane = tid & 63, wave = tid >> 6, nw = (nthr + 63) >> 6;
+  if (lane == 0) {
+    sRed0[wave] = r0;
+    sRed1[wave] = r1;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double m0 = sRed0[0], m1 = sRed1[0];
+    for (int w = 1; w < nw; ++w) {
+      m0 = nanmax(m0, sRed0[w]);
+      m1 = nanmax(m1, sRed1[w]);
+    }
+    a.ep0[rb] = m0;
+    a.ep1[rb] = m1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 contraction on the vector ALUs.  Wave (wr, wk) owns R rows and the k-slice
+// [wk KW, (wk+1) KW); lanes stride the row with 16-byte loads (2 doubles) and keep
+// U chunks of 128 columns in flight.  The WK slice sums are added in slice order.
+// ---------------------------------------------------------------------------
+template <int M, int R, int WR, int WK, int U>
+__global__ __launch_bounds__(WR* WK * 64) void k_contract_f64(Args a) {
+  constexpr int RB = R * WR;
+  __shared__ double sPart[WK][RB][M];
+  __shared__ double sP[RB][M];
+  if (a.ctl->status != kRunning) return;
+  const int rb = block_row(a);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w % WR, wk = w / WR;
+  const long long row0 = (long long)rb * RB + wr * R;
+  const double* __restrict__ Ab = (const double*)a.A + row0 * a.ld;
+  const double* __restrict__ V = a.V64[vin_of(a.stage)];
+  const long long jb = (long long)wk * a.KW;
+  const long long je = min(jb + (long long)a.KW, a.ld);
+  double acc[R][M];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < M; ++c) acc[r][c] = 0.0;
+  long long j0 = jb;
+  for (; j0 + 128 * U <= je; j0 += 128 * U) {
+    double2 av[U][R];
+    double2 vv[U][M];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long j = j0 + 128 * u + 2 * lane;
+#pragma unroll
+      for (int r = 0; r < R; ++r) av[u][r] = *(const double2*)(Ab + r * a.ld + j);
+#pragma unroll
+      for (int c = 0; c < M; ++c) vv[u][c] = *(const double2*)(V + j * M + 2 * c);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (M == 1) {
+          acc[r][0] = fma(av[u][r].x, vv[u][0].x, acc[r][0]);
+          acc[r][0] = fma(av[u][r].y, vv[u][0].y, acc[r][0]);
+        } else {
+          // vv[u][0] = (V[j][0], V[j][1]), vv[u][1] = (V[j+1][0], V[j+1][1])
+          acc[r][0] = fma(av[u][r].x, vv[u][0].x, acc[r][0]);
+          acc[r][M - 1] = fma(av[u][r].x, vv[u][0].y, acc[r][M - 1]);
+          acc[r][0] = fma(av[u][r].y, vv[u][M - 1].x, acc[r][0]);
+          acc[r][M - 1] = fma(av[u][r].y, vv[u][M - 1].y, acc[r][M - 1]);
+        }
+      }
+  }
+  for (; j0 < je; j0 += 128) {
+    const long long j = j0 + 2 * lane;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double2 x = *(const double2*)(Ab + r * a.ld + j);
+      const double2 v0 = *(const double2*)(V + j * M);
+      if (M == 1) {
+        acc[r][0] = fma(x.x, v0.x, acc[r][0]);
+        acc[r][0] = fma(x.y, v0.y, acc[r][0]);
+      } else {
+        const double2 v1 = *(const double2*)(V + j * M + 2);
+        acc[r][0] = fma(x.x, v0.x, acc[r][0]);
+        acc[r][M - 1] = fma(x.x, v0.y, acc[r][M - 1]);
+        acc[r][0] = fma(x.y, v1.x, acc[r][0]);
+        acc[r][M - 1] = fma(x.y, v1.y, acc[r][M - 1]);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      const double s = wave_sum(acc[r][c]);
+      if (lane == 0) sPart[wk][wr * R + r][c] = s;
+    }
+  __syncthreads();
+  for (int e = threadIdx.x; e < RB * M; e += blockDim.x) {
+    double s = 0.0;
+    for (int q = 0; q < WK; ++q) s += sPart[q][e / M][e % M];
+    sP[e / M][e % M] = s;
+  }
+  __syncthreads();
+  contract_tail<M>(a, rb, sP, RB);
+}
+
+// ---------------------------------------------------------------------------
+// FP32 contraction on the vector ALUs: A stored FP32, vector operand split into
+// T FP32 terms; each lane forms 4-element FP32 dot products per term and adds
+// them to FP64 accumulators (FP32 within a chunk, FP64 across chunks).
+// ---------------------------------------------------------------------------
+template <int M, int T, int R, int WR, int WK, int U>
+__global__ __launch_bounds__(WR* WK * 64) void k_contract_f32(Args a) {
+  constexpr int RB = R * WR;
+  constexpr int NC = M * T;
+  __shared__ double sPart[WK][RB][NC];
+  __shared__ double sP[RB][M];
+  if (a.ctl->status != kRunning) return;
+  const int rb = block_row(a);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w % WR, wk = w / WR;
+  const long long row0 = (long long)rb * RB + wr * R;
+  const float* __restrict__ Ab = (const float*)a.A + row0 * a.ld;
+  const float* __restrict__ Vq = (const float*)a.Vq[vin_of(a.stage)];
+  const long long jb = (long long)wk * a.KW;
+  const long long je = min(jb + (long long)a.KW, a.ld);
+  double acc[R][NC];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[r][c] = 0.0;
+  long long j0 = jb;
+  for (; j0 < je; j0 += 256 * U) {
+    const int uu = (int)min((long long)U, (je - j0) / 256);
+    f32x4 av[U][R];
+    f32x4 vv[U][NC];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (u < uu) {
+        const long long j = j0 + 256 * u + 4 * lane;
+#pragma unroll
+        for (int r = 0; r < R; ++r) av[u][r] = *(const f32x4*)(Ab + r * a.ld + j);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) vv[u][c] = *(const f32x4*)(Vq + c * a.ld + j);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        float s = 0.0f;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (u < uu) {
+            s = fmaf(av[u][r].x, vv[u][c].x, s);
+            s = fmaf(av[u][r].y, vv[u][c].y, s);
+            s = fmaf(av[u][r].z, vv[u][c].z, s);
+            s = fmaf(av[u][r].w, vv[u][c].w, s);
+          }
+        }
+        acc[r][c] += (double)s;
+      }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double s = wave_sum(acc[r][c]);
+      if (lane == 0) sPart[wk][wr * R + r][c] = s;
+    }
+  __syncthreads();
+  for (int e = threadIdx.x; e < RB * M; e += blockDim.x) {
+    const int row = e / M, cc = e % M;
+    double p = 0.0;
+    for (int t = 0; t < T; ++t) {
+      double s = 0.0;
+      for (int q = 0; q < WK; ++q) s += sPart[q][row][cc * T + t];
+      p += ldexp(s, -t * a.vshift);
+    }
+    sP[row][cc] = a.scale * p;
+  }
+  __syncthreads();
+  contract_tail<M>(a, rb, sP, RB);
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-core contraction for BF16 / FP16 / FP8-e4m3 storage.
+// One 16x16 MFMA tile: A operand = 16 rows of the coupling matrix, B operand =
+// the split vector terms as columns (c * T + t < 16; the rest zero).  Lane l
+// holds row l%16 and the k-group l/16 (8 elements; 16 for FP8 feeding two MFMAs
+// with the same k-permutation on both operands).  FP32 accumulation inside the
+// matrix core for KC k-groups, then FP64 accumulation; waves split k and their
+// sums are added in slice order.
+// ---------------------------------------------------------------------------
+template <int FMT>
+__device__ __forceinline__ f32x4 mma(u32x4 av, u32x4 bv, f32x4 c) {
+  if constexpr (FMT == F_BF16) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv), c,
+                                                   0, 0, 0);
+  } else if constexpr (FMT == F_F16) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, av), __builtin_bit_cast(f16x8, bv), c, 0,
+                                                  0, 0);
+  } else {
+    const long a0 = (long)(((unsigned long long)av.y << 32) | av.x);
+    const long a1 = (long)(((unsigned long long)av.w << 32) | av.z);
+    const long b0 = (long)(((unsigned long long)bv.y << 32) | bv.x);
+    const long b1 = (long)(((unsigned long long)bv.w << 32) | bv.z);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a0, b0, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1, b1, c, 0, 0, 0);
+  }
+}
+
+template <int FMT, int M, int T, int RT, int WR, int WK, int U>
+__global__ __launch_bounds__(WR* WK * 64) void k_contract_mfma(Args a) {
+  constexpr int NC = M * T;
+  static_assert(NC <= 16, "vector terms exceed the MFMA tile width");
+  constexpr int RB = 16 * RT * WR;
+  constexpr int ES = (FMT == F_E4M3) ? 1 : 2;  // bytes per element
+  constexpr int KB = 64 / ES;                  // k elements per 16-byte lane load x 4 lane groups
+  constexpr int KC = 8;                        // k-groups kept in FP32 before an FP64 flush
+  __shared__ double sPart[WK][RB][NC];
+  __shared__ double sP[RB][M];
+  if (a.ctl->status != kRunning) return;
+  const int rb = block_row(a);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w % WR, wk = w / WR;
+  const int r16 = lane & 15, g = lane >> 4;
+  const long long row_base = (long long)rb * RB + wr * 16 * RT;
+  const long long kb = (long long)wk * a.KW;
+  const long long ke = min(kb + (long long)a.KW, a.ld);
+  const char* Ab = (const char*)a.A;
+  const char* ap[RT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) ap[t] = Ab + ((row_base + 16 * t + r16) * a.ld + kb) * ES + g * 16;
+  const bool bcol = r16 < NC;
+  const char* bp = (const char*)a.Vq[vin_of(a.stage)] + ((long long)(bcol ? r16 : 0) * a.ld + kb) * ES + g * 16;
+  f32x4 c[RT];
+  double dacc[RT][4];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) {
+    c[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < 4; ++i) dacc[t][i] = 0.0;
+  }
+  const u32x4 zero = {0u, 0u, 0u, 0u};
+  int kc = 0;
+  long long off = 0;  // byte offset from the slice start
+  const long long span = (ke > kb) ? (ke - kb) * ES : 0;
+  for (; off + 64LL * U <= span; off += 64LL * U) {
+    u32x4 av[U][RT], bv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int t = 0; t < RT; ++t) av[u][t] = *(const u32x4*)(ap[t] + off + 64 * u);
+      bv[u] = bcol ? *(const u32x4*)(bp + off + 64 * u) : zero;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int t = 0; t < RT; ++t) c[t] = mma<FMT>(av[u][t], bv[u], c[t]);
+    kc += U;
+    if (kc >= KC) {
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        for (int i = 0; i < 4; ++i) dacc[t][i] += (double)c[t][i];
+        c[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+      kc = 0;
+    }
+  }
+  for (; off < span; off += 64) {
+    u32x4 av[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) av[t] = *(const u32x4*)(ap[t] + off);
+    const u32x4 bv = bcol ? *(const u32x4*)(bp + off) : zero;
+#pragma unroll
+    for (int t = 0; t < RT; ++t) c[t] = mma<FMT>(av[t], bv, c[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+    for (int i = 0; i < 4; ++i) dacc[t][i] += (double)c[t][i];
+  (void)KB;
+  // C layout: lane l holds rows 4 (l/16) + i of column l%16
+  if (bcol) {
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+      for (int i = 0; i < 4; ++i) sPart[wk][wr * 16 * RT + 16 * t + 4 * g + i][r16] = dacc[t][i];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < RB * M; e += blockDim.x) {
+    const int row = e / M, cc = e % M;
+    double p = 0.0;
+    for (int t = 0; t < T; ++t) {
+      double s = 0.0;
+      for (int q = 0; q < WK; ++q) s += sPart[q][row][cc * T + t];
+      p += ldexp(s, -t * a.vshift);
+    }
+    sP[row][cc] = a.scale * p;
+  }
+  __syncthreads();
+  contract_tail<M>(a, rb, sP, RB);
+}
+
+// ---------------------------------------------------------------------------
+// prep: vector operand of an evaluation from the current state (used for the
+// first evaluation of a solve, for bs32_rhs and for kernel timing).
+// ---------------------------------------------------------------------------
+__global__ void k_prep(Args a) {
+  const Ctl* ctl = a.ctl;
+  if (ctl->status != kRunning) return;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const double* X = a.X[ctl->xi];
+  const double* K1 = a.Kf[ctl->ki];
+  double y = X[i];
+  if (a.stage == ST_H0) y = X[i] + ctl->h0probe * K1[i];
+  else if (a.stage == ST_S2) y = X[i] + ctl->ha * (kA21 * K1[i]);
+  write_operand(a, 0, i, y);
+}
+
+// elementary controller (reading of the unspecified step-size correction; the
+// estimate is O(h^3), so the exponent is 1/3)
 __device__ double control(const Ctl* c, double h, double E, bool accepted) {
   const double fac = (E > 0.0) ? c->safety * cbrt(c->rtol / E) : c->facmax;
   if (accepted) {
@@ -210,7 +629,7 @@ __device__ double control(const Ctl* c, double h, double E, bool accepted) {
   return h * lo;
 }
 
-// runs on one thread after the grid-wide maxima of the stage are known
+// grid maxima of the evaluation that just finished -> new control state
 __device__ void finalize(const Args& a, Ctl* c, double m0, double m1) {
   switch (a.stage) {
     case ST_INIT: {
@@ -220,9 +639,8 @@ __device__ void finalize(const Args& a, Ctl* c, double m0, double m1) {
       if (c->h0user > 0.0) {
         c->h = c->h0user;
         c->ha = fmin(c->h, c->t1 - c->t);
-      } else {
-        // Hairer-Norsett-Wanner starting step, first half (reading)
-        double h0 = (m0 < 1e-5 || m1 < 1e-5) ? 1e-6 : 0.01 * m0 / m1;
+      } else {  // Hairer-Norsett-Wanner starting step, first half (reading)
+        const double h0 = (m0 < 1e-5 || m1 < 1e-5) ? 1e-6 : 0.01 * m0 / m1;
         c->h0probe = fmin(h0, c->h_max);
       }
       break;
@@ -243,14 +661,14 @@ __device__ void finalize(const Args& a, Ctl* c, double m0, double m1) {
       c->n_fev += 3;
       c->err = E;
       bool accepted;
-      if (c->fixed_step) accepted = true;
-      else {
+      if (c->fixed_step) {
+        accepted = true;
+      } else {
         if (!isfinite(E)) {
           c->status = 6;  // BS32_NONFINITE
           c->n_reject += 1;
           if (c->trace_on) {
-            TraceRec r = {c->t, ha, E, m1, 0, 0};
-            a.trace[c->trace_n % c->trace_cap] = r;
+            a.trace[c->trace_n % c->trace_cap] = TraceRec{c->t, ha, E, m1, 0, 0};
             c->trace_n += 1;
           }
           return;
@@ -258,8 +676,7 @@ __device__ void finalize(const Args& a, Ctl* c, double m0, double m1) {
         accepted = E < c->rtol;  // accept iff the estimate is smaller than Rel (Sec. 2.2)
       }
       if (c->trace_on) {
-        TraceRec r = {c->t, ha, E, m1, accepted ? 1 : 0, 0};
-        a.trace[c->trace_n % c->trace_cap] = r;
+        a.trace[c->trace_n % c->trace_cap] = TraceRec{c->t, ha, E, m1, accepted ? 1 : 0, 0};
         c->trace_n += 1;
       }
       double hn;
@@ -293,191 +710,62 @@ __device__ void finalize(const Args& a, Ctl* c, double m0, double m1) {
   }
 }
 
-// ---------------------------------------------------------------------------
-// common tail of every contraction kernel: split-K fixup, epilogue, grid maxima
-// sP: rows of this block (RB x m) in LDS.  Returns false when this workgroup
-// has nothing more to do.
-// ---------------------------------------------------------------------------
-template <int M>
-__device__ void contract_tail(const Args& a, int rb, int ks, double (*sP)[M]) {
-  __shared__ int sLast;
-  __shared__ double sRed0[16], sRed1[16];
-  Ctl* ctl = a.ctl;
-  const int tid = threadIdx.x;
-  const int nthr = blockDim.x;
-  const long long rowb = (long long)rb * a.RB;
-  if (a.S > 1) {
-    for (int t = tid; t < a.RB * M; t += nthr)
-      a.part[((long long)ks * a.np + rowb + t / M) * M + (t % M)] = sP[t / M][t % M];
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) {
-      const unsigned old = atomicAdd(&a.rbcnt[rb], 1u);
-      sLast = (old == (unsigned)(a.S - 1));
-    }
-    __syncthreads();
-    if (!sLast) return;
-    __threadfence();
-    for (int t = tid; t < a.RB * M; t += nthr) {
-      double s = 0.0;
-      for (int q = 0; q < a.S; ++q) s += a.part[((long long)q * a.np + rowb + t / M) * M + (t % M)];
-      sP[t / M][t % M] = s;
-    }
-    if (tid == 0) a.rbcnt[rb] = 0u;
-    __syncthreads();
-  }
-  double r0 = 0.0, r1 = 0.0;
-  for (int t = tid; t < a.RB; t += nthr) {
-    const long long i = rowb + t;
-    if (i < a.n) {
-      double q0, q1;
-      epilogue(a, ctl, i, sP[t], &q0, &q1);
-      r0 = nanmax(r0, q0);
-      r1 = nanmax(r1, q1);
-    }
-  }
-  if (a.stage == ST_S2 || a.stage == ST_S3 || a.stage == ST_RHS) return;
-  // block maxima, then grid maxima through the last-arriving workgroup
-  r0 = wave_nanmax(r0);
-  r1 = wave_nanmax(r1);
-  const int lane = tid & 63, wave = tid >> 6, nw = (nthr + 63) >> 6;
-  if (lane == 0) {
-    sRed0[wave] = r0;
-    sRed1[wave] = r1;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double m0 = sRed0[0], m1 = sRed1[0];
-    for (int w = 1; w < nw; ++w) {
-      m0 = nanmax(m0, sRed0[w]);
-      m1 = nanmax(m1, sRed1[w]);
-    }
-    a.ep0[rb] = m0;
-    a.ep1[rb] = m1;
-    __threadfence();
-    const unsigned old = atomicAdd(a.gcnt, 1u);
-    sLast = (old == (unsigned)(a.nrb - 1));
-  }
-  __syncthreads();
-  if (!sLast) return;
-  __threadfence();
+// One workgroup: reduce the block maxima of the last evaluation, update the
+// control state, and prepare the vector operand of the next evaluation.
+__global__ __launch_bounds__(1024) void k_finalize(Args a) {
+  __shared__ double sR0[16], sR1[16];
+  __shared__ int s_status, s_xi, s_ki, s_next;
+  __shared__ double s_ha, s_h0p;
+  Ctl* c = a.ctl;
+  if (c->status != kRunning) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   double m0 = 0.0, m1 = 0.0;
-  for (int q = tid; q < a.nrb; q += nthr) {
+  for (int q = tid; q < a.nrb; q += blockDim.x) {
     m0 = nanmax(m0, a.ep0[q]);
     m1 = nanmax(m1, a.ep1[q]);
   }
   m0 = wave_nanmax(m0);
   m1 = wave_nanmax(m1);
-  __syncthreads();
   if (lane == 0) {
-    sRed0[wave] = m0;
-    sRed1[wave] = m1;
+    sR0[wave] = m0;
+    sR1[wave] = m1;
   }
   __syncthreads();
   if (tid == 0) {
-    m0 = sRed0[0];
-    m1 = sRed1[0];
+    m0 = sR0[0];
+    m1 = sR1[0];
     for (int w = 1; w < nw; ++w) {
-      m0 = nanmax(m0, sRed0[w]);
-      m1 = nanmax(m1, sRed1[w]);
+      m0 = nanmax(m0, sR0[w]);
+      m1 = nanmax(m1, sR1[w]);
     }
-    *a.gcnt = 0u;
-    finalize(a, ctl, m0, m1);
+    if (c->range_error) {
+      c->status = kStatusRange;
+    } else {
+      finalize(a, c, m0, m1);
+    }
+    s_status = c->status;
+    s_xi = c->xi;
+    s_ki = c->ki;
+    s_ha = c->ha;
+    s_h0p = c->h0probe;
+    s_next = (a.stage == ST_INIT && !(c->h0user > 0.0)) ? ST_H0 : ST_S2;
   }
-}
-
-// XCD-aware block order: the hardware deals workgroups to the 8 XCDs round-robin;
-// give each XCD a contiguous range of logical blocks so that the split-K slices
-// of one row block share an L2.
-__device__ __forceinline__ void block_coords(const Args& a, int* rb, int* ks) {
-  const int total = a.nrb * a.S;
-  const int bid = blockIdx.x;
-  const int logical = (total % 8 == 0) ? (bid % 8) * (total / 8) + bid / 8 : bid;
-  *rb = logical / a.S;
-  *ks = logical % a.S;
-}
-
-// ---------------------------------------------------------------------------
-// FP64 contraction on the vector ALUs: each wave owns R rows, lanes stride the
-// row with 16-byte loads (two doubles), U chunks of 128 columns in flight.
-// ---------------------------------------------------------------------------
-template <int M, int R, int W, int U>
-__global__ __launch_bounds__(W * 64) void k_contract_f64(Args a) {
-  __shared__ double sP[W * R][M];
-  if (a.ctl->status != kRunning) return;
-  int rb, ks;
-  block_coords(a, &rb, &ks);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const long long row0 = (long long)rb * a.RB + wave * R;
-  const double* __restrict__ Ab = (const double*)a.A + row0 * a.ld;
-  const double* __restrict__ V = a.V64[vin_of(a.stage)];
-  const long long jb = (long long)ks * a.KS;
-  const long long je = min(jb + (long long)a.KS, a.ld);
-  double acc[R][M];
-#pragma unroll
-  for (int r = 0; r < R; ++r)
-#pragma unroll
-    for (int c = 0; c < M; ++c) acc[r][c] = 0.0;
-  long long j0 = jb;
-  for (; j0 + 128 * U <= je; j0 += 128 * U) {
-    double2 av[U][R];
-    double2 vv[U][M];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const long long j = j0 + 128 * u + 2 * lane;
-#pragma unroll
-      for (int r = 0; r < R; ++r) av[u][r] = *(const double2*)(Ab + r * a.ld + j);
-#pragma unroll
-      for (int c = 0; c < M; ++c) vv[u][c] = *(const double2*)(V + j * M + 2 * c);
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      // vv[u][0] = (V[j][0], V[j][1]) for M = 2, (V[j], V[j+1]) for M = 1
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if (M == 1) {
-          acc[r][0] = fma(av[u][r].x, vv[u][0].x, acc[r][0]);
-          acc[r][0] = fma(av[u][r].y, vv[u][0].y, acc[r][0]);
-        } else {
-          acc[r][0] = fma(av[u][r].x, vv[u][0].x, acc[r][0]);
-          acc[r][1] = fma(av[u][r].x, vv[u][0].y, acc[r][1]);
-          acc[r][0] = fma(av[u][r].y, vv[u][M - 1].x, acc[r][0]);
-          acc[r][M - 1] = fma(av[u][r].y, vv[u][M - 1].y, acc[r][M - 1]);
-        }
-      }
-    }
-  }
-  for (; j0 < je; j0 += 128) {
-    const long long j = j0 + 2 * lane;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const double2 x = *(const double2*)(Ab + r * a.ld + j);
-      const double2 v0 = *(const double2*)(V + j * M);
-      if (M == 1) {
-        acc[r][0] = fma(x.x, v0.x, acc[r][0]);
-        acc[r][0] = fma(x.y, v0.y, acc[r][0]);
-      } else {
-        const double2 v1 = *(const double2*)(V + j * M + 2);
-        acc[r][0] = fma(x.x, v0.x, acc[r][0]);
-        acc[r][1] = fma(x.x, v0.y, acc[r][1]);
-        acc[r][0] = fma(x.y, v1.x, acc[r][0]);
-        acc[r][M - 1] = fma(x.y, v1.y, acc[r][M - 1]);
-      }
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < R; ++r)
-#pragma unroll
-    for (int c = 0; c < M; ++c) {
-      const double s = wave_sum(acc[r][c]);
-      if (lane == 0) sP[wave * R + r][c] = s;
-    }
   __syncthreads();
-  contract_tail<M>(a, rb, ks, sP);
+  if (s_status != kRunning) return;
+  const double* X = a.X[s_xi];
+  const double* K1 = a.Kf[s_ki];
+  for (long long i = tid; i < a.n; i += blockDim.x) {
+    const double y = (s_next == ST_H0) ? X[i] + s_h0p * K1[i] : X[i] + s_ha * (kA21 * K1[i]);
+    write_operand(a, 0, i, y);
+  }
+}
+
+__global__ void k_set_status(Ctl* c, int code) {
+  if (threadIdx.x == 0 && c->status == kRunning) c->status = code;
 }
 
 // ---------------------------------------------------------------------------
-// layout conversions and packing
+// layout conversions and packing of the coupling matrix
 // ---------------------------------------------------------------------------
 __global__ void k_to_soa(const double* __restrict__ src, double* __restrict__ dst, long long n, int d, long long np) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -502,25 +790,52 @@ __global__ void k_pack_f64(const double* __restrict__ src, double* __restrict__ 
     dst[e] = v;
   }
 }
-// row sums of the stored matrix, FP64, fixed order (one workgroup per row)
-__global__ void k_rowsum_f64(const double* __restrict__ A, double* __restrict__ rsum, long long n, long long ld) {
+// max |A| over the packed matrix; out (zero-initialized) receives the bits of the
+// non-negative maximum, whose integer order equals the floating-point order
+__global__ void k_absmax(const double* __restrict__ A, long long count, unsigned long long* out) {
+  double m = 0.0;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (long long)gridDim.x * blockDim.x)
+    m = nanmax(m, fabs(A[e]));
+  m = wave_nanmax(m);
+  if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+}
+__global__ void k_pack_fmt(const double* __restrict__ A, void* __restrict__ dst, int fmt, double inv_scale,
+                           long long count) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (long long)gridDim.x * blockDim.x) {
+    const double x = A[e] * inv_scale;  // power-of-two scale: exact
+    if (fmt == F_F32) ((float*)dst)[e] = (float)x;
+    else if (fmt == F_E4M3) ((uint8_t*)dst)[e] = (uint8_t)encode_rne(x, fmt_desc(fmt));
+    else ((uint16_t*)dst)[e] = (uint16_t)encode_rne(x, fmt_desc(fmt));
+  }
+}
+__device__ __forceinline__ double stored_value(const void* A, int fmt, long long e) {
+  switch (fmt) {
+    case F_F64: return ((const double*)A)[e];
+    case F_F32: return (double)((const float*)A)[e];
+    case F_E4M3: return decode_bits(((const uint8_t*)A)[e], fmt_desc(fmt));
+    default: return decode_bits(((const uint16_t*)A)[e], fmt_desc(fmt));
+  }
+}
+// row sums of the stored matrix in FP64 (fixed order; one workgroup per row)
+__global__ void k_rowsum(const void* __restrict__ A, int fmt, double scale, double* __restrict__ rsum, long long n,
+                         long long ld) {
   __shared__ double red[4];
   const long long r = blockIdx.x;
   double s = 0.0;
-  for (long long j = threadIdx.x; j < n; j += blockDim.x) s += A[r * ld + j];
+  for (long long j = threadIdx.x; j < n; j += blockDim.x) s += scale * stored_value(A, fmt, r * ld + j);
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
-    rsum[r] = t;
-  }
+  if (threadIdx.x == 0) rsum[r] = red[0] + red[1] + red[2] + red[3];
 }
 
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
+static unsigned grid_for(long long count) { return (unsigned)std::min<long long>((count + 255) / 256, 65536); }
+
 hipError_t launch_to_soa(const double* src, double* dst, long long n, int d, long long np, hipStream_t s) {
   k_to_soa<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, dst, n, d, np);
   return hipGetLastError();
@@ -531,53 +846,97 @@ hipError_t launch_from_soa(const double* src, double* dst, long long n, int d, l
 }
 hipError_t launch_pack_f64(const double* src, double* dst, long long n, long long ld, long long rows, int uniform,
                            hipStream_t s) {
-  const long long blocks = std::min<long long>((rows * ld + 255) / 256, 65536);
-  k_pack_f64<<<(unsigned)blocks, 256, 0, s>>>(src, dst, n, ld, rows, uniform);
+  k_pack_f64<<<grid_for(rows * ld), 256, 0, s>>>(src, dst, n, ld, rows, uniform);
+  return hipGetLastError();
+}
+hipError_t launch_absmax(const double* A64, long long count, double* out, hipStream_t s) {
+  hipError_t e = hipMemsetAsync(out, 0, sizeof(double), s);
+  if (e != hipSuccess) return e;
+  k_absmax<<<grid_for(count), 256, 0, s>>>(A64, count, (unsigned long long*)out);
+  return hipGetLastError();
+}
+hipError_t launch_pack_fmt(const double* A64, void* dst, int fmt, double inv_scale, long long count, hipStream_t s) {
+  k_pack_fmt<<<grid_for(count), 256, 0, s>>>(A64, dst, fmt, inv_scale, count);
   return hipGetLastError();
 }
 hipError_t launch_rowsum(const void* A, int fmt, double scale, double* rsum, long long n, long long ld,
                          hipStream_t s) {
-  if (fmt != F_F64) return hipErrorInvalidValue;
-  (void)scale;
-  k_rowsum_f64<<<(unsigned)n, 256, 0, s>>>((const double*)A, rsum, n, ld);
-  return hipGetLastError();
-}
-__global__ void k_set_status(Ctl* c, int code) {
-  if (threadIdx.x == 0 && c->status == kRunning) c->status = code;
-}
-hipError_t launch_set_status(Ctl* c, int code, hipStream_t s) {
-  k_set_status<<<1, 64, 0, s>>>(c, code);
+  k_rowsum<<<(unsigned)n, 256, 0, s>>>(A, fmt, scale, rsum, n, ld);
   return hipGetLastError();
 }
 hipError_t launch_prep(const Args& a, hipStream_t s) {
   k_prep<<<(unsigned)((a.n + 255) / 256), 256, 0, s>>>(a);
   return hipGetLastError();
 }
+hipError_t launch_finalize(const Args& a, hipStream_t s) {
+  k_finalize<<<1, 1024, 0, s>>>(a);
+  return hipGetLastError();
+}
+hipError_t launch_set_status(Ctl* c, int code, hipStream_t s) {
+  k_set_status<<<1, 64, 0, s>>>(c, code);
+  return hipGetLastError();
+}
 
-int tile_rows(int fmt, const Tile& t) { return fmt == F_F64 || fmt == F_F32 ? t.R * t.W : 16 * t.R * t.W; }
-int tile_kalign(int fmt, const Tile& t) { (void)t; return fmt == F_F64 ? 128 : 256; }
+int tile_rows(int fmt, const Tile& t) { return (fmt == F_F64 || fmt == F_F32) ? t.R * t.WR : 16 * t.R * t.WR; }
+int tile_kalign(int fmt) { return fmt == F_F64 ? 128 : fmt == F_F32 ? 256 : fmt == F_E4M3 ? 64 : 32; }
+
+// ---- instantiated tiles ------------------------------------------------------
+#define BS32_F64_TILES(X) X(1, 4, 1, 4) X(1, 1, 4, 4) X(2, 2, 2, 2) X(4, 4, 1, 1) X(2, 4, 1, 2) X(1, 2, 2, 4) X(4, 1, 4, 2) X(2, 1, 4, 2) X(1, 1, 8, 2)
+#define BS32_F32_TILES(X) X(1, 4, 1, 2) X(2, 2, 2, 2) X(1, 1, 4, 2) X(4, 1, 4, 1) X(2, 4, 1, 2) X(1, 1, 8, 2) X(2, 1, 4, 2)
+#define BS32_MMA_TILES(X) X(1, 1, 4, 2) X(1, 1, 8, 2) X(2, 1, 4, 2) X(1, 2, 4, 2) X(1, 1, 16, 1) X(2, 1, 8, 1) X(1, 1, 8, 4) X(2, 1, 8, 2)
 
 template <int M>
-static hipError_t launch_f64(const Args& a, const Tile& t, hipStream_t s) {
-  const unsigned grid = (unsigned)(a.nrb * a.S);
-#define BS32_F64(R_, W_, U_)                                                    \
-  if (t.R == R_ && t.W == W_ && t.U == U_) {                                    \
-    k_contract_f64<M, R_, W_, U_><<<grid, W_ * 64, 0, s>>>(a);                  \
-    return hipGetLastError();                                                   \
+static hipError_t launch_f64(const Args& a, const Tile& t, hipStream_t s, bool dry) {
+#define X(R_, WR_, WK_, U_)                                                                 \
+  if (t.R == R_ && t.WR == WR_ && t.WK == WK_ && t.U == U_) {                               \
+    if (!dry) k_contract_f64<M, R_, WR_, WK_, U_><<<(unsigned)a.nrb, WR_ * WK_ * 64, 0, s>>>(a); \
+    return dry ? hipSuccess : hipGetLastError();                                            \
   }
-  BS32_F64(1, 4, 4)
-  BS32_F64(2, 4, 2)
-  BS32_F64(2, 4, 4)
-  BS32_F64(4, 4, 2)
-  BS32_F64(4, 4, 1)
-  BS32_F64(2, 8, 2)
-#undef BS32_F64
+  BS32_F64_TILES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+template <int M>
+static hipError_t launch_f32(const Args& a, const Tile& t, hipStream_t s, bool dry) {
+#define X(R_, WR_, WK_, U_)                                                                    \
+  if (t.R == R_ && t.WR == WR_ && t.WK == WK_ && t.U == U_) {                                  \
+    if (!dry) k_contract_f32<M, 2, R_, WR_, WK_, U_><<<(unsigned)a.nrb, WR_ * WK_ * 64, 0, s>>>(a); \
+    return dry ? hipSuccess : hipGetLastError();                                               \
+  }
+  BS32_F32_TILES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+template <int FMT, int M, int T>
+static hipError_t launch_mma(const Args& a, const Tile& t, hipStream_t s, bool dry) {
+#define X(R_, WR_, WK_, U_)                                                                              \
+  if (t.R == R_ && t.WR == WR_ && t.WK == WK_ && t.U == U_) {                                            \
+    if (!dry) k_contract_mfma<FMT, M, T, R_, WR_, WK_, U_><<<(unsigned)a.nrb, WR_ * WK_ * 64, 0, s>>>(a); \
+    return dry ? hipSuccess : hipGetLastError();                                                         \
+  }
+  BS32_MMA_TILES(X)
+#undef X
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_contract(const Args& a, int fmt, const Tile& t, hipStream_t s) {
-  if (fmt == F_F64) return a.m == 2 ? launch_f64<2>(a, t, s) : launch_f64<1>(a, t, s);
-  return hipErrorInvalidValue;
+static hipError_t dispatch(const Args& a, int fmt, const Tile& t, hipStream_t s, bool dry) {
+  const int m = a.m;
+  switch (fmt) {
+    case F_F64: return m == 2 ? launch_f64<2>(a, t, s, dry) : launch_f64<1>(a, t, s, dry);
+    case F_F32: return m == 2 ? launch_f32<2>(a, t, s, dry) : launch_f32<1>(a, t, s, dry);
+    case F_BF16: return m == 2 ? launch_mma<F_BF16, 2, 2>(a, t, s, dry) : launch_mma<F_BF16, 1, 2>(a, t, s, dry);
+    case F_F16: return m == 2 ? launch_mma<F_F16, 2, 2>(a, t, s, dry) : launch_mma<F_F16, 1, 2>(a, t, s, dry);
+    case F_E4M3: return m == 2 ? launch_mma<F_E4M3, 2, 3>(a, t, s, dry) : launch_mma<F_E4M3, 1, 3>(a, t, s, dry);
+    default: return hipErrorInvalidValue;
+  }
 }
+
+bool tile_supported(int fmt, int m, const Tile& t) {
+  Args a{};
+  a.m = m;
+  return dispatch(a, fmt, t, nullptr, true) == hipSuccess;
+}
+
+hipError_t launch_contract(const Args& a, int fmt, const Tile& t, hipStream_t s) { return dispatch(a, fmt, t, s, false); }
 
 }  // namespace bs32
