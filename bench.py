@@ -45,7 +45,8 @@ def parse():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--rtol", type=float, default=1e-6)
     ap.add_argument("--t1", type=float, default=50.0)
-    ap.add_argument("--modes", default="0", help="comma-separated precision modes to compare with FP64")
+    ap.add_argument("--modes", default="0,1,2,3,4", help="comma-separated precision modes to compare with FP64")
+    ap.add_argument("--head", type=int, default=None, help="force the headline precision mode")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ref", action="store_true", help="skip the rtol=1e-12 reference solution")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -81,7 +82,6 @@ def main():
     del A
 
     modes = [int(m) for m in args.modes.split(",") if m != ""]
-    head = modes[-1] if modes else 0
 
     # reference solution (FP64 GPU path at rtol = atol = 1e-12; parity-checked against the oracle)
     ref = None
@@ -122,6 +122,14 @@ def main():
             kernel_ms=stats["kernel_ms"])
 
     r0 = results[0]
+    # headline: the fastest mode whose final error stays within 2x plain FP64's
+    # (FP64 itself always qualifies); --head forces one
+    if args.head is not None:
+        head = args.head
+    else:
+        ok = [m for m, r in results.items() if r["status"] == 0 and (
+            r0["final_error"] is None or r["final_error"] is None or r["final_error"] <= 2.0 * r0["final_error"])]
+        head = min(ok, key=lambda m: results[m]["time_to_t_end_s"]) if ok else 0
     rh = results[head]
     roof = dict(bound="hbm", achieved=round(rh["contraction_gbs"], 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(rh["contraction_gbs"] / HBM_PEAK_GBS, 4), traffic=None,

@@ -52,15 +52,11 @@ int mode_fmt(int mode) {
   }
 }
 
-// candidate tiles per format for the autotuner (all instantiated in bs32_kernels.hip)
-const std::vector<Tile>& candidates(int fmt) {
-  static const std::vector<Tile> f64 = {{1, 4, 1, 4}, {1, 1, 4, 4}, {2, 2, 2, 2}, {4, 4, 1, 1}, {2, 4, 1, 2},
-                                        {1, 2, 2, 4}, {4, 1, 4, 2}, {2, 1, 4, 2}, {1, 1, 8, 2}};
-  static const std::vector<Tile> f32 = {{1, 4, 1, 2}, {2, 2, 2, 2}, {1, 1, 4, 2}, {4, 1, 4, 1},
-                                        {2, 4, 1, 2}, {1, 1, 8, 2}, {2, 1, 4, 2}};
-  static const std::vector<Tile> mma = {{1, 1, 4, 2}, {1, 1, 8, 2}, {2, 1, 4, 2}, {1, 2, 4, 2},
-                                        {1, 1, 16, 1}, {2, 1, 8, 1}, {1, 1, 8, 4}, {2, 1, 8, 2}};
-  return fmt == F_F64 ? f64 : fmt == F_F32 ? f32 : mma;
+// candidate tiles per format for the autotuner (the instantiated set of bs32_kernels.hip)
+std::vector<Tile> candidates(int fmt) {
+  int cnt = 0;
+  const Tile* t = tile_candidates(fmt, &cnt);
+  return std::vector<Tile>(t, t + cnt);
 }
 
 struct Geom {
@@ -102,7 +98,9 @@ struct bs32_ctx {
   double* ep1 = nullptr;
   double* stage_buf = nullptr;  // d*n staging for host <-> device copies
   double* scratch = nullptr;    // small device scratch (max reductions)
-  Ctl* ctl_d = nullptr;
+  Ctl* ctlbuf[2] = {nullptr, nullptr};  // alternating device control blocks
+  int par = 0;                          // index of the block holding the current state
+  Ctl* ctl_d() const { return ctlbuf[par]; }
   Ctl* ctl_h[2] = {nullptr, nullptr};  // pinned host mirrors
   TraceRec* trace_d = nullptr;
   int trace_alloc = 0;
@@ -221,7 +219,7 @@ Geom geometry(const bs32_ctx* c, int fmt, const Tile& t) {
   g.t = t;
   g.RB = tile_rows(fmt, t);
   g.nrb = (int)((c->np + g.RB - 1) / g.RB);
-  g.KW = (int)roundup((c->ld + t.WK - 1) / t.WK, tile_kalign(fmt));
+  g.KW = (int)roundup((c->ld + t.WK - 1) / t.WK, tile_kalign(fmt, t));
   return g;
 }
 
@@ -240,7 +238,9 @@ Args make_args(bs32_ctx* c, int fmt, const Geom& g, int stage) {
   a.K3 = c->K3;
   a.ep0 = c->ep0;
   a.ep1 = c->ep1;
-  a.ctl = c->ctl_d;
+  a.ctl = c->ctlbuf[c->par];
+  a.ctl_out = c->ctlbuf[1 - c->par];
+  a.rflag = (unsigned*)((char*)c->scratch + 32);
   a.trace = c->trace_d;
   a.gain = c->gain;
   a.invN = 1.0 / (double)c->n;
@@ -314,7 +314,8 @@ bs32_status set_ctl_scratch(bs32_ctx* c) {
   h->rtol = 1.0;
   h->atol = 1.0;
   h->trace_cap = 1;
-  HIPCHK(c, hipMemcpyAsync(c->ctl_d, h, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->ctl_d(), h, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemsetAsync((char*)c->scratch + 32, 0, sizeof(unsigned), c->stream));
   return BS32_OK;
 }
 
@@ -362,7 +363,7 @@ bs32_status prepare(bs32_ctx* c, int mode, Geom* g, int* fmt) {
   s = ensure_packed(c, *fmt);
   if (s != BS32_OK) return s;
   Tile t;
-  const auto& cand = candidates(*fmt);
+  const std::vector<Tile> cand = candidates(*fmt);
   if (c->opt.tile >= 0) {
     if (c->opt.tile >= (int)cand.size()) return fail(c, BS32_EINVAL, "tile index %d out of range", c->opt.tile);
     t = cand[(size_t)c->opt.tile];
@@ -373,7 +374,7 @@ bs32_status prepare(bs32_ctx* c, int mode, Geom* g, int* fmt) {
   }
   *g = geometry(c, *fmt, t);
   char key[128];
-  snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%p", mode, t.R, t.WR, t.WK, t.U, (void*)c->trace_d);
+  snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%p", mode, t.R, t.WR, t.WK, t.U, t.NT, t.MM, (void*)c->trace_d);
   if (c->graph_key != key) {
     free_graphs(c);
     c->graph_key = key;
@@ -389,7 +390,9 @@ hipError_t enqueue_attempt(bs32_ctx* c, int fmt, const Geom& g) {
   if ((e = launch_contract(a, fmt, g.t, c->stream)) != hipSuccess) return e;
   a.stage = ST_S4;
   if ((e = launch_contract(a, fmt, g.t, c->stream)) != hipSuccess) return e;
-  return launch_finalize(a, c->stream);
+  e = launch_finalize(a, c->stream);
+  c->par ^= 1;  // the finalize wrote the other control block
+  return e;
 }
 
 bs32_status run_chunk(bs32_ctx* c, int fmt, const Geom& g, int attempts) {
@@ -397,7 +400,10 @@ bs32_status run_chunk(bs32_ctx* c, int fmt, const Geom& g, int attempts) {
     for (int q = 0; q < attempts; ++q) HIPCHK(c, enqueue_attempt(c, fmt, g));
     return BS32_OK;
   }
-  auto it = c->graphs.find(attempts);
+  // an even number of attempts flips the control block an even number of times, so
+  // a captured chunk is replayable whenever it starts from the same block
+  const int key = attempts * 2 + c->par;
+  auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
     hipGraph_t graph;
     HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
@@ -410,7 +416,9 @@ bs32_status run_chunk(bs32_ctx* c, int fmt, const Geom& g, int attempts) {
     e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
     ignore(hipGraphDestroy(graph));
     if (e != hipSuccess) return fail(c, BS32_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
-    it = c->graphs.emplace(attempts, ex).first;
+    it = c->graphs.emplace(key, ex).first;
+  } else {
+    c->par ^= (attempts & 1);
   }
   HIPCHK(c, hipGraphLaunch(it->second, c->stream));
   return BS32_OK;
@@ -459,7 +467,8 @@ bs32_status bs32_create(bs32_ctx** out, int device, void* hip_stream) {
     }
     c->own_stream = true;
   }
-  const bool ok = hipMalloc((void**)&c->ctl_d, sizeof(Ctl)) == hipSuccess &&
+  const bool ok = hipMalloc((void**)&c->ctlbuf[0], sizeof(Ctl)) == hipSuccess &&
+                  hipMalloc((void**)&c->ctlbuf[1], sizeof(Ctl)) == hipSuccess &&
                   hipHostMalloc((void**)&c->ctl_h[0], sizeof(Ctl), hipHostMallocDefault) == hipSuccess &&
                   hipHostMalloc((void**)&c->ctl_h[1], sizeof(Ctl), hipHostMallocDefault) == hipSuccess &&
                   hipEventCreate(&c->ev_start) == hipSuccess && hipEventCreate(&c->ev_stop) == hipSuccess &&
@@ -480,7 +489,8 @@ void bs32_destroy(bs32_ctx* c) {
   ignore(hipSetDevice(c->device));
   if (c->stream) ignore(hipStreamSynchronize(c->stream));
   free_system(c);
-  dfree(c->ctl_d);
+  dfree(c->ctlbuf[0]);
+  dfree(c->ctlbuf[1]);
   dfree(c->trace_d);
   for (int q = 0; q < 2; ++q)
     if (c->ctl_h[q]) ignore(hipHostFree(c->ctl_h[q]));
@@ -579,11 +589,11 @@ bs32_status bs32_rhs(bs32_ctx* c, const double* y, int mode, int repeat, double*
     HIPCHK(c, launch_prep(a, c->stream));
     HIPCHK(c, launch_contract(a, fmt, g.t, c->stream));
   }
-  Ctl chk;
-  HIPCHK(c, hipMemcpyAsync(&chk, c->ctl_d, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+  unsigned rflag = 0;
+  HIPCHK(c, hipMemcpyAsync(&rflag, (char*)c->scratch + 32, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
   s = download_state(c, c->Kf[0], f_out);
   if (s != BS32_OK) return s;
-  if (chk.range_error) return fail(c, BS32_RANGE, "vector operand outside the storage format's range");
+  if (rflag) return fail(c, BS32_RANGE, "vector operand outside the storage format's range");
   return BS32_OK;
 }
 
@@ -683,7 +693,9 @@ bs32_status bs32_solve(bs32_ctx* c, const double* y0, double t0, double t1, doub
   h->fixed_step = o.fixed_step;
   h->trace_on = o.trace ? 1 : 0;
   h->trace_cap = o.trace ? o.trace_cap : 1;
-  HIPCHK(c, hipMemcpyAsync(c->ctl_d, h, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
+  c->par = 0;
+  HIPCHK(c, hipMemcpyAsync(c->ctl_d(), h, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemsetAsync((char*)c->scratch + 32, 0, sizeof(unsigned), c->stream));
   s = upload_state(c, y0, c->X[0]);
   if (s != BS32_OK) return s;
   HIPCHK(c, hipEventRecord(c->ev_start, c->stream));
@@ -693,10 +705,12 @@ bs32_status bs32_solve(bs32_ctx* c, const double* y0, double t0, double t1, doub
     HIPCHK(c, launch_prep(a, c->stream));
     HIPCHK(c, launch_contract(a, fmt, g.t, c->stream));
     HIPCHK(c, launch_finalize(a, c->stream));
+    c->par ^= 1;
     if (!(o.h0 > 0.0)) {
-      a.stage = ST_H0;
+      a = make_args(c, fmt, g, ST_H0);
       HIPCHK(c, launch_contract(a, fmt, g.t, c->stream));
       HIPCHK(c, launch_finalize(a, c->stream));
+      c->par ^= 1;
     }
   }
   // attempt chunks; one chunk is always in flight ahead of the one being checked,
@@ -705,13 +719,13 @@ bs32_status bs32_solve(bs32_ctx* c, const double* y0, double t0, double t1, doub
   int k = 0;
   s = run_chunk(c, fmt, g, chunk);
   if (s != BS32_OK) return s;
-  HIPCHK(c, hipMemcpyAsync(c->ctl_h[0], c->ctl_d, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->ctl_h[0], c->ctl_d(),sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipEventRecord(c->ev_chunk[0], c->stream));
   int final_status = kRunning;
   while (true) {
     s = run_chunk(c, fmt, g, chunk);
     if (s != BS32_OK) return s;
-    HIPCHK(c, hipMemcpyAsync(c->ctl_h[(k + 1) & 1], c->ctl_d, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->ctl_h[(k + 1) & 1], c->ctl_d(),sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipEventRecord(c->ev_chunk[(k + 1) & 1], c->stream));
     HIPCHK(c, hipEventSynchronize(c->ev_chunk[k & 1]));
     const Ctl* cur = c->ctl_h[k & 1];
@@ -735,9 +749,9 @@ bs32_status bs32_solve(bs32_ctx* c, const double* y0, double t0, double t1, doub
     chunk = std::min(64, std::max(2, std::min(p2, chunk * 2)));
     ++k;
   }
-  if (final_status != kRunning) HIPCHK(c, launch_set_status(c->ctl_d, final_status, c->stream));
+  if (final_status != kRunning) HIPCHK(c, launch_set_status(c->ctl_d(),final_status, c->stream));
   HIPCHK(c, hipEventRecord(c->ev_stop, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->ctl_h[0], c->ctl_d, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->ctl_h[0], c->ctl_d(),sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   const Ctl fin = *c->ctl_h[0];
   s = download_state(c, c->X[fin.xi], y_out);

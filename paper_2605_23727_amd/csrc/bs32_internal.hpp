@@ -23,8 +23,9 @@ enum Stage : int { ST_INIT = 0, ST_H0 = 1, ST_S2 = 2, ST_S3 = 3, ST_S4 = 4, ST_R
 enum Fmt : int { F_F64 = 0, F_F32 = 1, F_BF16 = 2, F_F16 = 3, F_E4M3 = 4 };
 
 // Device-resident control block of one solve: the step-size state lives on the
-// GPU so that attempts run back to back without host round trips.  Only the
-// single-workgroup finalize kernel writes it during a solve.
+// GPU so that attempts run back to back without host round trips.  Two buffers
+// alternate: each finalize launch reads one and workgroup 0 writes the other, so
+// no launch ever reads a block that the same launch writes.
 struct Ctl {
   double t, h, ha;        // time, proposed step, step of the current attempt (clipped to t1)
   double t0, t1, rtol, atol;
@@ -42,7 +43,7 @@ struct Ctl {
   int fixed_step;
   int trace_on;
   int trace_cap;
-  int range_error;        // set by an epilogue when the vector operand leaves the format's range
+  int pad0;
   long long trace_n;      // attempts recorded so far (ring index = trace_n % cap)
 };
 
@@ -64,7 +65,9 @@ struct Args {
   void* Vq[2];            // split vector operand terms for reduced formats, [m*T][ld]
   double* ep0;            // per-row-block partial maxima
   double* ep1;
-  Ctl* ctl;
+  Ctl* ctl;               // control state read by this launch
+  Ctl* ctl_out;           // finalize: where the next control state goes (the other buffer)
+  unsigned* rflag;        // sticky flag: a vector term left the storage format's range
   TraceRec* trace;
   double gain, invN, scale; // coupling gain, 1/N, per-tensor scale of A (power of two)
   double vmax;            // largest magnitude the vector terms may hold (format range check)
@@ -83,15 +86,17 @@ struct Args {
 // owns R rows (VALU kernels) or R tiles of 16 rows (matrix-core kernels) and
 // keeps U loads per row in flight.
 struct Tile {
-  int R, WR, WK, U;
+  int R, WR, WK, U, NT;  // NT: non-temporal loads of A
+  int MM;                // 1: matrix-core kernel (rows come in 16-row tiles)
 };
+const Tile* tile_candidates(int fmt, int* count);
 
 // host launchers (bs32_kernels.hip)
 int dim_of(int kind);
 int vcols_of(int kind);
 size_t fmt_bytes(int fmt);
 int tile_rows(int fmt, const Tile& t);
-int tile_kalign(int fmt);
+int tile_kalign(int fmt, const Tile& t);
 bool tile_supported(int fmt, int m, const Tile& t);
 hipError_t launch_prep(const Args& a, hipStream_t s);
 hipError_t launch_finalize(const Args& a, hipStream_t s);

@@ -25,6 +25,15 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+// streaming load of the coupling matrix; NT: non-temporal hint (read once, keep
+// the vector operand resident in the caches instead)
+template <bool NT, typename T>
+__device__ __forceinline__ T ldA(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
 
 int dim_of(int kind) { return kind == 1 ? 2 : kind == 2 ? 2 : kind == 3 ? 1 : kind == 4 ? 3 : 0; }
 int vcols_of(int kind) { return kind == 3 ? 2 : 1; }
@@ -143,7 +152,7 @@ __device__ void write_vq(const Args& a, void* Vq, long long i, const double* v) 
   if (a.vfmt == F_F64 || Vq == nullptr) return;
   for (int c = 0; c < a.m; ++c) {
     double r = v[c];
-    if (fabs(r) > a.vmax && isfinite(r)) a.ctl->range_error = 1;
+    if (fabs(r) > a.vmax && isfinite(r)) *a.rflag = 1u;
     for (int t = 0; t < a.vterms; ++t) {
       const long long idx = (long long)(c * a.vterms + t) * a.ld + i;
       const double x = ldexp(r, t * a.vshift);
@@ -321,7 +330,7 @@ __device__ void contract_tail(const Args& a, int rb, double (*sP)[M], int RB) {
 // [wk KW, (wk+1) KW); lanes stride the row with 16-byte loads (2 doubles) and keep
 // U chunks of 128 columns in flight.  The WK slice sums are added in slice order.
 // ---------------------------------------------------------------------------
-template <int M, int R, int WR, int WK, int U>
+template <int M, int R, int WR, int WK, int U, bool NT>
 __global__ __launch_bounds__(WR* WK * 64) void k_contract_f64(Args a) {
   constexpr int RB = R * WR;
   __shared__ double sPart[WK][RB][M];
@@ -342,15 +351,15 @@ __global__ __launch_bounds__(WR* WK * 64) void k_contract_f64(Args a) {
     for (int c = 0; c < M; ++c) acc[r][c] = 0.0;
   long long j0 = jb;
   for (; j0 + 128 * U <= je; j0 += 128 * U) {
-    double2 av[U][R];
-    double2 vv[U][M];
+    f64x2 av[U][R];
+    f64x2 vv[U][M];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const long long j = j0 + 128 * u + 2 * lane;
 #pragma unroll
-      for (int r = 0; r < R; ++r) av[u][r] = *(const double2*)(Ab + r * a.ld + j);
+      for (int r = 0; r < R; ++r) av[u][r] = ldA<NT>((const f64x2*)(Ab + r * a.ld + j));
 #pragma unroll
-      for (int c = 0; c < M; ++c) vv[u][c] = *(const double2*)(V + j * M + 2 * c);
+      for (int c = 0; c < M; ++c) vv[u][c] = *(const f64x2*)(V + j * M + 2 * c);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -372,13 +381,13 @@ __global__ __launch_bounds__(WR* WK * 64) void k_contract_f64(Args a) {
     const long long j = j0 + 2 * lane;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const double2 x = *(const double2*)(Ab + r * a.ld + j);
-      const double2 v0 = *(const double2*)(V + j * M);
+      const f64x2 x = ldA<NT>((const f64x2*)(Ab + r * a.ld + j));
+      const f64x2 v0 = *(const f64x2*)(V + j * M);
       if (M == 1) {
         acc[r][0] = fma(x.x, v0.x, acc[r][0]);
         acc[r][0] = fma(x.y, v0.y, acc[r][0]);
       } else {
-        const double2 v1 = *(const double2*)(V + j * M + 2);
+        const f64x2 v1 = *(const f64x2*)(V + j * M + 2);
         acc[r][0] = fma(x.x, v0.x, acc[r][0]);
         acc[r][M - 1] = fma(x.x, v0.y, acc[r][M - 1]);
         acc[r][0] = fma(x.y, v1.x, acc[r][0]);
@@ -408,7 +417,7 @@ __global__ __launch_bounds__(WR* WK * 64) void k_contract_f64(Args a) {
 // T FP32 terms; each lane forms 4-element FP32 dot products per term and adds
 // them to FP64 accumulators (FP32 within a chunk, FP64 across chunks).
 // ---------------------------------------------------------------------------
-template <int M, int T, int R, int WR, int WK, int U>
+template <int M, int T, int R, int WR, int WK, int U, bool NT>
 __global__ __launch_bounds__(WR* WK * 64) void k_contract_f32(Args a) {
   constexpr int RB = R * WR;
   constexpr int NC = M * T;
@@ -438,7 +447,7 @@ __global__ __launch_bounds__(WR* WK * 64) void k_contract_f32(Args a) {
       if (u < uu) {
         const long long j = j0 + 256 * u + 4 * lane;
 #pragma unroll
-        for (int r = 0; r < R; ++r) av[u][r] = *(const f32x4*)(Ab + r * a.ld + j);
+        for (int r = 0; r < R; ++r) av[u][r] = ldA<NT>((const f32x4*)(Ab + r * a.ld + j));
 #pragma unroll
         for (int c = 0; c < NC; ++c) vv[u][c] = *(const f32x4*)(Vq + c * a.ld + j);
       }
@@ -499,6 +508,16 @@ __device__ __forceinline__ f32x4 mma(u32x4 av, u32x4 bv, f32x4 c) {
   } else if constexpr (FMT == F_F16) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, av), __builtin_bit_cast(f16x8, bv), c, 0,
                                                   0, 0);
+  } else if constexpr (FMT == F_F32) {
+    // four 16x16x4 steps; lane group g holds columns 4g..4g+3 of the 16-column
+    // block, step e uses column 4g+e on both operands (same k-permutation).
+    // (Cast the whole vector: a bit_cast of a single vector element compiles to
+    // element 0 with this toolchain.)
+    const f32x4 fa = __builtin_bit_cast(f32x4, av), fb = __builtin_bit_cast(f32x4, bv);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[0], fb[0], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[1], fb[1], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[2], fb[2], c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(fa[3], fb[3], c, 0, 0, 0);
   } else {
     const long a0 = (long)(((unsigned long long)av.y << 32) | av.x);
     const long a1 = (long)(((unsigned long long)av.w << 32) | av.z);
@@ -509,13 +528,13 @@ __device__ __forceinline__ f32x4 mma(u32x4 av, u32x4 bv, f32x4 c) {
   }
 }
 
-template <int FMT, int M, int T, int RT, int WR, int WK, int U>
+template <int FMT, int M, int T, int RT, int WR, int WK, int U, bool NT>
 __global__ __launch_bounds__(WR* WK * 64) void k_contract_mfma(Args a) {
   constexpr int NC = M * T;
   static_assert(NC <= 16, "vector terms exceed the MFMA tile width");
   constexpr int RB = 16 * RT * WR;
-  constexpr int ES = (FMT == F_E4M3) ? 1 : 2;  // bytes per element
-  constexpr int KB = 64 / ES;                  // k elements per 16-byte lane load x 4 lane groups
+  constexpr int ES = (FMT == F_E4M3) ? 1 : (FMT == F_F32) ? 4 : 2;  // bytes per element
+  constexpr int KB = 64 / ES;  // k elements per 16-byte lane load x 4 lane groups
   constexpr int KC = 8;                        // k-groups kept in FP32 before an FP64 flush
   __shared__ double sPart[WK][RB][NC];
   __shared__ double sP[RB][M];
@@ -549,7 +568,7 @@ __global__ __launch_bounds__(WR* WK * 64) void k_contract_mfma(Args a) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
-      for (int t = 0; t < RT; ++t) av[u][t] = *(const u32x4*)(ap[t] + off + 64 * u);
+      for (int t = 0; t < RT; ++t) av[u][t] = ldA<NT>((const u32x4*)(ap[t] + off + 64 * u));
       bv[u] = bcol ? *(const u32x4*)(bp + off + 64 * u) : zero;
     }
 #pragma unroll
@@ -569,7 +588,7 @@ __global__ __launch_bounds__(WR* WK * 64) void k_contract_mfma(Args a) {
   for (; off < span; off += 64) {
     u32x4 av[RT];
 #pragma unroll
-    for (int t = 0; t < RT; ++t) av[t] = *(const u32x4*)(ap[t] + off);
+    for (int t = 0; t < RT; ++t) av[t] = ldA<NT>((const u32x4*)(ap[t] + off));
     const u32x4 bv = bcol ? *(const u32x4*)(bp + off) : zero;
 #pragma unroll
     for (int t = 0; t < RT; ++t) c[t] = mma<FMT>(av[t], bv, c[t]);
@@ -630,7 +649,7 @@ __device__ double control(const Ctl* c, double h, double E, bool accepted) {
 }
 
 // grid maxima of the evaluation that just finished -> new control state
-__device__ void finalize(const Args& a, Ctl* c, double m0, double m1) {
+__device__ void finalize(const Args& a, Ctl* c, double m0, double m1, bool writer) {
   switch (a.stage) {
     case ST_INIT: {
       c->n_fev += 1;
@@ -668,7 +687,7 @@ __device__ void finalize(const Args& a, Ctl* c, double m0, double m1) {
           c->status = 6;  // BS32_NONFINITE
           c->n_reject += 1;
           if (c->trace_on) {
-            a.trace[c->trace_n % c->trace_cap] = TraceRec{c->t, ha, E, m1, 0, 0};
+            if (writer) a.trace[c->trace_n % c->trace_cap] = TraceRec{c->t, ha, E, m1, 0, 0};
             c->trace_n += 1;
           }
           return;
@@ -676,7 +695,7 @@ __device__ void finalize(const Args& a, Ctl* c, double m0, double m1) {
         accepted = E < c->rtol;  // accept iff the estimate is smaller than Rel (Sec. 2.2)
       }
       if (c->trace_on) {
-        a.trace[c->trace_n % c->trace_cap] = TraceRec{c->t, ha, E, m1, accepted ? 1 : 0, 0};
+        if (writer) a.trace[c->trace_n % c->trace_cap] = TraceRec{c->t, ha, E, m1, accepted ? 1 : 0, 0};
         c->trace_n += 1;
       }
       double hn;
@@ -710,20 +729,40 @@ __device__ void finalize(const Args& a, Ctl* c, double m0, double m1) {
   }
 }
 
-// One workgroup: reduce the block maxima of the last evaluation, update the
-// control state, and prepare the vector operand of the next evaluation.
-__global__ __launch_bounds__(1024) void k_finalize(Args a) {
-  __shared__ double sR0[16], sR1[16];
-  __shared__ int s_status, s_xi, s_ki, s_next;
-  __shared__ double s_ha, s_h0p;
-  Ctl* c = a.ctl;
-  if (c->status != kRunning) return;
+// Every workgroup reduces the block maxima of the last evaluation and derives the
+// same new control state from the same inputs (fixed-order reduction, so the
+// copies agree bit for bit); workgroup 0 alone stores it into the other control
+// buffer.  Then each workgroup prepares its slice of the next vector operand.
+__global__ __launch_bounds__(256) void k_finalize(Args a) {
+  __shared__ double sR0[4], sR1[4];
+  __shared__ Ctl sc;
+  __shared__ int s_next;
+  constexpr int kWords = (int)(sizeof(Ctl) / sizeof(unsigned long long));
+  static_assert(sizeof(Ctl) % sizeof(unsigned long long) == 0 && kWords <= 256, "control block layout");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  const bool writer = blockIdx.x == 0;
+  const long long i = (long long)blockIdx.x * blockDim.x + tid;
+  // issue every independent load at once: the control block, the block maxima and
+  // both candidate buffers of this agent (which one is current depends on the decision)
+  if (tid < kWords) ((unsigned long long*)&sc)[tid] = ((const unsigned long long*)a.ctl)[tid];
+  double xc[2] = {0.0, 0.0}, kc[2] = {0.0, 0.0};
+  if (i < a.n) {
+    xc[0] = a.X[0][i];
+    xc[1] = a.X[1][i];
+    kc[0] = a.Kf[0][i];
+    kc[1] = a.Kf[1][i];
+  }
   double m0 = 0.0, m1 = 0.0;
   for (int q = tid; q < a.nrb; q += blockDim.x) {
     m0 = nanmax(m0, a.ep0[q]);
     m1 = nanmax(m1, a.ep1[q]);
   }
+  __syncthreads();
+  if (sc.status != kRunning) {
+    if (writer && tid < kWords) ((unsigned long long*)a.ctl_out)[tid] = ((const unsigned long long*)&sc)[tid];
+    return;
+  }
+  Ctl* c = &sc;
   m0 = wave_nanmax(m0);
   m1 = wave_nanmax(m1);
   if (lane == 0) {
@@ -738,24 +777,16 @@ __global__ __launch_bounds__(1024) void k_finalize(Args a) {
       m0 = nanmax(m0, sR0[w]);
       m1 = nanmax(m1, sR1[w]);
     }
-    if (c->range_error) {
-      c->status = kStatusRange;
-    } else {
-      finalize(a, c, m0, m1);
-    }
-    s_status = c->status;
-    s_xi = c->xi;
-    s_ki = c->ki;
-    s_ha = c->ha;
-    s_h0p = c->h0probe;
+    if (*a.rflag) c->status = kStatusRange;
+    else finalize(a, c, m0, m1, writer);
     s_next = (a.stage == ST_INIT && !(c->h0user > 0.0)) ? ST_H0 : ST_S2;
   }
   __syncthreads();
-  if (s_status != kRunning) return;
-  const double* X = a.X[s_xi];
-  const double* K1 = a.Kf[s_ki];
-  for (long long i = tid; i < a.n; i += blockDim.x) {
-    const double y = (s_next == ST_H0) ? X[i] + s_h0p * K1[i] : X[i] + s_ha * (kA21 * K1[i]);
+  if (writer && tid < kWords) ((unsigned long long*)a.ctl_out)[tid] = ((const unsigned long long*)&sc)[tid];
+  if (sc.status != kRunning) return;
+  if (i < a.n) {
+    const double x = xc[sc.xi], k1 = kc[sc.ki];
+    const double y = (s_next == ST_H0) ? x + sc.h0probe * k1 : x + sc.ha * (kA21 * k1);
     write_operand(a, 0, i, y);
   }
 }
@@ -797,8 +828,14 @@ __global__ void k_absmax(const double* __restrict__ A, long long count, unsigned
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count;
        e += (long long)gridDim.x * blockDim.x)
     m = nanmax(m, fabs(A[e]));
+  __shared__ double red[4];
   m = wave_nanmax(m);
-  if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = nanmax(nanmax(red[0], red[1]), nanmax(red[2], red[3]));
+    atomicMax(out, (unsigned long long)__double_as_longlong(m));
+  }
 }
 __global__ void k_pack_fmt(const double* __restrict__ A, void* __restrict__ dst, int fmt, double inv_scale,
                            long long count) {
@@ -852,7 +889,7 @@ hipError_t launch_pack_f64(const double* src, double* dst, long long n, long lon
 hipError_t launch_absmax(const double* A64, long long count, double* out, hipStream_t s) {
   hipError_t e = hipMemsetAsync(out, 0, sizeof(double), s);
   if (e != hipSuccess) return e;
-  k_absmax<<<grid_for(count), 256, 0, s>>>(A64, count, (unsigned long long*)out);
+  k_absmax<<<std::min(grid_for(count), 2048u), 256, 0, s>>>(A64, count, (unsigned long long*)out);
   return hipGetLastError();
 }
 hipError_t launch_pack_fmt(const double* A64, void* dst, int fmt, double inv_scale, long long count, hipStream_t s) {
@@ -869,7 +906,7 @@ hipError_t launch_prep(const Args& a, hipStream_t s) {
   return hipGetLastError();
 }
 hipError_t launch_finalize(const Args& a, hipStream_t s) {
-  k_finalize<<<1, 1024, 0, s>>>(a);
+  k_finalize<<<(unsigned)((a.n + 255) / 256), 256, 0, s>>>(a);
   return hipGetLastError();
 }
 hipError_t launch_set_status(Ctl* c, int code, hipStream_t s) {
@@ -877,20 +914,53 @@ hipError_t launch_set_status(Ctl* c, int code, hipStream_t s) {
   return hipGetLastError();
 }
 
-int tile_rows(int fmt, const Tile& t) { return (fmt == F_F64 || fmt == F_F32) ? t.R * t.WR : 16 * t.R * t.WR; }
-int tile_kalign(int fmt) { return fmt == F_F64 ? 128 : fmt == F_F32 ? 256 : fmt == F_E4M3 ? 64 : 32; }
+int tile_rows(int fmt, const Tile& t) { return t.MM ? 16 * t.R * t.WR : t.R * t.WR; }
+// columns one wave step covers: 64 lanes x 16 bytes (VALU), 4 lane groups x 16 bytes (matrix cores)
+int tile_kalign(int fmt, const Tile& t) {
+  if (t.MM) return 64 / (int)fmt_bytes(fmt);
+  return fmt == F_F64 ? 128 : 256;
+}
 
 // ---- instantiated tiles ------------------------------------------------------
-#define BS32_F64_TILES(X) X(1, 4, 1, 4) X(1, 1, 4, 4) X(2, 2, 2, 2) X(4, 4, 1, 1) X(2, 4, 1, 2) X(1, 2, 2, 4) X(4, 1, 4, 2) X(2, 1, 4, 2) X(1, 1, 8, 2)
-#define BS32_F32_TILES(X) X(1, 4, 1, 2) X(2, 2, 2, 2) X(1, 1, 4, 2) X(4, 1, 4, 1) X(2, 4, 1, 2) X(1, 1, 8, 2) X(2, 1, 4, 2)
-#define BS32_MMA_TILES(X) X(1, 1, 4, 2) X(1, 1, 8, 2) X(2, 1, 4, 2) X(1, 2, 4, 2) X(1, 1, 16, 1) X(2, 1, 8, 1) X(1, 1, 8, 4) X(2, 1, 8, 2)
+// (R, WR, WK, U, NT): the candidate set the autotuner times, per kernel family
+#define BS32_F64_TILES(X)                                                                                   \
+  X(1, 4, 1, 4, 0) X(2, 1, 4, 2, 0) X(2, 2, 2, 2, 0) X(4, 1, 4, 2, 0) X(1, 1, 8, 2, 0) X(1, 1, 4, 8, 0)     \
+  X(2, 1, 4, 4, 0) X(1, 1, 8, 4, 0) X(2, 1, 4, 2, 1) X(4, 1, 4, 2, 1) X(1, 1, 4, 8, 1) X(2, 1, 8, 4, 0)     \
+  X(1, 1, 16, 2, 0)
+#define BS32_F32_TILES(X)                                                                                   \
+  X(1, 4, 1, 2, 0) X(1, 1, 4, 2, 0) X(2, 1, 4, 2, 0) X(1, 1, 8, 2, 0) X(1, 1, 4, 4, 0) X(2, 1, 4, 4, 0)     \
+  X(1, 1, 8, 4, 0) X(2, 1, 4, 2, 1) X(1, 1, 8, 4, 1) X(1, 1, 16, 2, 0)
+#define BS32_MMA_TILES(X)                                                                                   \
+  X(1, 1, 8, 2, 0) X(1, 1, 8, 4, 0) X(1, 1, 8, 8, 0) X(1, 1, 16, 4, 0) X(1, 1, 16, 8, 0) X(2, 1, 8, 4, 0)  \
+  X(1, 1, 4, 8, 0) X(2, 1, 4, 4, 0) X(1, 1, 8, 4, 1) X(1, 1, 16, 4, 1) X(2, 1, 8, 4, 1) X(1, 2, 8, 4, 0)
+
+#define BS32_TILE_VALU(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 0},
+#define BS32_TILE_MMA(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 1},
+static const Tile kF64Tiles[] = {BS32_F64_TILES(BS32_TILE_VALU)};
+static const Tile kF32Tiles[] = {BS32_F32_TILES(BS32_TILE_VALU) BS32_MMA_TILES(BS32_TILE_MMA)};
+static const Tile kMmaTiles[] = {BS32_MMA_TILES(BS32_TILE_MMA)};
+#undef BS32_TILE_VALU
+#undef BS32_TILE_MMA
+
+const Tile* tile_candidates(int fmt, int* count) {
+  if (fmt == F_F64) {
+    *count = (int)(sizeof(kF64Tiles) / sizeof(Tile));
+    return kF64Tiles;
+  }
+  if (fmt == F_F32) {
+    *count = (int)(sizeof(kF32Tiles) / sizeof(Tile));
+    return kF32Tiles;
+  }
+  *count = (int)(sizeof(kMmaTiles) / sizeof(Tile));
+  return kMmaTiles;
+}
 
 template <int M>
 static hipError_t launch_f64(const Args& a, const Tile& t, hipStream_t s, bool dry) {
-#define X(R_, WR_, WK_, U_)                                                                 \
-  if (t.R == R_ && t.WR == WR_ && t.WK == WK_ && t.U == U_) {                               \
-    if (!dry) k_contract_f64<M, R_, WR_, WK_, U_><<<(unsigned)a.nrb, WR_ * WK_ * 64, 0, s>>>(a); \
-    return dry ? hipSuccess : hipGetLastError();                                            \
+#define X(R_, WR_, WK_, U_, NT_)                                                                           \
+  if (t.R == R_ && t.WR == WR_ && t.WK == WK_ && t.U == U_ && t.NT == NT_) {                               \
+    if (!dry) k_contract_f64<M, R_, WR_, WK_, U_, NT_><<<(unsigned)a.nrb, WR_ * WK_ * 64, 0, s>>>(a);      \
+    return dry ? hipSuccess : hipGetLastError();                                                           \
   }
   BS32_F64_TILES(X)
 #undef X
@@ -898,10 +968,10 @@ static hipError_t launch_f64(const Args& a, const Tile& t, hipStream_t s, bool d
 }
 template <int M>
 static hipError_t launch_f32(const Args& a, const Tile& t, hipStream_t s, bool dry) {
-#define X(R_, WR_, WK_, U_)                                                                    \
-  if (t.R == R_ && t.WR == WR_ && t.WK == WK_ && t.U == U_) {                                  \
-    if (!dry) k_contract_f32<M, 2, R_, WR_, WK_, U_><<<(unsigned)a.nrb, WR_ * WK_ * 64, 0, s>>>(a); \
-    return dry ? hipSuccess : hipGetLastError();                                               \
+#define X(R_, WR_, WK_, U_, NT_)                                                                           \
+  if (t.R == R_ && t.WR == WR_ && t.WK == WK_ && t.U == U_ && t.NT == NT_) {                               \
+    if (!dry) k_contract_f32<M, 2, R_, WR_, WK_, U_, NT_><<<(unsigned)a.nrb, WR_ * WK_ * 64, 0, s>>>(a);   \
+    return dry ? hipSuccess : hipGetLastError();                                                           \
   }
   BS32_F32_TILES(X)
 #undef X
@@ -909,10 +979,10 @@ static hipError_t launch_f32(const Args& a, const Tile& t, hipStream_t s, bool d
 }
 template <int FMT, int M, int T>
 static hipError_t launch_mma(const Args& a, const Tile& t, hipStream_t s, bool dry) {
-#define X(R_, WR_, WK_, U_)                                                                              \
-  if (t.R == R_ && t.WR == WR_ && t.WK == WK_ && t.U == U_) {                                            \
-    if (!dry) k_contract_mfma<FMT, M, T, R_, WR_, WK_, U_><<<(unsigned)a.nrb, WR_ * WK_ * 64, 0, s>>>(a); \
-    return dry ? hipSuccess : hipGetLastError();                                                         \
+#define X(R_, WR_, WK_, U_, NT_)                                                                                \
+  if (t.R == R_ && t.WR == WR_ && t.WK == WK_ && t.U == U_ && t.NT == NT_) {                                    \
+    if (!dry) k_contract_mfma<FMT, M, T, R_, WR_, WK_, U_, NT_><<<(unsigned)a.nrb, WR_ * WK_ * 64, 0, s>>>(a); \
+    return dry ? hipSuccess : hipGetLastError();                                                                \
   }
   BS32_MMA_TILES(X)
 #undef X
@@ -923,7 +993,9 @@ static hipError_t dispatch(const Args& a, int fmt, const Tile& t, hipStream_t s,
   const int m = a.m;
   switch (fmt) {
     case F_F64: return m == 2 ? launch_f64<2>(a, t, s, dry) : launch_f64<1>(a, t, s, dry);
-    case F_F32: return m == 2 ? launch_f32<2>(a, t, s, dry) : launch_f32<1>(a, t, s, dry);
+    case F_F32:
+      if (t.MM) return m == 2 ? launch_mma<F_F32, 2, 2>(a, t, s, dry) : launch_mma<F_F32, 1, 2>(a, t, s, dry);
+      return m == 2 ? launch_f32<2>(a, t, s, dry) : launch_f32<1>(a, t, s, dry);
     case F_BF16: return m == 2 ? launch_mma<F_BF16, 2, 2>(a, t, s, dry) : launch_mma<F_BF16, 1, 2>(a, t, s, dry);
     case F_F16: return m == 2 ? launch_mma<F_F16, 2, 2>(a, t, s, dry) : launch_mma<F_F16, 1, 2>(a, t, s, dry);
     case F_E4M3: return m == 2 ? launch_mma<F_E4M3, 2, 3>(a, t, s, dry) : launch_mma<F_E4M3, 1, 3>(a, t, s, dry);

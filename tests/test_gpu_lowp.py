@@ -5,7 +5,7 @@
 * one right-hand side per mode matches the oracle's reduced-precision
   definition (stored weights, split vector operand, exact sums) within the
   FP32-accumulation bound 4 * 2^-24 * L * (gain/N) sum_j |A_ij||v_j|, with L the
-  number of products one FP32 partial sum holds (16 for FP32 VALU, 256 for the
+  number of products one FP32 partial sum holds (128 for FP32, 256 for the
   BF16/FP16 matrix cores, 512 for e4m3);
 * short solves track the oracle's reduced-precision solve.
 """
@@ -18,7 +18,7 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-MODES = {1: ("rhs_fp32", 1, 16), 2: ("rhs_bf16", 2, 256), 3: ("rhs_fp16", 3, 256), 4: ("rhs_fp8", 4, 512)}
+MODES = {1: ("rhs_fp32", 1, 128), 2: ("rhs_bf16", 2, 256), 3: ("rhs_fp16", 3, 256), 4: ("rhs_fp8", 4, 512)}
 NP_DT = {1: np.float32, 2: np.uint16, 3: np.uint16, 4: np.uint8}
 
 
@@ -107,6 +107,38 @@ def test_solve_lowp_tracks_oracle(bs, orc, name, make, mode):
     say(f"   rel l2 {rel:.2e} accepted {st['n_accept']} / {rst['n_accept']}")
     assert rel <= 2e-5
     assert abs(st["n_accept"] - rst["n_accept"]) <= max(2, 0.03 * rst["n_accept"])
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4])
+def test_every_tile_matches_oracle(bs, orc, mode):
+    """Every instantiated contraction tile (the autotuner's candidates), forced one
+    by one, on a ragged size; FP64 to summation-order rounding, others to the bound."""
+    b, s = bs
+    w = workloads.kuramoto(777, seed=76)
+    s.set_workload(w)
+    if mode == 0:
+        ref = orc.rhs(w["kind"], w["n"], w["y0"], A=w["A"], param=w["param"], gain=w["gain"])
+        tol = 1e-13 * (np.abs(w["A"]).sum(1) * abs(w["gain"]) / w["n"]) + 1e-15
+    else:
+        mname, fmt, L = MODES[mode]
+        ref = orc.rhs_lowp(w["kind"], w["n"], w["y0"], fmt, A=w["A"], param=w["param"], gain=w["gain"])
+        tol = 4 * 2.0**-24 * L * (np.abs(w["A"]).sum(1) * 2 * abs(w["gain"]) / w["n"]) + 1e-15
+    k = 0
+    try:
+        while True:
+            s.set_options(tile=k)
+            say(f"[tile] mode {mode} tile {k}")
+            try:
+                f = s.rhs(w["y0"], mode=mode)
+            except b.BS32Error as e:
+                assert e.code == b.EINVAL and k > 0  # past the last candidate
+                break
+            err = np.abs(f - ref)
+            assert np.all(err <= tol), (k, np.max(err / tol))
+            k += 1
+    finally:
+        s.set_options(tile=-1)
+    assert k >= 8
 
 
 def test_lowp_reproducible(bs):
