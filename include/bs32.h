@@ -160,6 +160,31 @@ bs32_status bs32_time_contraction(bs32_ctx* ctx, int precision_mode, int repeat,
    (A ~= s * stored).  For inspection and tests of the quantizer. */
 bs32_status bs32_get_packed_coupling(bs32_ctx* ctx, int precision_mode, void* dst, size_t bytes, double* scale);
 
+/* ---- ensembles -------------------------------------------------------------
+   Many independent instances of the general model (each its own N, A, parameters,
+   initial value and interval) solved together: each stage of an attempt is one
+   grouped launch over the row blocks of every running instance, each instance
+   keeps its own step size, counters and status (Sec. 2.2 applies per instance). */
+
+/* Copy and pack `count` systems, all of the same kind (descs as for
+   bs32_set_system).  Replaces any previous system or ensemble. */
+bs32_status bs32_set_ensemble(bs32_ctx* ctx, int32_t count, const bs32_system_desc* descs);
+
+/* Solve instance b from (t0[b], y0_b) to t1[b] for every b, with shared rtol, atol
+   and precision mode.  y0_concat, y_out_concat: the instances' agent-major vectors
+   concatenated in instance order (sum_b d N_b FP64 values; host or device; may be
+   the same buffer).  t0, t1: host arrays of `count` values (t1[b] >= t0[b]).
+   status_out: host array of `count` bs32_status values (may be NULL).  Returns
+   BS32_OK when every instance reached its t1, otherwise the status of the first
+   instance that did not. */
+bs32_status bs32_solve_batch(bs32_ctx* ctx, const double* y0_concat, const double* t0, const double* t1,
+                             double rtol, double atol, int precision_mode, double* y_out_concat,
+                             int32_t* status_out);
+
+/* Statistics of instance `instance` of the last batch solve (bs32_stats gives the
+   totals: counts summed, time of the whole batch). */
+bs32_status bs32_batch_stats(const bs32_ctx* ctx, int32_t instance, bs32_stats_t* out);
+
 /* Trace records of the last solve, oldest first; *n_records receives the count copied. */
 bs32_status bs32_get_trace(bs32_ctx* ctx, bs32_trace_rec* buf, size_t cap, size_t* n_records);
 

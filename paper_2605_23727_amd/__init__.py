@@ -80,6 +80,10 @@ _SIGS = {
     "bs32_get_trace": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "bs32_time_contraction": ([C.c_void_p, C.c_int, C.c_int, C.c_void_p], C.c_int),
     "bs32_get_packed_coupling": ([C.c_void_p, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "bs32_set_ensemble": ([C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
+    "bs32_solve_batch": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_int,
+                          C.c_void_p, C.c_void_p], C.c_int),
+    "bs32_batch_stats": ([C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
     "bs32_last_error": ([C.c_void_p], C.c_char_p),
     "bs32_destroy": ([C.c_void_p], None),
 }
@@ -232,6 +236,42 @@ class Solver:
         ms = C.c_double(0)
         self._check(lib().bs32_time_contraction(self._ctx, int(mode), int(repeat), C.byref(ms)))
         return ms.value
+
+    # -- ensembles
+    def set_ensemble(self, systems):
+        """systems: list of dicts with kind, n, A, param, gain (same kind for all)."""
+        keep = []
+        descs = (SystemDesc * len(systems))()
+        for q, w in enumerate(systems):
+            Ab = _Buf(w.get("A"), w["n"] * w["n"])
+            pb = _Buf(w.get("param"), w["n"])
+            keep += [Ab, pb]
+            descs[q] = SystemDesc(w["kind"], 0, w["n"], Ab.ptr, pb.ptr, float(w.get("gain", 1.0)))
+        self._check(lib().bs32_set_ensemble(self._ctx, len(systems), descs))
+        self.kind = systems[0]["kind"]
+        self.ens_n = [int(w["n"]) for w in systems]
+        self.n = None
+
+    def solve_batch(self, y0_concat, t0, t1, rtol, atol=None, mode=PREC_FP64, out=None):
+        """Returns (y_out concatenated, per-instance status array, totals dict)."""
+        B = len(self.ens_n)
+        m = DIM[self.kind] * sum(self.ens_n)
+        yb = _Buf(y0_concat, m)
+        if out is None:
+            out = np.empty(m)
+        ob = _Buf(out, m, writable=True)
+        t0a = np.ascontiguousarray(np.broadcast_to(np.asarray(t0, dtype=np.float64), (B,)))
+        t1a = np.ascontiguousarray(np.broadcast_to(np.asarray(t1, dtype=np.float64), (B,)))
+        st = np.zeros(B, dtype=np.int32)
+        rc = lib().bs32_solve_batch(self._ctx, yb.ptr, t0a.ctypes.data, t1a.ctypes.data, float(rtol),
+                                    float(rtol if atol is None else atol), int(mode), ob.ptr, st.ctypes.data)
+        self._check(rc, allow_positive=True)
+        return out, st, self.stats()
+
+    def batch_stats(self, instance):
+        s = Stats()
+        self._check(lib().bs32_batch_stats(self._ctx, int(instance), C.byref(s)))
+        return s.as_dict()
 
     def packed_coupling(self, mode):
         """(stored N x N matrix as raw format values, power-of-two scale) for a precision mode."""

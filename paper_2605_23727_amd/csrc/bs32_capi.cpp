@@ -111,7 +111,10 @@ struct bs32_ctx {
   std::string graph_key;
 
   bs32_stats_t st{};
+
+  struct EnsembleState* ens = nullptr;  // set by bs32_set_ensemble (bs32_ensemble.inc)
 };
+void ens_free(bs32_ctx* c);
 
 namespace {
 
@@ -488,6 +491,7 @@ void bs32_destroy(bs32_ctx* c) {
   if (!c) return;
   ignore(hipSetDevice(c->device));
   if (c->stream) ignore(hipStreamSynchronize(c->stream));
+  ens_free(c);
   free_system(c);
   dfree(c->ctlbuf[0]);
   dfree(c->ctlbuf[1]);
@@ -525,6 +529,7 @@ bs32_status bs32_set_system(bs32_ctx* c, const bs32_system_desc* sd) {
   if (!std::isfinite(sd->gain)) return fail(c, BS32_EINVAL, "gain must be finite");
   HIPCHK(c, hipSetDevice(c->device));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  ens_free(c);
   free_system(c);
   c->kind = sd->kind;
   c->d = d;
@@ -798,3 +803,5 @@ bs32_status bs32_get_trace(bs32_ctx* c, bs32_trace_rec* buf, size_t cap, size_t*
 }
 
 }  // extern "C"
+
+#include "bs32_ensemble.inc"

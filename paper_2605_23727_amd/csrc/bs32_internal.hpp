@@ -82,6 +82,19 @@ struct Args {
   int vshift;             // exponent shift between consecutive terms
 };
 
+// Ensembles: one work item = (instance, row block) for a contraction, or
+// (instance, 256-agent slice) for prep / finalize.
+struct Item {
+  unsigned inst, blk;
+};
+constexpr int kStages = 6;  // Args copies per instance and control parity: one per Stage
+struct Group {
+  const Args* inst;       // [(instance * kStages + stage) * 2 + parity]
+  const Item* items;      // live work items
+  const unsigned* count;  // number of live items
+  int stage, par;
+};
+
 // Contraction tile: WR row groups x WK k-slices of waves per workgroup; each wave
 // owns R rows (VALU kernels) or R tiles of 16 rows (matrix-core kernels) and
 // keeps U loads per row in flight.
@@ -102,6 +115,9 @@ hipError_t launch_prep(const Args& a, hipStream_t s);
 hipError_t launch_finalize(const Args& a, hipStream_t s);
 hipError_t launch_set_status(Ctl* c, int code, hipStream_t s);
 hipError_t launch_contract(const Args& a, int fmt, const Tile& t, hipStream_t s);
+hipError_t launch_group_contract(const Group& g, int m, int fmt, const Tile& t, unsigned grid, hipStream_t s);
+hipError_t launch_group_prep(const Group& g, unsigned grid, hipStream_t s);
+hipError_t launch_group_finalize(const Group& g, unsigned grid, hipStream_t s);
 hipError_t launch_to_soa(const double* src, double* dst, long long n, int d, long long np, hipStream_t s);
 hipError_t launch_from_soa(const double* src, double* dst, long long n, int d, long long np, hipStream_t s);
 hipError_t launch_pack_f64(const double* src, double* dst, long long n, long long ld, long long rows, int uniform,

@@ -331,12 +331,11 @@ __device__ void contract_tail(const Args& a, int rb, double (*sP)[M], int RB) {
 // U chunks of 128 columns in flight.  The WK slice sums are added in slice order.
 // ---------------------------------------------------------------------------
 template <int M, int R, int WR, int WK, int U, bool NT>
-__global__ __launch_bounds__(WR* WK * 64) void k_contract_f64(Args a) {
+__device__ __forceinline__ void contract_f64(const Args& a, int rb) {
   constexpr int RB = R * WR;
   __shared__ double sPart[WK][RB][M];
   __shared__ double sP[RB][M];
   if (a.ctl->status != kRunning) return;
-  const int rb = block_row(a);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w % WR, wk = w / WR;
   const long long row0 = (long long)rb * RB + wr * R;
@@ -418,13 +417,12 @@ __global__ __launch_bounds__(WR* WK * 64) void k_contract_f64(Args a) {
 // them to FP64 accumulators (FP32 within a chunk, FP64 across chunks).
 // ---------------------------------------------------------------------------
 template <int M, int T, int R, int WR, int WK, int U, bool NT>
-__global__ __launch_bounds__(WR* WK * 64) void k_contract_f32(Args a) {
+__device__ __forceinline__ void contract_f32(const Args& a, int rb) {
   constexpr int RB = R * WR;
   constexpr int NC = M * T;
   __shared__ double sPart[WK][RB][NC];
   __shared__ double sP[RB][M];
   if (a.ctl->status != kRunning) return;
-  const int rb = block_row(a);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w % WR, wk = w / WR;
   const long long row0 = (long long)rb * RB + wr * R;
@@ -529,7 +527,7 @@ __device__ __forceinline__ f32x4 mma(u32x4 av, u32x4 bv, f32x4 c) {
 }
 
 template <int FMT, int M, int T, int RT, int WR, int WK, int U, bool NT>
-__global__ __launch_bounds__(WR* WK * 64) void k_contract_mfma(Args a) {
+__device__ __forceinline__ void contract_mfma(const Args& a, int rb) {
   constexpr int NC = M * T;
   static_assert(NC <= 16, "vector terms exceed the MFMA tile width");
   constexpr int RB = 16 * RT * WR;
@@ -539,7 +537,6 @@ __global__ __launch_bounds__(WR* WK * 64) void k_contract_mfma(Args a) {
   __shared__ double sPart[WK][RB][NC];
   __shared__ double sP[RB][M];
   if (a.ctl->status != kRunning) return;
-  const int rb = block_row(a);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w % WR, wk = w / WR;
   const int r16 = lane & 15, g = lane >> 4;
@@ -622,10 +619,10 @@ __global__ __launch_bounds__(WR* WK * 64) void k_contract_mfma(Args a) {
 // prep: vector operand of an evaluation from the current state (used for the
 // first evaluation of a solve, for bs32_rhs and for kernel timing).
 // ---------------------------------------------------------------------------
-__global__ void k_prep(Args a) {
+__device__ __forceinline__ void prep_block(const Args& a, int blk) {
   const Ctl* ctl = a.ctl;
   if (ctl->status != kRunning) return;
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long i = (long long)blk * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const double* X = a.X[ctl->xi];
   const double* K1 = a.Kf[ctl->ki];
@@ -634,6 +631,48 @@ __global__ void k_prep(Args a) {
   else if (a.stage == ST_S2) y = X[i] + ctl->ha * (kA21 * K1[i]);
   write_operand(a, 0, i, y);
 }
+__global__ void k_prep(Args a) { prep_block(a, blockIdx.x); }
+
+// ---------------------------------------------------------------------------
+// kernels of one system (block index = row block) and of an ensemble (each
+// workgroup walks the live work items of a grouped launch)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ const Args& group_args(const Group& g, const Item& w) {
+  return g.inst[((size_t)w.inst * kStages + g.stage) * 2 + g.par];
+}
+#define BS32_GROUP_LOOP(BODY)                                       \
+  const unsigned cnt_ = *g.count;                                   \
+  for (unsigned it_ = blockIdx.x; it_ < cnt_; it_ += gridDim.x) {   \
+    const Item w_ = g.items[it_];                                   \
+    BODY(group_args(g, w_), (int)w_.blk);                           \
+    __syncthreads();                                                \
+  }
+
+template <int M, int R, int WR, int WK, int U, bool NT>
+__global__ __launch_bounds__(WR* WK * 64) void k_contract_f64(Args a) {
+  contract_f64<M, R, WR, WK, U, NT>(a, block_row(a));
+}
+template <int M, int R, int WR, int WK, int U, bool NT>
+__global__ __launch_bounds__(WR* WK * 64) void k_group_f64(Group g) {
+  BS32_GROUP_LOOP((contract_f64<M, R, WR, WK, U, NT>))
+}
+template <int M, int T, int R, int WR, int WK, int U, bool NT>
+__global__ __launch_bounds__(WR* WK * 64) void k_contract_f32(Args a) {
+  contract_f32<M, T, R, WR, WK, U, NT>(a, block_row(a));
+}
+template <int M, int T, int R, int WR, int WK, int U, bool NT>
+__global__ __launch_bounds__(WR* WK * 64) void k_group_f32(Group g) {
+  BS32_GROUP_LOOP((contract_f32<M, T, R, WR, WK, U, NT>))
+}
+template <int FMT, int M, int T, int RT, int WR, int WK, int U, bool NT>
+__global__ __launch_bounds__(WR* WK * 64) void k_contract_mfma(Args a) {
+  contract_mfma<FMT, M, T, RT, WR, WK, U, NT>(a, block_row(a));
+}
+template <int FMT, int M, int T, int RT, int WR, int WK, int U, bool NT>
+__global__ __launch_bounds__(WR* WK * 64) void k_group_mfma(Group g) {
+  BS32_GROUP_LOOP((contract_mfma<FMT, M, T, RT, WR, WK, U, NT>))
+}
+__global__ __launch_bounds__(256) void k_group_prep(Group g) { BS32_GROUP_LOOP(prep_block) }
 
 // elementary controller (reading of the unspecified step-size correction; the
 // estimate is O(h^3), so the exponent is 1/3)
@@ -733,15 +772,15 @@ __device__ void finalize(const Args& a, Ctl* c, double m0, double m1, bool write
 // same new control state from the same inputs (fixed-order reduction, so the
 // copies agree bit for bit); workgroup 0 alone stores it into the other control
 // buffer.  Then each workgroup prepares its slice of the next vector operand.
-__global__ __launch_bounds__(256) void k_finalize(Args a) {
+__device__ __forceinline__ void finalize_block(const Args& a, int blk) {
   __shared__ double sR0[4], sR1[4];
   __shared__ Ctl sc;
   __shared__ int s_next;
   constexpr int kWords = (int)(sizeof(Ctl) / sizeof(unsigned long long));
   static_assert(sizeof(Ctl) % sizeof(unsigned long long) == 0 && kWords <= 256, "control block layout");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-  const bool writer = blockIdx.x == 0;
-  const long long i = (long long)blockIdx.x * blockDim.x + tid;
+  const bool writer = blk == 0;
+  const long long i = (long long)blk * blockDim.x + tid;
   // issue every independent load at once: the control block, the block maxima and
   // both candidate buffers of this agent (which one is current depends on the decision)
   if (tid < kWords) ((unsigned long long*)&sc)[tid] = ((const unsigned long long*)a.ctl)[tid];
@@ -790,6 +829,9 @@ __global__ __launch_bounds__(256) void k_finalize(Args a) {
     write_operand(a, 0, i, y);
   }
 }
+
+__global__ __launch_bounds__(256) void k_finalize(Args a) { finalize_block(a, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_group_finalize(Group g) { BS32_GROUP_LOOP(finalize_block) }
 
 __global__ void k_set_status(Ctl* c, int code) {
   if (threadIdx.x == 0 && c->status == kRunning) c->status = code;
@@ -955,60 +997,86 @@ const Tile* tile_candidates(int fmt, int* count) {
   return kMmaTiles;
 }
 
+// one contraction launch: a single system (a) or an ensemble (g, ggrid workgroups)
+struct Launch {
+  const Args* a;
+  const Group* g;
+  unsigned ggrid;
+  hipStream_t s;
+  bool dry;
+};
+#define BS32_LAUNCH(SINGLE, GROUP, THREADS)                                      \
+  if (!L.dry) {                                                                  \
+    if (L.g) GROUP<<<L.ggrid, THREADS, 0, L.s>>>(*L.g);                          \
+    else SINGLE<<<(unsigned)L.a->nrb, THREADS, 0, L.s>>>(*L.a);                  \
+  }                                                                              \
+  return L.dry ? hipSuccess : hipGetLastError();
+
 template <int M>
-static hipError_t launch_f64(const Args& a, const Tile& t, hipStream_t s, bool dry) {
-#define X(R_, WR_, WK_, U_, NT_)                                                                           \
-  if (t.R == R_ && t.WR == WR_ && t.WK == WK_ && t.U == U_ && t.NT == NT_) {                               \
-    if (!dry) k_contract_f64<M, R_, WR_, WK_, U_, NT_><<<(unsigned)a.nrb, WR_ * WK_ * 64, 0, s>>>(a);      \
-    return dry ? hipSuccess : hipGetLastError();                                                           \
+static hipError_t launch_f64(const Launch& L, const Tile& t) {
+#define X(R_, WR_, WK_, U_, NT_)                                                                 \
+  if (t.R == R_ && t.WR == WR_ && t.WK == WK_ && t.U == U_ && t.NT == NT_) {                     \
+    BS32_LAUNCH((k_contract_f64<M, R_, WR_, WK_, U_, NT_>), (k_group_f64<M, R_, WR_, WK_, U_, NT_>), \
+                WR_ * WK_ * 64)                                                                  \
   }
   BS32_F64_TILES(X)
 #undef X
   return hipErrorInvalidValue;
 }
 template <int M>
-static hipError_t launch_f32(const Args& a, const Tile& t, hipStream_t s, bool dry) {
-#define X(R_, WR_, WK_, U_, NT_)                                                                           \
-  if (t.R == R_ && t.WR == WR_ && t.WK == WK_ && t.U == U_ && t.NT == NT_) {                               \
-    if (!dry) k_contract_f32<M, 2, R_, WR_, WK_, U_, NT_><<<(unsigned)a.nrb, WR_ * WK_ * 64, 0, s>>>(a);   \
-    return dry ? hipSuccess : hipGetLastError();                                                           \
+static hipError_t launch_f32(const Launch& L, const Tile& t) {
+#define X(R_, WR_, WK_, U_, NT_)                                                                       \
+  if (t.R == R_ && t.WR == WR_ && t.WK == WK_ && t.U == U_ && t.NT == NT_) {                           \
+    BS32_LAUNCH((k_contract_f32<M, 2, R_, WR_, WK_, U_, NT_>), (k_group_f32<M, 2, R_, WR_, WK_, U_, NT_>), \
+                WR_ * WK_ * 64)                                                                        \
   }
   BS32_F32_TILES(X)
 #undef X
   return hipErrorInvalidValue;
 }
 template <int FMT, int M, int T>
-static hipError_t launch_mma(const Args& a, const Tile& t, hipStream_t s, bool dry) {
-#define X(R_, WR_, WK_, U_, NT_)                                                                                \
-  if (t.R == R_ && t.WR == WR_ && t.WK == WK_ && t.U == U_ && t.NT == NT_) {                                    \
-    if (!dry) k_contract_mfma<FMT, M, T, R_, WR_, WK_, U_, NT_><<<(unsigned)a.nrb, WR_ * WK_ * 64, 0, s>>>(a); \
-    return dry ? hipSuccess : hipGetLastError();                                                                \
+static hipError_t launch_mma(const Launch& L, const Tile& t) {
+#define X(R_, WR_, WK_, U_, NT_)                                                            \
+  if (t.R == R_ && t.WR == WR_ && t.WK == WK_ && t.U == U_ && t.NT == NT_) {                \
+    BS32_LAUNCH((k_contract_mfma<FMT, M, T, R_, WR_, WK_, U_, NT_>),                        \
+                (k_group_mfma<FMT, M, T, R_, WR_, WK_, U_, NT_>), WR_ * WK_ * 64)           \
   }
   BS32_MMA_TILES(X)
 #undef X
   return hipErrorInvalidValue;
 }
+#undef BS32_LAUNCH
 
-static hipError_t dispatch(const Args& a, int fmt, const Tile& t, hipStream_t s, bool dry) {
-  const int m = a.m;
+static hipError_t dispatch(const Launch& L, int m, int fmt, const Tile& t) {
   switch (fmt) {
-    case F_F64: return m == 2 ? launch_f64<2>(a, t, s, dry) : launch_f64<1>(a, t, s, dry);
+    case F_F64: return m == 2 ? launch_f64<2>(L, t) : launch_f64<1>(L, t);
     case F_F32:
-      if (t.MM) return m == 2 ? launch_mma<F_F32, 2, 2>(a, t, s, dry) : launch_mma<F_F32, 1, 2>(a, t, s, dry);
-      return m == 2 ? launch_f32<2>(a, t, s, dry) : launch_f32<1>(a, t, s, dry);
-    case F_BF16: return m == 2 ? launch_mma<F_BF16, 2, 2>(a, t, s, dry) : launch_mma<F_BF16, 1, 2>(a, t, s, dry);
-    case F_F16: return m == 2 ? launch_mma<F_F16, 2, 2>(a, t, s, dry) : launch_mma<F_F16, 1, 2>(a, t, s, dry);
-    case F_E4M3: return m == 2 ? launch_mma<F_E4M3, 2, 3>(a, t, s, dry) : launch_mma<F_E4M3, 1, 3>(a, t, s, dry);
+      if (t.MM) return m == 2 ? launch_mma<F_F32, 2, 2>(L, t) : launch_mma<F_F32, 1, 2>(L, t);
+      return m == 2 ? launch_f32<2>(L, t) : launch_f32<1>(L, t);
+    case F_BF16: return m == 2 ? launch_mma<F_BF16, 2, 2>(L, t) : launch_mma<F_BF16, 1, 2>(L, t);
+    case F_F16: return m == 2 ? launch_mma<F_F16, 2, 2>(L, t) : launch_mma<F_F16, 1, 2>(L, t);
+    case F_E4M3: return m == 2 ? launch_mma<F_E4M3, 2, 3>(L, t) : launch_mma<F_E4M3, 1, 3>(L, t);
     default: return hipErrorInvalidValue;
   }
 }
 
 bool tile_supported(int fmt, int m, const Tile& t) {
-  Args a{};
-  a.m = m;
-  return dispatch(a, fmt, t, nullptr, true) == hipSuccess;
+  return dispatch(Launch{nullptr, nullptr, 0, nullptr, true}, m, fmt, t) == hipSuccess;
 }
 
-hipError_t launch_contract(const Args& a, int fmt, const Tile& t, hipStream_t s) { return dispatch(a, fmt, t, s, false); }
+hipError_t launch_contract(const Args& a, int fmt, const Tile& t, hipStream_t s) {
+  return dispatch(Launch{&a, nullptr, 0, s, false}, a.m, fmt, t);
+}
+hipError_t launch_group_contract(const Group& g, int m, int fmt, const Tile& t, unsigned grid, hipStream_t s) {
+  return dispatch(Launch{nullptr, &g, grid, s, false}, m, fmt, t);
+}
+hipError_t launch_group_prep(const Group& g, unsigned grid, hipStream_t s) {
+  k_group_prep<<<grid, 256, 0, s>>>(g);
+  return hipGetLastError();
+}
+hipError_t launch_group_finalize(const Group& g, unsigned grid, hipStream_t s) {
+  k_group_finalize<<<grid, 256, 0, s>>>(g);
+  return hipGetLastError();
+}
 
 }  // namespace bs32

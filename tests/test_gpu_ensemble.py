@@ -1,0 +1,131 @@
+"""GPU tests of the batched ensemble path (grouped launches over many instances).
+
+Each instance of a batch must equal the single-system GPU solve of the same
+instance bit for bit when both use the same contraction tile (same kernels,
+same summation order), and match the oracle at the FP64 parity bar.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def bs():
+    import paper_2605_23727_amd as b
+    s = b.Solver(0)
+    yield b, s
+    s.close()
+
+
+def _members(B, seed, t1=2.0, kind="kuramoto"):
+    g = np.random.default_rng(seed)
+    ns = g.integers(33, 700, B)
+    ws = []
+    for q, n in enumerate(ns):
+        if kind == "kuramoto":
+            ws.append(workloads.kuramoto(int(n), seed=seed * 100 + q, K=float(g.uniform(0.5, 4.0)), t1=t1))
+        else:
+            ws.append(workloads.osc2(int(n), seed=seed * 100 + q, t1=t1))
+    return ws
+
+
+@pytest.mark.parametrize("kind", ["kuramoto", "osc2"])
+def test_batch_fp64_matches_oracle_and_single(bs, orc, kind):
+    b, s = bs
+    ws = _members(9, 5 if kind == "kuramoto" else 6, kind=kind)
+    t1 = np.array([w["t1"] for w in ws])
+    t1[3] = 0.0  # empty interval: returns y0
+    t1[5] = 0.7
+    say(f"[batch fp64] {kind} B={len(ws)} n={[w['n'] for w in ws]}")
+    s.set_options(tile=2)
+    try:
+        s.set_ensemble(ws)
+        y0 = np.concatenate([w["y0"] for w in ws])
+        y, st, tot = s.solve_batch(y0, 0.0, t1, 1e-7)
+        assert np.all(st == 0)
+        off = 0
+        single = b.Solver(0)
+        single.set_options(tile=2)
+        for q, w in enumerate(ws):
+            m = w["y0"].size
+            yq = y[off:off + m]
+            off += m
+            bst = s.batch_stats(q)
+            if t1[q] == 0.0:
+                assert np.array_equal(yq, w["y0"]) and bst["n_fev"] == 0
+                continue
+            ref, rst, _ = orc.bs32_solve(w["kind"], w["n"], w["y0"], 0.0, t1[q], 1e-7, A=w["A"],
+                                         param=w["param"], gain=w["gain"])
+            rel = np.linalg.norm(yq - ref) / np.linalg.norm(ref)
+            assert rel <= 1e-10, (q, rel)
+            assert abs(bst["n_accept"] - rst["n_accept"]) <= max(1, 0.01 * rst["n_accept"])
+            single.set_workload(w)
+            ys, sst = single.solve(w["y0"], 0.0, t1[q], 1e-7)
+            assert np.array_equal(ys, yq), q
+            assert sst["n_accept"] == bst["n_accept"] and sst["n_reject"] == bst["n_reject"]
+        single.close()
+        assert tot["n_fev"] == sum(s.batch_stats(q)["n_fev"] for q in range(len(ws)))
+    finally:
+        s.set_options(tile=-1)
+
+
+@pytest.mark.parametrize("mode", [1, 2, 4])
+def test_batch_reduced_equals_single(bs, mode):
+    b, s = bs
+    ws = _members(6, 7)
+    say(f"[batch mode {mode}] kuramoto B=6")
+    s.set_options(tile=1)
+    try:
+        s.set_ensemble(ws)
+        y, st, _ = s.solve_batch(np.concatenate([w["y0"] for w in ws]), 0.0, 1.0, 1e-6, mode=mode)
+        assert np.all(st == 0)
+        single = b.Solver(0)
+        single.set_options(tile=1)
+        off = 0
+        for w in ws:
+            m = w["y0"].size
+            single.set_workload(w)
+            ys, _ = single.solve(w["y0"], 0.0, 1.0, 1e-6, mode=mode)
+            assert np.array_equal(ys, y[off:off + m])
+            off += m
+        single.close()
+    finally:
+        s.set_options(tile=-1)
+
+
+def test_batch_autotuned_and_failures(bs, orc):
+    b, s = bs
+    ws = _members(12, 8, t1=1.5)
+    y0 = np.concatenate([w["y0"] for w in ws])
+    k = sum(w["y0"].size for w in ws[:4])
+    y0[k + 2] = math.nan  # instance 4 starts from a NaN
+    say("[batch autotuned + NaN instance] kuramoto B=12")
+    s.set_ensemble(ws)
+    y, st, tot = s.solve_batch(y0, 0.0, 1.5, 1e-6)
+    assert st[4] == b.NONFINITE
+    assert np.all(np.delete(st, 4) == 0)
+    off = 0
+    for q, w in enumerate(ws):
+        m = w["y0"].size
+        if q != 4:
+            ref, _, _ = orc.bs32_solve(w["kind"], w["n"], w["y0"], 0.0, 1.5, 1e-6, A=w["A"], param=w["param"],
+                                       gain=w["gain"])
+            assert np.linalg.norm(y[off:off + m] - ref) / np.linalg.norm(ref) <= 1e-10
+        off += m
+
+
+def test_batch_rejects_mixed_kinds(bs):
+    b, s = bs
+    with pytest.raises(b.BS32Error):
+        s.set_ensemble([workloads.kuramoto(40, seed=1), workloads.osc2(40, seed=2)])
