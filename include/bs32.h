@@ -188,6 +188,67 @@ bs32_status bs32_batch_stats(const bs32_ctx* ctx, int32_t instance, bs32_stats_t
 /* Trace records of the last solve, oldest first; *n_records receives the count copied. */
 bs32_status bs32_get_trace(bs32_ctx* ctx, bs32_trace_rec* buf, size_t cap, size_t* n_records);
 
+/* ---- learned step-size proposer ---------------------------------------------
+   The paper says only that the error estimate drives the step-size correction
+   (Sec. 2.2).  This extension lets a small network propose the next step while
+   the estimate stays the only judge of acceptance: a step is accepted iff
+   E < Rel whatever proposed it.
+
+   Network: 9 -> 64 -> 64 -> 1, tanh hidden layers, BF16-valued weights, FP32
+   accumulation, on standardized features x_k = (f_k - mu_k) * inv_sd_k (FP32).
+   Parameter vector of BS32_MLP_PARAMS floats, in this order: W1[64][9], b1[64],
+   W2[64][64], b2[64], w3[64], b3 (4865 network weights, used rounded to BF16),
+   mu[9], inv_sd[9] (used as given).
+   Features after an accepted attempt n (most recent first):
+     f[0..3] = log h_n, log h_{n-1}, log h_{n-2}, log h_{n-3}   (attempted steps)
+     f[4..7] = log(max(E, 1e-30 Rel) / Rel) of the same attempts
+     f[8]    = log max(fnorm_n, 1e-300), fnorm_n = max_k |K1_k| / max(|X^n_k|, Ab/Rel),
+               the weighted size of f(t_n, X^n) (trace field fnorm)
+   Output: delta = log(h_{n+1} / h_n).  The proposal is used only after an
+   accepted attempt with four attempts recorded, when every |x_k| <= 4 (the
+   features lie where the network was trained) and delta is finite, inside
+   [log 0.2, log 5] and within log 2 of the standard controller's own
+   log(h_{n+1} / h_n); otherwise the standard controller chooses (it always does
+   in the attempt after a rejection).  The step is then clipped to h_max and t1. */
+#define BS32_MLP_PARAMS 4883
+
+/* Training samples from a trace (bs32_get_trace of a solve with tolerance rtol):
+   one per accepted attempt n >= 3 whose next attempt n+1 is not the last record
+   and has 0 < E < inf.  features: 9 floats per sample (layout above) or NULL;
+   labels: 1 float per sample or NULL, the step that would have put attempt n+1's
+   estimate at 0.8 Rel under E ~ h^3:
+     label = log(h_{n+1} / h_n) + (1/3) log(0.8 Rel / E_{n+1}).
+   Buffers must hold n-4 samples; *n_samples receives the count.  Host only. */
+bs32_status bs32_mlp_features(const bs32_trace_rec* trace, size_t n, double rtol, float* features, float* labels,
+                              size_t* n_samples);
+
+/* Train the network on the GPU: mu and inv_sd from the mean and deviation of the
+   n feature vectors; Glorot-uniform initial weights, zero biases and the epoch
+   shuffles drawn from `seed` (splitmix64); minibatch Adam (beta 0.9 / 0.999,
+   eps 1e-8, learning rate lr) on FP32 master weights, every forward pass with
+   their BF16-rounded copies; loss (1/B) sum w (y - label)^2 with w = 4 when the
+   prediction overshoots the label (a rejection costs three RHS) and 1 otherwise.
+   weights_out: BS32_MLP_PARAMS values, the FP32 master weights and the
+   standardization (host).  loss_per_epoch: `epochs` values (host, may be NULL),
+   the loss over all n samples after each epoch.  Host buffers; n >= 2; the last
+   partial minibatch of an epoch is dropped. */
+bs32_status bs32_mlp_train(bs32_ctx* ctx, const float* features, const float* labels, size_t n, int epochs,
+                           int batch, float lr, uint64_t seed, float* weights_out, float* loss_per_epoch);
+
+/* Gradient of that loss over n samples (features as the solver forms them; the
+   weights' own standardization is applied) at the BF16-rounded network weights,
+   by the training kernels.  grad_out: BS32_MLP_PARAMS doubles (zero for mu and
+   inv_sd, which are not trained); loss_out: the loss (may be NULL).  Host
+   buffers.  For tests of the training kernels. */
+bs32_status bs32_mlp_grad(bs32_ctx* ctx, const float* weights, const float* features, const float* labels, size_t n,
+                          double* grad_out, double* loss_out);
+
+/* Select the step-size controller of later solves: kind 0 = standard (weights
+   ignored), kind 1 = learned proposer with `count` = BS32_MLP_PARAMS finite FP32
+   values (host); the network weights are stored rounded to BF16.  Sets
+   options.controller. */
+bs32_status bs32_set_controller(bs32_ctx* ctx, int kind, const float* weights, size_t count);
+
 /* Message of the last negative status on this context (never NULL). */
 const char* bs32_last_error(const bs32_ctx* ctx);
 

@@ -27,6 +27,7 @@ FMT_F64, FMT_F32, FMT_BF16, FMT_F16, FMT_E4M3 = 0, 1, 2, 3, 4
  PREC_PAPER_SINGLE, PREC_PAPER_MIXED1, PREC_PAPER_MIXED2) = range(8)
 OK, MAX_STEPS, MAX_REJECTS, H_TOO_SMALL, NONFINITE = 0, 1, 2, 3, 6
 DIM = {OSC2: 2, LCO_PAPER: 2, KURAMOTO: 1, GOODWIN3: 3}
+MLP_IN, MLP_HID, MLP_PARAMS = 9, 64, 4883
 
 
 def build(force: bool = True) -> str:
@@ -48,7 +49,7 @@ class Options(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("h_max", C.c_double), ("h0", C.c_double),
                 ("i_max", C.c_int64), ("fixed_step", C.c_int32), ("safety", C.c_double),
                 ("facmin", C.c_double), ("facmax", C.c_double), ("split_terms", C.c_int32),
-                ("split_fmt", C.c_int32), ("split_shift", C.c_int32)]
+                ("split_fmt", C.c_int32), ("split_shift", C.c_int32), ("mlp_w", C.c_void_p)]
 
 
 class Stats(C.Structure):
@@ -61,8 +62,8 @@ class Stats(C.Structure):
 
 
 class TraceRec(C.Structure):
-    _fields_ = [("t", C.c_double), ("h", C.c_double), ("err", C.c_double), ("accepted", C.c_int32),
-                ("pad", C.c_int32)]
+    _fields_ = [("t", C.c_double), ("h", C.c_double), ("err", C.c_double), ("fnorm", C.c_double),
+                ("accepted", C.c_int32), ("proposer", C.c_int32)]
 
 
 _lib = None
@@ -92,6 +93,8 @@ def lib():
         L.orc_dp54_solve.argtypes = [P, P, P, C.c_double, C.c_double, P, P]
         L.orc_bs32_attempt.argtypes = [P, C.c_double, C.c_double, P, P, C.c_double, C.c_double, P, P, P]
         L.orc_bs32_tableau.argtypes = [P, P, P, P]
+        L.orc_mlp_forward.argtypes = [P, P]
+        L.orc_mlp_forward.restype = C.c_double
         L.orc_dp54_tableau.argtypes = [P, P, P, P]
         _lib = L
     return _lib
@@ -191,10 +194,17 @@ def options(rtol, atol=None, h_max=0.0, h0=0.0, i_max=0, fixed_step=False, safet
 
 
 def bs32_solve(kind, n, y0, t0, t1, rtol, atol=None, A=None, param=None, gain=1.0, mode=PREC_FP64,
-               trace_cap=0, **opt):
-    """Adaptive BS3(2)+FSAL solve.  Returns (y, stats dict, trace array or None)."""
+               trace_cap=0, mlp_w=None, **opt):
+    """Adaptive BS3(2)+FSAL solve.  Returns (y, stats dict, trace array or None).
+
+    mlp_w: MLP_PARAMS weights of the learned step-size proposer (None: standard controller)."""
     s = _Sys(kind, n, A, param, gain)
     o = options(rtol, atol, **opt)
+    w = None
+    if mlp_w is not None:
+        w = _f64(mlp_w)
+        assert w.size == MLP_PARAMS
+        o.mlp_w = w.ctypes.data
     y0 = _f64(y0)
     y = np.empty_like(y0)
     st = Stats()
@@ -204,9 +214,18 @@ def bs32_solve(kind, n, y0, t0, t1, rtol, atol=None, A=None, param=None, gain=1.
                          C.cast(tr, C.c_void_p) if tr is not None else None, trace_cap, C.byref(tl))
     trace = None
     if tr is not None:
-        trace = np.array([(r.t, r.h, r.err, r.accepted) for r in tr[: tl.value]],
-                         dtype=[("t", "f8"), ("h", "f8"), ("err", "f8"), ("accepted", "i4")])
+        trace = np.array([(r.t, r.h, r.err, r.fnorm, r.accepted, r.proposer) for r in tr[: tl.value]],
+                         dtype=[("t", "f8"), ("h", "f8"), ("err", "f8"), ("fnorm", "f8"), ("accepted", "i4"),
+                                ("proposer", "i4")])
     return y, st.as_dict(), trace
+
+
+def mlp_forward(w, f):
+    """FP64 network output for one feature vector (the C oracle's evaluation)."""
+    w = _f64(w)
+    f = _f64(f)
+    assert w.size == MLP_PARAMS and f.size == MLP_IN
+    return lib().orc_mlp_forward(_ptr(w), _ptr(f))
 
 
 def dp54_solve(kind, n, y0, t0, t1, rtol, atol=None, A=None, param=None, gain=1.0, **opt):

@@ -617,6 +617,34 @@ static double start_step(evaluator* e, int p, double t0, const double* y0, const
   return fmin(fmin(100.0 * h0, h1), h_max);
 }
 
+/* learned proposer network, plain FP64 (parameter order as in the header) */
+double orc_mlp_forward(const double* w, const double* f) {
+  const int I = ORC_MLP_IN, H = ORC_MLP_HID;
+  const double* W1 = w;
+  const double* b1 = W1 + H * I;
+  const double* W2 = b1 + H;
+  const double* b2 = W2 + H * H;
+  const double* w3 = b2 + H;
+  const double b3 = w3[H];
+  const double* mu = w3 + H + 1;
+  const double* inv_sd = mu + I;
+  double x[ORC_MLP_IN], h1[ORC_MLP_HID], h2[ORC_MLP_HID];
+  for (int k = 0; k < I; ++k) x[k] = (f[k] - mu[k]) * inv_sd[k];
+  for (int j = 0; j < H; ++j) {
+    double z = b1[j];
+    for (int k = 0; k < I; ++k) z += W1[j * I + k] * x[k];
+    h1[j] = tanh(z);
+  }
+  for (int j = 0; j < H; ++j) {
+    double z = b2[j];
+    for (int k = 0; k < H; ++k) z += W2[j * H + k] * h1[k];
+    h2[j] = tanh(z);
+  }
+  double y = b3;
+  for (int j = 0; j < H; ++j) y += w3[j] * h2[j];
+  return y;
+}
+
 static void fill_defaults(const orc_options* o, double t0, double t1, double* h_max, int64_t* i_max,
                           double* safety, double* facmin, double* facmax) {
   *h_max = (o->h_max > 0.0) ? o->h_max : 0.1 * fabs(t1 - t0);
@@ -679,6 +707,9 @@ int orc_bs32_solve(const orc_system* s, const orc_options* o, int mode, const do
   int last_rejected = 0;
   int status = ORC_OK;
   const double snap = 4.0 * DBL_EPSILON * fabs(t1);
+  double hist_h[4] = {0}, hist_e[4] = {0}; /* learned proposer history, most recent first */
+  int64_t nhist = 0;
+  int proposer = 0; /* 1: the current h came from the learned proposer */
 
   while (t < t1) {
     const double ha = fmin(h, t1 - t); /* reading: clip the last step onto t1 */
@@ -700,13 +731,19 @@ int orc_bs32_solve(const orc_system* s, const orc_options* o, int mode, const do
                    (BS_B[3] - BS_BT[3]) * K4[k]);
     double err = weighted_max(E, X, Xn, m, o->rtol, o->atol);
     st->err_last = err;
+    double fnorm = 0.0; /* weighted size of f(t_n, X^n), a proposer feature */
+    for (int64_t k = 0; k < m; ++k) {
+      const double v = fabs(K1[k]) / fmax(fabs(X[k]), o->atol / o->rtol);
+      if (isnan(v) || isnan(fnorm)) fnorm = NAN;
+      else if (v > fnorm) fnorm = v;
+    }
     int accepted;
     if (o->fixed_step) accepted = 1;
     else {
       if (!isfinite(err)) {
         status = ORC_NONFINITE;
         if (trace && trace_len && *trace_len < trace_cap) {
-          orc_trace_rec r = {t, ha, err, 0, 0};
+          orc_trace_rec r = {t, ha, err, fnorm, 0, proposer};
           trace[(*trace_len)++] = r;
         }
         st->n_reject++;
@@ -715,7 +752,7 @@ int orc_bs32_solve(const orc_system* s, const orc_options* o, int mode, const do
       accepted = err < o->rtol; /* Sec. 2.2: accept iff the estimate is smaller than Rel */
     }
     if (trace && trace_len && *trace_len < trace_cap) {
-      orc_trace_rec r = {t, ha, err, accepted, 0};
+      orc_trace_rec r = {t, ha, err, fnorm, accepted, proposer};
       trace[(*trace_len)++] = r;
     }
     double hn;
@@ -733,6 +770,38 @@ int orc_bs32_solve(const orc_system* s, const orc_options* o, int mode, const do
       last_rejected = 1;
     }
     st->h_last = ha;
+    for (int q = 3; q > 0; --q) {
+      hist_h[q] = hist_h[q - 1];
+      hist_e[q] = hist_e[q - 1];
+    }
+    hist_h[0] = ha;
+    hist_e[0] = err;
+    nhist++;
+    proposer = 0;
+    /* the learned proposal replaces the controller's after an accepted attempt
+       with four attempts recorded, when its standardized features lie inside
+       [-4, 4] and its step ratio is finite, inside [0.2, 5] and within a factor
+       of 2 of the classical rule's */
+    if (o->mlp_w && accepted && nhist >= 4 && !o->fixed_step && t < t1) {
+      double f[ORC_MLP_IN];
+      for (int q = 0; q < 4; ++q) {
+        f[q] = log(hist_h[q]);
+        f[4 + q] = log(fmax(hist_e[q], 1e-30 * o->rtol) / o->rtol);
+      }
+      f[8] = log(fmax(fnorm, 1e-300));
+      const double* mu = o->mlp_w + (ORC_MLP_PARAMS - 2 * ORC_MLP_IN);
+      const double* inv_sd = mu + ORC_MLP_IN;
+      int inside = 1;
+      for (int k = 0; k < ORC_MLP_IN; ++k)
+        if (!(fabs((f[k] - mu[k]) * inv_sd[k]) <= 4.0)) inside = 0;
+      const double delta = orc_mlp_forward(o->mlp_w, f);
+      const double d_std = log(hn / ha);
+      if (inside && isfinite(delta) && delta >= fmax(log(0.2), d_std - log(2.0)) &&
+          delta <= fmin(log(5.0), d_std + log(2.0))) {
+        hn = ha * exp(delta);
+        proposer = 1;
+      }
+    }
     hn = fmin(hn, h_max);
     h = hn;
     if (t >= t1) break;

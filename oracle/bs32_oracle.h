@@ -73,6 +73,8 @@ typedef struct {
   int32_t split_terms;     /* <= 0: mode default */
   int32_t split_fmt;       /* -1: mode default */
   int32_t split_shift;     /* <= 0: mode default */
+  /* learned step-size proposer: ORC_MLP_PARAMS weights, NULL = standard controller only */
+  const double* mlp_w;
 } orc_options;
 
 typedef struct {
@@ -84,8 +86,9 @@ typedef struct {
 /* one record per step attempt */
 typedef struct {
   double t, h, err;
+  double fnorm;        /* max_k |K1_k| / max(|X^n_k|, atol/rtol) at the start of the attempt */
   int32_t accepted;
-  int32_t pad;
+  int32_t proposer;    /* 1: the learned proposer chose h */
 } orc_trace_rec;
 
 int orc_dim(int kind);
@@ -131,6 +134,20 @@ int orc_bs32_solve(const orc_system* sys, const orc_options* opt, int prec_mode,
 /* Adaptive Dormand-Prince 5(4) in FP64, used only to build reference solutions. */
 int orc_dp54_solve(const orc_system* sys, const orc_options* opt,
                    const double* y0, double t0, double t1, double* y_out, orc_stats* st);
+
+/* ---- learned step-size proposer ----------------------------------------
+   An extension: Sec. 2.2 only says that the error estimate drives the step-size
+   correction.  9 -> 64 -> 64 -> 1 network with tanh hidden layers on standardized
+   features x_k = (f_k - mu_k) inv_sd_k; parameter vector W1[64][9], b1[64],
+   W2[64][64], b2[64], w3[64], b3, mu[9], inv_sd[9].  Features after an
+   accepted attempt n: log h_n..h_{n-3}, log(max(E, 1e-30 Rel)/Rel) of the same
+   attempts, log max(fnorm_n, 1e-300); output log(h_{n+1}/h_n), used when finite
+   and inside [log 0.2, log 5] once four attempts are recorded. */
+#define ORC_MLP_IN 9
+#define ORC_MLP_HID 64
+#define ORC_MLP_PARAMS 4883
+/* FP64 evaluation of the network on one feature vector. */
+double orc_mlp_forward(const double* w, const double* features);
 
 /* Butcher tables as the oracle holds them (for the tableau tests). */
 void orc_bs32_tableau(double c[4], double a[16], double b[4], double bt[4]);

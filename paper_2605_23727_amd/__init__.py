@@ -27,6 +27,8 @@ DIM = {OSC2: 2, LCO_PAPER: 2, KURAMOTO: 1, GOODWIN3: 3}
 # bs32_precision_mode
 (PREC_FP64, PREC_RHS_FP32, PREC_RHS_BF16, PREC_RHS_FP16, PREC_RHS_FP8_E4M3,
  PREC_PAPER_SINGLE, PREC_PAPER_MIXED1, PREC_PAPER_MIXED2) = range(8)
+MLP_PARAMS = 4883  # BS32_MLP_PARAMS
+MLP_IN = 9
 MODE_NAMES = {0: "fp64", 1: "rhs_fp32", 2: "rhs_bf16", 3: "rhs_fp16", 4: "rhs_fp8_e4m3", 5: "paper_single",
               6: "paper_mixed1", 7: "paper_mixed2"}
 
@@ -84,6 +86,11 @@ _SIGS = {
     "bs32_solve_batch": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_int,
                           C.c_void_p, C.c_void_p], C.c_int),
     "bs32_batch_stats": ([C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
+    "bs32_mlp_features": ([C.c_void_p, C.c_size_t, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "bs32_mlp_train": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_int, C.c_float, C.c_uint64,
+                        C.c_void_p, C.c_void_p], C.c_int),
+    "bs32_mlp_grad": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p], C.c_int),
+    "bs32_set_controller": ([C.c_void_p, C.c_int, C.c_void_p, C.c_size_t], C.c_int),
     "bs32_last_error": ([C.c_void_p], C.c_char_p),
     "bs32_destroy": ([C.c_void_p], None),
 }
@@ -106,6 +113,31 @@ def lib():
 
 def exported_symbols():
     return list(_SIGS)
+
+
+_TRACE_DTYPE = np.dtype([("t", "f8"), ("h", "f8"), ("err", "f8"), ("fnorm", "f8"), ("accepted", "i4"),
+                         ("proposer", "i4")])
+
+
+def _f32(x, n=None):
+    a = np.ascontiguousarray(x, dtype=np.float32)
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+def mlp_features(trace, rtol):
+    """(features [n, 9] float32, labels [n] float32) of the learned proposer from a trace."""
+    tr = np.ascontiguousarray(trace, dtype=_TRACE_DTYPE)
+    cap = max(len(tr) - 4, 0)
+    F = np.zeros((cap, MLP_IN), dtype=np.float32)
+    Y = np.zeros(cap, dtype=np.float32)
+    n = C.c_size_t(0)
+    rc = lib().bs32_mlp_features(tr.ctypes.data if len(tr) else None, len(tr), float(rtol),
+                                 F.ctypes.data if cap else None, Y.ctypes.data if cap else None, C.byref(n))
+    if rc != 0:
+        raise BS32Error(rc, "bs32_mlp_features failed")
+    return F[: n.value].copy(), Y[: n.value].copy()
 
 
 class _Buf:
@@ -282,9 +314,38 @@ class Solver:
         return buf, sc.value
 
     def trace(self, cap=1 << 20):
-        buf = (TraceRec * cap)()
+        buf = np.zeros(cap, dtype=_TRACE_DTYPE)
         n = C.c_size_t(0)
-        self._check(lib().bs32_get_trace(self._ctx, buf, cap, C.byref(n)))
-        return np.array([(r.t, r.h, r.err, r.fnorm, r.accepted, r.proposer) for r in buf[: n.value]],
-                        dtype=[("t", "f8"), ("h", "f8"), ("err", "f8"), ("fnorm", "f8"), ("accepted", "i4"),
-                               ("proposer", "i4")])
+        self._check(lib().bs32_get_trace(self._ctx, buf.ctypes.data, cap, C.byref(n)))
+        return buf[: n.value].copy()
+
+    # -- learned step-size proposer
+    def set_controller(self, kind, weights=None):
+        """kind 0: standard controller; kind 1: learned proposer with MLP_PARAMS weights."""
+        w = None if weights is None else _f32(weights, MLP_PARAMS)
+        self._check(lib().bs32_set_controller(self._ctx, int(kind), None if w is None else w.ctypes.data,
+                                              0 if w is None else w.size))
+        self._opt.controller = int(kind)
+
+    def mlp_train(self, features, labels, epochs=50, batch=256, lr=1e-3, seed=0):
+        """Train on the GPU; returns (weights [MLP_PARAMS] float32, loss per epoch [epochs])."""
+        F = _f32(features)
+        n = F.size // MLP_IN
+        Y = _f32(labels, n)
+        W = np.zeros(MLP_PARAMS, dtype=np.float32)
+        L = np.zeros(int(epochs), dtype=np.float32)
+        self._check(lib().bs32_mlp_train(self._ctx, F.ctypes.data, Y.ctypes.data, n, int(epochs), int(batch),
+                                         float(lr), int(seed), W.ctypes.data, L.ctypes.data))
+        return W, L
+
+    def mlp_grad(self, weights, features, labels):
+        """(gradient [MLP_PARAMS] float64, loss) of the training loss at BF16-rounded weights."""
+        W = _f32(weights, MLP_PARAMS)
+        F = _f32(features)
+        n = F.size // MLP_IN
+        Y = _f32(labels, n)
+        g = np.zeros(MLP_PARAMS, dtype=np.float64)
+        loss = C.c_double(0)
+        self._check(lib().bs32_mlp_grad(self._ctx, W.ctypes.data, F.ctypes.data, Y.ctypes.data, n, g.ctypes.data,
+                                        C.byref(loss)))
+        return g, loss.value

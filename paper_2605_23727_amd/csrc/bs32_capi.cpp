@@ -19,6 +19,7 @@
 
 #include "../../include/bs32.h"
 #include "bs32_internal.hpp"
+#include "bs32_mlp.hpp"
 
 using namespace bs32;
 
@@ -113,6 +114,7 @@ struct bs32_ctx {
   bs32_stats_t st{};
 
   struct EnsembleState* ens = nullptr;  // set by bs32_set_ensemble (bs32_ensemble.inc)
+  float* mlp_w = nullptr;               // learned proposer weights (BF16 values), bs32_set_controller
 };
 void ens_free(bs32_ctx* c);
 
@@ -244,6 +246,7 @@ Args make_args(bs32_ctx* c, int fmt, const Geom& g, int stage) {
   a.ctl = c->ctlbuf[c->par];
   a.ctl_out = c->ctlbuf[1 - c->par];
   a.rflag = (unsigned*)((char*)c->scratch + 32);
+  a.mlp = c->mlp_w;
   a.trace = c->trace_d;
   a.gain = c->gain;
   a.invN = 1.0 / (double)c->n;
@@ -496,6 +499,7 @@ void bs32_destroy(bs32_ctx* c) {
   dfree(c->ctlbuf[0]);
   dfree(c->ctlbuf[1]);
   dfree(c->trace_d);
+  dfree(c->mlp_w);
   for (int q = 0; q < 2; ++q)
     if (c->ctl_h[q]) ignore(hipHostFree(c->ctl_h[q]));
   if (c->ev_start) ignore(hipEventDestroy(c->ev_start));
@@ -515,7 +519,8 @@ bs32_status bs32_set_options(bs32_ctx* c, const bs32_options* o) {
     return fail(c, BS32_EINVAL, "controller constants out of range");
   if (o->trace && (o->trace_cap <= 0 || o->trace_cap > (1 << 26))) return fail(c, BS32_EINVAL, "bad trace_cap");
   if (o->fixed_step && !(o->h0 > 0)) return fail(c, BS32_EINVAL, "fixed_step needs h0 > 0");
-  if (o->controller != 0) return fail(c, BS32_EUNSUPPORTED, "controller %d not available", o->controller);
+  if (o->controller != 0 && o->controller != 1) return fail(c, BS32_EINVAL, "unknown controller %d", o->controller);
+  if (o->controller == 1 && !c->mlp_w) return fail(c, BS32_ESTATE, "learned controller needs bs32_set_controller");
   c->opt = *o;
   free_graphs(c);
   return BS32_OK;
@@ -698,6 +703,7 @@ bs32_status bs32_solve(bs32_ctx* c, const double* y0, double t0, double t1, doub
   h->fixed_step = o.fixed_step;
   h->trace_on = o.trace ? 1 : 0;
   h->trace_cap = o.trace ? o.trace_cap : 1;
+  h->use_mlp = (o.controller == 1 && c->mlp_w) ? 1 : 0;
   c->par = 0;
   HIPCHK(c, hipMemcpyAsync(c->ctl_d(), h, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemsetAsync((char*)c->scratch + 32, 0, sizeof(unsigned), c->stream));
@@ -805,3 +811,4 @@ bs32_status bs32_get_trace(bs32_ctx* c, bs32_trace_rec* buf, size_t cap, size_t*
 }  // extern "C"
 
 #include "bs32_ensemble.inc"
+#include "bs32_mlp.inc"

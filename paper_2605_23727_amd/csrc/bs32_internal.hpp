@@ -43,8 +43,14 @@ struct Ctl {
   int fixed_step;
   int trace_on;
   int trace_cap;
-  int pad0;
+  int use_mlp;            // 1: the learned proposer chooses h when its conditions hold
   long long trace_n;      // attempts recorded so far (ring index = trace_n % cap)
+  double hist_h[4];       // attempted steps, most recent first (learned proposer features)
+  double hist_e[4];       // their error estimates
+  long long nhist;        // attempts recorded in the history
+  long long n_mlp;        // steps chosen by the learned proposer
+  int prop_cur;           // 1 if the current step size came from the learned proposer
+  int pad1;
 };
 
 struct TraceRec {
@@ -68,6 +74,7 @@ struct Args {
   Ctl* ctl;               // control state read by this launch
   Ctl* ctl_out;           // finalize: where the next control state goes (the other buffer)
   unsigned* rflag;        // sticky flag: a vector term left the storage format's range
+  const float* mlp;       // learned proposer weights (BF16 values as FP32), or null
   TraceRec* trace;
   double gain, invN, scale; // coupling gain, 1/N, per-tensor scale of A (power of two)
   double vmax;            // largest magnitude the vector terms may hold (format range check)
@@ -118,6 +125,14 @@ hipError_t launch_contract(const Args& a, int fmt, const Tile& t, hipStream_t s)
 hipError_t launch_group_contract(const Group& g, int m, int fmt, const Tile& t, unsigned grid, hipStream_t s);
 hipError_t launch_group_prep(const Group& g, unsigned grid, hipStream_t s);
 hipError_t launch_group_finalize(const Group& g, unsigned grid, hipStream_t s);
+
+// learned proposer training (bs32_mlp.hip)
+hipError_t launch_mlp_grad(const float* W, const float* X, const float* Y, const int* idx, int nb, float inv_n,
+                           float over_w, float* part, double* loss_part, hipStream_t s);
+hipError_t launch_mlp_reduce(const float* part, int nparts, double* out, hipStream_t s);
+hipError_t launch_mlp_adam(float* master, float* m1, float* m2, float* wq, const float* part, int nparts, float lr,
+                           float beta1, float beta2, float eps, float bc1, float bc2, hipStream_t s);
+hipError_t launch_bf16_copy(const float* src, float* dst, int n_round, int n, hipStream_t s);
 hipError_t launch_to_soa(const double* src, double* dst, long long n, int d, long long np, hipStream_t s);
 hipError_t launch_from_soa(const double* src, double* dst, long long n, int d, long long np, hipStream_t s);
 hipError_t launch_pack_f64(const double* src, double* dst, long long n, long long ld, long long rows, int uniform,

@@ -18,6 +18,7 @@
 #include <algorithm>
 
 #include "bs32_internal.hpp"
+#include "bs32_mlp.hpp"
 
 namespace bs32 {
 
@@ -688,7 +689,8 @@ __device__ double control(const Ctl* c, double h, double E, bool accepted) {
 }
 
 // grid maxima of the evaluation that just finished -> new control state
-__device__ void finalize(const Args& a, Ctl* c, double m0, double m1, bool writer) {
+// returns true when the learned proposer should choose the next step (features in feat)
+__device__ bool finalize(const Args& a, Ctl* c, double m0, double m1, bool writer, float* feat) {
   switch (a.stage) {
     case ST_INIT: {
       c->n_fev += 1;
@@ -726,15 +728,15 @@ __device__ void finalize(const Args& a, Ctl* c, double m0, double m1, bool write
           c->status = 6;  // BS32_NONFINITE
           c->n_reject += 1;
           if (c->trace_on) {
-            if (writer) a.trace[c->trace_n % c->trace_cap] = TraceRec{c->t, ha, E, m1, 0, 0};
+            if (writer) a.trace[c->trace_n % c->trace_cap] = TraceRec{c->t, ha, E, m1, 0, c->prop_cur};
             c->trace_n += 1;
           }
-          return;
+          return false;
         }
         accepted = E < c->rtol;  // accept iff the estimate is smaller than Rel (Sec. 2.2)
       }
       if (c->trace_on) {
-        if (writer) a.trace[c->trace_n % c->trace_cap] = TraceRec{c->t, ha, E, m1, accepted ? 1 : 0, 0};
+        if (writer) a.trace[c->trace_n % c->trace_cap] = TraceRec{c->t, ha, E, m1, accepted ? 1 : 0, c->prop_cur};
         c->trace_n += 1;
       }
       double hn;
@@ -752,20 +754,56 @@ __device__ void finalize(const Args& a, Ctl* c, double m0, double m1, bool write
         c->last_rejected = 1;
       }
       c->h_last = ha;
-      c->h = fmin(hn, c->h_max);
-      if (c->t >= c->t1) {
-        c->status = 0;
-        return;
+      c->h = hn;  // the standard proposal; finalize_step may replace it
+      for (int q = 3; q > 0; --q) {
+        c->hist_h[q] = c->hist_h[q - 1];
+        c->hist_e[q] = c->hist_e[q - 1];
       }
-      // failure conditions of Sec. 2.2 (strict thresholds: reading)
-      if (c->n_accept + c->n_reject > c->i_max) { c->status = 1; return; }
-      if ((double)c->n_reject > 0.85 * (double)c->i_max) { c->status = 2; return; }
-      if (!c->fixed_step && c->h <= c->h_min) { c->status = 3; return; }
-      c->ha = fmin(c->h, c->t1 - c->t);
-      break;
+      c->hist_h[0] = ha;
+      c->hist_e[0] = E;
+      c->nhist += 1;
+      // the learned proposer only after 4 attempts and an accepted step, never at the end
+      const bool want = c->use_mlp && a.mlp != nullptr && accepted && c->nhist >= 4 && !c->fixed_step &&
+                        c->t < c->t1;
+      if (want && feat) {
+        for (int q = 0; q < 4; ++q) {
+          feat[q] = (float)log(c->hist_h[q]);
+          feat[4 + q] = (float)log(fmax(c->hist_e[q], 1e-30 * c->rtol) / c->rtol);
+        }
+        feat[8] = (float)log(fmax(m1, 1e-300));
+      }
+      return want;
     }
     default: break;
   }
+  return false;
+}
+
+// second half of the step-size update, after the optional learned proposal:
+// choose h, clip to h_max, failure conditions of Sec. 2.2, next attempt's step
+__device__ void finalize_step(Ctl* c, bool want, float delta) {
+  double hn = c->h;
+  int prop = 0;
+  if (want && isfinite(delta)) {
+    const double d = (double)delta;
+    const double d_std = log(c->h / c->h_last);  // the classical rule's step ratio
+    if (d >= fmax(kMlpDeltaMin, d_std - kMlpTrust) && d <= fmin(kMlpDeltaMax, d_std + kMlpTrust)) {
+      hn = c->h_last * exp(d);
+      prop = 1;
+      c->n_mlp += 1;
+    }
+  }
+  c->prop_cur = prop;
+  c->h = fmin(hn, c->h_max);
+  if (c->t >= c->t1) {
+    c->status = 0;
+    return;
+  }
+  // failure conditions of Sec. 2.2 (strict thresholds: reading)
+  if (c->n_accept + c->n_reject > c->i_max) { c->status = 1; return; }
+  if ((double)c->n_reject > 0.85 * (double)c->i_max) { c->status = 2; return; }
+  if (!c->fixed_step && c->h <= c->h_min) { c->status = 3; return; }
+  c->ha = fmin(c->h, c->t1 - c->t);
 }
 
 // Every workgroup reduces the block maxima of the last evaluation and derives the
@@ -809,6 +847,8 @@ __device__ __forceinline__ void finalize_block(const Args& a, int blk) {
     sR1[wave] = m1;
   }
   __syncthreads();
+  __shared__ float s_feat[kMlpIn], s_h1[kMlpHid], s_h2[kMlpHid], s_red[1];
+  __shared__ int s_want;
   if (tid == 0) {
     m0 = sR0[0];
     m1 = sR1[0];
@@ -816,11 +856,18 @@ __device__ __forceinline__ void finalize_block(const Args& a, int blk) {
       m0 = nanmax(m0, sR0[w]);
       m1 = nanmax(m1, sR1[w]);
     }
+    s_want = 0;
     if (*a.rflag) c->status = kStatusRange;
-    else finalize(a, c, m0, m1, writer);
+    else s_want = finalize(a, c, m0, m1, writer, s_feat) ? 1 : 0;
     s_next = (a.stage == ST_INIT && !(c->h0user > 0.0)) ? ST_H0 : ST_S2;
   }
   __syncthreads();
+  if (a.stage == ST_S4 && sc.status == kRunning) {
+    // learned proposal (whole workgroup), then the rest of the step-size update
+    const float delta = s_want ? mlp_forward_wg(a.mlp, s_feat, s_h1, s_h2, s_red) : 0.0f;
+    if (tid == 0) finalize_step(c, s_want != 0, delta);
+    __syncthreads();
+  }
   if (writer && tid < kWords) ((unsigned long long*)a.ctl_out)[tid] = ((const unsigned long long*)&sc)[tid];
   if (sc.status != kRunning) return;
   if (i < a.n) {
