@@ -1,9 +1,10 @@
 #!/usr/bin/env python3
-"""Benchmark of the gfx950 BS3(2) hot path on the Kuramoto network N = 4096.
+"""Benchmark of the gfx950 BS3(2) hot path.
 
-Workload (paper Benchmark 2 with dense weights): theta_i' = w_i + (K/N) sum_j
-A_ij sin(theta_j - theta_i), A ~ U[0,1) with zero diagonal, w ~ N(0,1),
-theta0 ~ U[0,2pi), K = 2, t in [0, 50], rtol = atol = 1e-6, seed 2000.
+Default workload (--config c2), the Kuramoto network N = 4096 (paper Benchmark 2
+with dense weights): theta_i' = w_i + (K/N) sum_j A_ij sin(theta_j - theta_i),
+A ~ U[0,1) with zero diagonal, w ~ N(0,1), theta0 ~ U[0,2pi), K = 2,
+t in [0, 50], rtol = atol = 1e-6, seed 2000.
 
 One "step" is one complete solve t0 -> t_end (every stage of the method:
 vector operand, N^2 contractions, stage combinations, FSAL, error norm,
@@ -13,16 +14,30 @@ one (i, j) term of one right-hand-side evaluation (n_fev * N^2 per solve).
 
 Also reported: time-to-t_end of each precision mode next to plain FP64, the
 normalized final error ||y - y_ref||_2 / sqrt(N) (paper eq. (Metric)) against an
-FP64 reference at rtol = 1e-12, the roofline of the contraction kernel
+FP64 reference at a tight tolerance, the roofline of the contraction kernel
 (algorithmic bytes N^2 * bytes(A) per launch over its event-timed mean
-duration), and the CPU oracle timed on a bounded sample.
+duration, and the HBM traffic the PMC counters measured for the same kernel
+when the committed summary matches the kernel sources), and the CPU oracle
+timed on a bounded sample.
+
+Other measurement configurations, one JSON line each:
+  c3  Goodwin clock network N = 16384 (state 49152), t in [0, 500],
+      rtol = atol = 1e-6, coupling stored FP64 / FP32 / BF16 / FP16 / FP8-e4m3.
+  c4  ensemble of 512 Kuramoto instances, N log-uniform in [256, 8192],
+      K ~ U[0.5, 4), t in [0, 50], rtol = atol = 1e-6, BF16 contraction vs FP64.
+  c5  learned step-size proposer trained on solver traces of the c1-c3 laws,
+      run on Kuramoto N = 32768 (t in [0, 50]) and coupled oscillators
+      N = 32768 (t in [0, 10]), FP64 coupling, rtol = atol = 1e-7, against the
+      standard controller.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -31,6 +46,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES = {0: 8, 1: 4, 2: 2, 3: 2, 4: 1}
+DTYPE = {0: "f64", 1: "f32", 2: "bf16", 3: "f16", 4: "fp8e4m3"}
+METRIC = "pair-interactions/s + time-to-t_end vs plain FP64 GPU at matched final error"
+KERNEL_SOURCES = ("bs32_kernels.hip", "bs32_internal.hpp", "bs32_mlp.hpp")
 
 
 def log(msg):
@@ -42,54 +60,140 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=4096)
-    ap.add_argument("--rtol", type=float, default=1e-6)
-    ap.add_argument("--t1", type=float, default=50.0)
-    ap.add_argument("--modes", default="0,1,2,3,4", help="comma-separated precision modes to compare with FP64")
+    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--n", type=int, default=None, help="agents (single-system configs)")
+    ap.add_argument("--rtol", type=float, default=None)
+    ap.add_argument("--t1", type=float, default=None)
+    ap.add_argument("--modes", default=None, help="comma-separated precision modes to compare with FP64")
     ap.add_argument("--head", type=int, default=None, help="force the headline precision mode")
+    ap.add_argument("--ref-rtol", type=float, default=None, help="tolerance of the FP64 reference solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-ref", action="store_true", help="skip the rtol=1e-12 reference solution")
+    ap.add_argument("--no-ref", action="store_true", help="skip the reference solution")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calib-copy", type=int, default=0,
+                    help="MiB of a plain device copy run first (calibrates PMC byte counters)")
+    ap.add_argument("--instances", type=int, default=512, help="c4: ensemble size")
+    ap.add_argument("--no-graph", action="store_true", help="launch attempts directly instead of from HIP graphs")
     return ap.parse_args()
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the path would shard rows of A with one all-gather per stage).", file=sys.stderr)
-        sys.exit(2)
-    import numpy as np
-    import torch
+def sources_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2605_23727_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
-    import paper_2605_23727_amd as bs
-    import workloads
+
+def traffic_lookup(workload, mode_name, kernel):
+    """HBM bytes per launch of the contraction kernel from the committed PMC summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when the summary has
+    no row for this kernel instance or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernel sources sha256: ([0-9a-f]+)", text)
+    if not m or m.group(1) != sources_hash():
+        return None
+    for line in text.splitlines():
+        cells = [c.strip().strip("`") for c in line.strip().strip("|").split("|")]
+        if len(cells) == 7 and cells[0] == mode_name and cells[1] == kernel:
+            try:
+                return float(cells[6])
+            except ValueError:
+                return None
+    return None
+
+
+def calib_copy(torch, dev, mib):
+    if mib <= 0:
+        return
+    src = torch.ones(mib * (1 << 20) // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"calibration copy of {mib} MiB done")
+    del src, dst
+
+
+def cpu_baseline(w, seconds):
+    """The oracle as it stands, timed on this host's cores on a bounded sample of the
+    same workload: the first attempts of the same solve, sized to ~`seconds`."""
+    import numpy as np
+    import oracle
+
+    def host(x):
+        return x.cpu().numpy() if hasattr(x, "cpu") else np.asarray(x)
+
+    n = w["n"]
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+    kw = dict(A=host(w["A"]), param=host(w["param"]), gain=w["gain"])
+    y0 = host(w["y0"])
+    t0 = time.perf_counter()
+    _, st, _ = oracle.bs32_solve(w["kind"], n, y0, 0.0, w["t1"], w["rtol"], w["atol"], i_max=2, **kw)
+    dt = time.perf_counter() - t0
+    per_fev = dt / max(1, st["n_fev"])
+    attempts = max(2, int(seconds / per_fev / 3.0))
+    t0 = time.perf_counter()
+    _, st, _ = oracle.bs32_solve(w["kind"], n, y0, 0.0, w["t1"], w["rtol"], w["atol"], i_max=attempts, **kw)
+    dt = time.perf_counter() - t0
+    pairs = st["n_fev"] * float(n) * n
+    return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": min(threads, cores), "kind": "oracle",
+            "sample": f"first {st['n_accept'] + st['n_reject']} attempts ({st['n_fev']} RHS evaluations, "
+                      f"t reached {st['t_reached']:.3g} of {w['t1']:g}) of the same solve, {dt:.1f} s",
+            "seconds": dt}
+
+
+def base_line(args, value, ms_per_step, dtype, config):
+    return {"metric": METRIC, "value": value, "unit": "pair-interactions/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+def roofline(kms, bytes_per_launch, kernel, traffic):
+    gbs = bytes_per_launch / (kms * 1e-3) / 1e9
+    return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4),
+                traffic=traffic, kernel=kernel, bytes_per_launch=bytes_per_launch, avg_launch_ms=kms)
+
+
+# ---------------------------------------------------------------------------
+# single-system configurations (c2, c3)
+# ---------------------------------------------------------------------------
+def bench_single(args, torch, bs, workload, w, modes, ref_rtol):
+    import numpy as np
 
     dev = torch.device("cuda:0")
-    w = workloads.kuramoto(args.n, seed=2000, K=2.0, t1=args.t1, rtol=args.rtol)
     n = w["n"]
-    A = torch.from_numpy(w["A"]).to(dev)
-    om = torch.from_numpy(w["param"]).to(dev)
-    y0 = torch.from_numpy(w["y0"]).to(dev)
+    t1, rtol = w["t1"], w["rtol"]
+    y0 = w["y0"].to(dev) if hasattr(w["y0"], "to") else torch.from_numpy(w["y0"]).to(dev)
     out = torch.empty_like(y0)
 
+    def dev_t(x):
+        return x.to(dev) if hasattr(x, "to") else torch.from_numpy(x).to(dev)
+
     s = bs.Solver(0)
+    if args.no_graph:
+        s.set_options(use_graph=0)
+    A = dev_t(w["A"])
     torch.cuda.synchronize()
     t_setup = time.perf_counter()
-    s.set_system(w["kind"], n, A, om, w["gain"])
+    s.set_system(w["kind"], n, A, dev_t(w["param"]), w["gain"])
     torch.cuda.synchronize()
     setup_ms = (time.perf_counter() - t_setup) * 1e3
     del A
 
-    modes = [int(m) for m in args.modes.split(",") if m != ""]
-
-    # reference solution (FP64 GPU path at rtol = atol = 1e-12; parity-checked against the oracle)
     ref = None
     if not args.no_ref:
-        log(f"reference solve (FP64, rtol=1e-12) n={n}")
+        log(f"reference solve (FP64, rtol={ref_rtol:g}) n={n}")
         s.set_options(i_max=10_000_000)
         ref_t = torch.empty_like(y0)
-        _, rst = s.solve(y0, 0.0, args.t1, 1e-12, 1e-12, mode=bs.PREC_FP64, out=ref_t)
+        _, rst = s.solve(y0, 0.0, t1, ref_rtol, ref_rtol, mode=bs.PREC_FP64, out=ref_t)
         s.set_options(i_max=100000)
         ref = ref_t.cpu().numpy()
         log(f"  reference: {rst['n_accept']} accepted, {rst['solve_ms'] / 1e3:.1f} s, status {rst['status']}")
@@ -101,13 +205,13 @@ def main():
     for mode in sorted(set([0] + modes)):
         log(f"mode {bs.MODE_NAMES[mode]}: {args.warmup} warm-up + {args.steps} timed solves")
         for _ in range(args.warmup):
-            s.solve(y0, 0.0, args.t1, args.rtol, mode=mode, out=out)
+            s.solve(y0, 0.0, t1, rtol, mode=mode, out=out)
         torch.cuda.synchronize()
         times, pairs, stats = [], 0.0, None
         for _ in range(args.steps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            _, stats = s.solve(y0, 0.0, args.t1, args.rtol, mode=mode, out=out)
+            _, stats = s.solve(y0, 0.0, t1, rtol, mode=mode, out=out)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
             pairs += stats["pair_interactions"]
@@ -119,7 +223,9 @@ def main():
             pairs_per_s=pairs / sum(times), accepted=int(stats["n_accept"]), rejected=int(stats["n_reject"]),
             n_fev=int(stats["n_fev"]), accepted_steps_per_s=stats["n_accept"] / float(np.median(times)),
             final_error=final_err(y), status=int(stats["status"]), contraction_ms=kms, contraction_gbs=gbs,
-            kernel_ms=stats["kernel_ms"])
+            kernel_ms=stats["kernel_ms"], tile=int(stats["tile"]), kernel=s.kernel_name(mode, stats["tile"]))
+        log(f"  {results[mode]['time_to_t_end_s'] * 1e3:.2f} ms, error {results[mode]['final_error']}, "
+            f"contraction {kms * 1e3:.2f} us ({gbs:.0f} GB/s), tile {stats['tile']}")
 
     r0 = results[0]
     # headline: the fastest mode whose final error stays within 2x plain FP64's
@@ -131,75 +237,297 @@ def main():
             r0["final_error"] is None or r["final_error"] is None or r["final_error"] <= 2.0 * r0["final_error"])]
         head = min(ok, key=lambda m: results[m]["time_to_t_end_s"]) if ok else 0
     rh = results[head]
-    roof = dict(bound="hbm", achieved=round(rh["contraction_gbs"], 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(rh["contraction_gbs"] / HBM_PEAK_GBS, 4), traffic=None,
-                kernel=f"contraction ({rh['name']})", bytes_per_launch=n * n * BYTES[min(head, 4)],
-                avg_launch_ms=rh["contraction_ms"])
+    traffic = traffic_lookup(workload, rh["name"], rh["kernel"])
+    roof = roofline(rh["contraction_ms"], n * n * BYTES[min(head, 4)], rh["kernel"], traffic)
 
     cpu = None
     if not args.no_cpu:
         log(f"CPU oracle baseline (~{args.cpu_seconds:g} s)")
         cpu = cpu_baseline(w, args.cpu_seconds)
 
-    line = {
-        "metric": "pair-interactions/s + time-to-t_end vs plain FP64 GPU at matched final error",
-        "value": rh["pairs_per_s"],
-        "unit": "pair-interactions/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": rh["ms_per_step"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": {0: "f64", 1: "f32", 2: "bf16", 3: "f16", 4: "fp8e4m3"}[min(head, 4)] + "+f64-update",
-        "data": "synthetic",
-        "config": {"workload": f"kuramoto-dense N={n} K=2 t=[0,{args.t1:g}] rtol=atol={args.rtol:g} seed=2000",
-                   "precision_mode": rh["name"], "global_batch": 1, "seq_len": None},
+    line = base_line(args, rh["pairs_per_s"], rh["ms_per_step"], DTYPE[min(head, 4)] + "+f64-update",
+                     {"workload": workload_desc(workload, w), "precision_mode": rh["name"], "global_batch": 1,
+                      "seq_len": None})
+    line.update({
         "time_to_t_end_s": rh["time_to_t_end_s"],
         "fp64_time_to_t_end_s": r0["time_to_t_end_s"],
         "speedup_vs_fp64": r0["time_to_t_end_s"] / rh["time_to_t_end_s"],
         "final_error": rh["final_error"],
         "fp64_final_error": r0["final_error"],
+        "reference_rtol": None if ref is None else ref_rtol,
         "matched_error": (None if rh["final_error"] is None else rh["final_error"] <= 2.0 * r0["final_error"]),
         "accepted_steps_per_s": rh["accepted_steps_per_s"],
         "beta": (r0["accepted"] + r0["rejected"]) / max(1, rh["accepted"] + rh["rejected"]),
         "setup_ms": setup_ms,
-        "modes": {v["name"]: {k: v[k] for k in ("time_to_t_end_s", "pairs_per_s", "accepted", "rejected",
-                                                 "final_error", "contraction_ms", "contraction_gbs", "status")}
+        "modes": {v["name"]: {k: v[k] for k in ("time_to_t_end_s", "pairs_per_s", "accepted", "rejected", "n_fev",
+                                                 "final_error", "contraction_ms", "contraction_gbs", "tile", "kernel",
+                                                 "status")}
                   for v in results.values()},
         "roofline": roof,
         "cpu_baseline": cpu,
-    }
-    print(json.dumps(line), flush=True)
+    })
+    s.close()
+    return line
 
 
-def cpu_baseline(w, seconds):
-    """The oracle as it stands, timed on this host's cores on a bounded sample of the
-    same workload: the first attempts of the same solve, sized to ~`seconds`."""
+def workload_desc(workload, w):
+    if w["kind"] == 3:
+        return f"kuramoto-dense N={w['n']} K={w['gain']:g} t=[0,{w['t1']:g}] rtol=atol={w['rtol']:g} seed={w['seed']}"
+    if w["kind"] == 4:
+        return (f"goodwin3-dense N={w['n']} kappa={w['gain']:g} t=[0,{w['t1']:g}] rtol=atol={w['rtol']:g} "
+                f"seed={w['seed']}")
+    return f"{workload} N={w['n']} t=[0,{w['t1']:g}] rtol=atol={w['rtol']:g} seed={w['seed']}"
+
+
+# ---------------------------------------------------------------------------
+# c4: batched ensemble
+# ---------------------------------------------------------------------------
+def bench_ensemble(args, torch, bs, modes, ref_rtol):
     import numpy as np
-    import oracle
+    import workloads
 
-    n = w["n"]
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count()
-    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
-    kw = dict(A=w["A"], param=w["param"], gain=w["gain"])
-    t0 = time.perf_counter()
-    _, st, _ = oracle.bs32_solve(w["kind"], n, w["y0"], 0.0, w["t1"], w["rtol"], w["atol"], i_max=2, **kw)
-    dt = time.perf_counter() - t0
-    per_fev = dt / max(1, st["n_fev"])
-    attempts = max(2, int(seconds / per_fev / 3.0))
-    t0 = time.perf_counter()
-    _, st, _ = oracle.bs32_solve(w["kind"], n, w["y0"], 0.0, w["t1"], w["rtol"], w["atol"], i_max=attempts, **kw)
-    dt = time.perf_counter() - t0
-    pairs = st["n_fev"] * float(n) * n
-    return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": min(threads, cores), "kind": "oracle",
-            "sample": f"first {st['n_accept'] + st['n_reject']} attempts ({st['n_fev']} RHS evaluations, "
-                      f"t reached {st['t_reached']:.3g} of {w['t1']:g}) of the same solve, {dt:.1f} s",
-            "seconds": dt}
+    B = args.instances
+    rtol = args.rtol or 1e-6
+    t1 = args.t1 or 50.0
+    ns, ks = workloads.ensemble_sizes(B, seed=4000)
+    pairs_total = float(np.sum(ns.astype(np.float64) ** 2))
+    log(f"ensemble: {B} instances, sum N^2 = {pairs_total:.3e}, drawing on the device")
+    members = [workloads.kuramoto_device(int(n), seed=4001 + b, K=float(k), t1=t1, rtol=rtol)
+               for b, (n, k) in enumerate(zip(ns, ks))]
+    # stratified subset (by N) checked against a tight-tolerance FP64 reference
+    order = np.argsort(ns, kind="stable")
+    subset = sorted(int(order[q]) for q in np.linspace(0, B - 1, min(B, 32)).round().astype(int))
+    y0 = torch.cat([m["y0"] for m in members]).contiguous()
+    offs = np.concatenate([[0], np.cumsum(ns)])
+    s = bs.Solver(0)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter()
+    s.set_ensemble(members)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t_setup) * 1e3
+    keep = {b: members[b] for b in subset}
+    for b, m in enumerate(members):
+        if b not in keep:
+            m["A"] = None
+    del members
+    torch.cuda.empty_cache()
+    out = torch.empty_like(y0)
+
+    results = {}
+    for mode in sorted(set([0] + modes)):
+        log(f"mode {bs.MODE_NAMES[mode]}: {args.warmup} warm-up + {args.steps} timed batch solves")
+        for _ in range(args.warmup):
+            s.solve_batch(y0, 0.0, t1, rtol, mode=mode, out=out)
+        times, pairs, tot = [], 0.0, None
+        for _ in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st, tot = s.solve_batch(y0, 0.0, t1, rtol, mode=mode, out=out)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            pairs += tot["pair_interactions"]
+        kms = s.time_contraction(mode, repeat=10)
+        y = out.cpu().numpy()
+        results[mode] = dict(name=bs.MODE_NAMES[mode], time_to_t_end_s=float(np.median(times)),
+                             ms_per_step=1e3 * sum(times) / len(times), pairs_per_s=pairs / sum(times),
+                             accepted=int(tot["n_accept"]), rejected=int(tot["n_reject"]), n_fev=int(tot["n_fev"]),
+                             failed=int(np.sum(st != 0)), contraction_ms=kms,
+                             contraction_gbs=pairs_total * BYTES[min(mode, 4)] / (kms * 1e-3) / 1e9,
+                             tile=int(tot["tile"]), kernel=s.kernel_name(mode, tot["tile"]), y=y)
+        log(f"  {results[mode]['time_to_t_end_s']:.3f} s, {results[mode]['pairs_per_s']:.3e} pairs/s, "
+            f"grouped contraction {kms:.3f} ms ({results[mode]['contraction_gbs']:.0f} GB/s)")
+
+    errs = None
+    if not args.no_ref:
+        log(f"reference: FP64 batch of the {len(subset)}-instance subset at rtol {ref_rtol:g}")
+        r = bs.Solver(0)
+        r.set_options(i_max=10_000_000)
+        r.set_ensemble([keep[b] for b in subset])
+        ysub = torch.cat([keep[b]["y0"] for b in subset]).contiguous()
+        yr, st, _ = r.solve_batch(ysub, 0.0, t1, ref_rtol, mode=bs.PREC_FP64)
+        r.close()
+        errs = {}
+        for mode, res in results.items():
+            e, off = [], 0
+            for q, b in enumerate(subset):
+                n = int(ns[b])
+                e.append(float(np.linalg.norm(res["y"][offs[b]:offs[b] + n] - yr[off:off + n]) / math.sqrt(n)))
+                off += n
+            errs[mode] = np.array(e)
+    head = args.head if args.head is not None else 2
+    rh, r0 = results[head], results[0]
+    ratio = None if errs is None else errs[head] / np.maximum(errs[0], 1e-300)
+    roof = roofline(rh["contraction_ms"], pairs_total * BYTES[min(head, 4)],
+                    rh["kernel"].replace("k_contract_", "k_group_") + f" over {B} instances",
+                    traffic_lookup(f"kuramoto_ensemble{B}", rh["name"], rh["kernel"].replace("k_contract_", "k_group_")))
+    line = base_line(args, rh["pairs_per_s"], rh["ms_per_step"], DTYPE[min(head, 4)] + "+f64-update",
+                     {"workload": f"kuramoto-ensemble B={B} N=logU[256,8192] K=U[0.5,4) t=[0,{t1:g}] "
+                                  f"rtol=atol={rtol:g} seed=4000", "precision_mode": rh["name"],
+                      "global_batch": B, "seq_len": None})
+    line.update({
+        "time_to_t_end_s": rh["time_to_t_end_s"],
+        "fp64_time_to_t_end_s": r0["time_to_t_end_s"],
+        "speedup_vs_fp64": r0["time_to_t_end_s"] / rh["time_to_t_end_s"],
+        "sum_N2": pairs_total,
+        "failed_instances": rh["failed"],
+        "error_subset": subset if errs is not None else None,
+        "final_error_median": None if errs is None else float(np.median(errs[head])),
+        "fp64_final_error_median": None if errs is None else float(np.median(errs[0])),
+        "error_ratio_vs_fp64_median": None if ratio is None else float(np.median(ratio)),
+        "error_ratio_vs_fp64_max": None if ratio is None else float(np.max(ratio)),
+        "matched_error_fraction": None if ratio is None else float(np.mean(ratio <= 2.0)),
+        "reference_rtol": None if errs is None else ref_rtol,
+        "setup_ms": setup_ms,
+        "modes": {v["name"]: {k: v[k] for k in ("time_to_t_end_s", "pairs_per_s", "accepted", "rejected", "n_fev",
+                                                 "failed", "contraction_ms", "contraction_gbs", "tile", "kernel")}
+                  for v in results.values()},
+        "roofline": roof,
+        "cpu_baseline": None,
+    })
+    s.close()
+    return line
+
+
+# ---------------------------------------------------------------------------
+# c5: learned step-size proposer
+# ---------------------------------------------------------------------------
+def training_set(bs, workloads, log_fn):
+    """Traces of the c1-c3 laws (several seeds, tolerances and controller safety
+    factors, so that the features cover steps above and below the classical choice)."""
+    import numpy as np
+
+    laws = [("osc2", lambda sd: workloads.osc2(256, seed=sd, t1=10.0)),
+            ("kuramoto", lambda sd: workloads.kuramoto(1024, seed=sd, t1=50.0)),
+            ("goodwin3", lambda sd: workloads.goodwin3(1024, seed=sd, t1=500.0))]
+    s = bs.Solver(0)
+    F, Y = [], []
+    for name, make in laws:
+        for sd in (11, 12, 13):
+            w = make(sd)
+            s.set_workload(w)
+            for rtol in (1e-5, 1e-6, 1e-7, 1e-8):
+                for safety in (0.9, 0.75, 0.97):
+                    s.set_options(trace=1, trace_cap=1 << 20, safety=safety)
+                    s.solve(w["y0"], 0.0, w["t1"], rtol)
+                    f, y = bs.mlp_features(s.trace(), rtol)
+                    F.append(f)
+                    Y.append(y)
+        log_fn(f"traces of the {name} law: {sum(len(f) for f in F)} samples so far")
+    s.close()
+    return np.concatenate(F), np.concatenate(Y)
+
+
+def bench_learned(args, torch, bs, ref_rtol):
+    import numpy as np
+    import workloads
+
+    t_train = time.perf_counter()
+    F, Y = training_set(bs, workloads, log)
+    s = bs.Solver(0)
+    W, losses = s.mlp_train(F, Y, epochs=60, batch=256, lr=1e-3, seed=0)
+    train_s = time.perf_counter() - t_train
+    log(f"trained on {len(F)} samples: loss {losses[0]:.3g} -> {losses[-1]:.3g} ({train_s:.1f} s with traces)")
+    n = args.n or 32768
+    rtol = args.rtol or 1e-7
+    systems = [("kuramoto", workloads.kuramoto_device(n, seed=5000, t1=50.0, rtol=rtol)),
+               ("osc2", workloads.osc2_device(n, seed=5001, t1=10.0, rtol=rtol))]
+    per = {}
+    for name, w in systems:
+        s.set_system(w["kind"], n, w["A"], w["param"], w["gain"])
+        w["A"] = None
+        torch.cuda.empty_cache()
+        y0 = w["y0"]
+        out = torch.empty_like(y0)
+        ref = None
+        if not args.no_ref:
+            log(f"{name}: reference FP64 rtol {ref_rtol:g}")
+            s.set_controller(0)
+            s.set_options(i_max=10_000_000)
+            yr, _ = s.solve(y0, 0.0, w["t1"], ref_rtol)
+            s.set_options(i_max=100000)
+            ref = yr
+        res = {}
+        for ctl in (0, 1):
+            if ctl:
+                s.set_controller(1, W)
+            else:
+                s.set_controller(0)
+            for _ in range(args.warmup):
+                s.solve(y0, 0.0, w["t1"], rtol, out=out)
+            times, pairs, st = [], 0.0, None
+            for _ in range(args.steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, st = s.solve(y0, 0.0, w["t1"], rtol, out=out)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+                pairs += st["pair_interactions"]
+            y = out.cpu().numpy()
+            res[ctl] = dict(time_to_t_end_s=float(np.median(times)), ms_per_step=1e3 * sum(times) / len(times),
+                            pairs_per_s=pairs / sum(times), n_fev=int(st["n_fev"]), accepted=int(st["n_accept"]),
+                            rejected=int(st["n_reject"]), learned_steps=int(st["n_learned"]), status=int(st["status"]),
+                            final_error=None if ref is None else float(np.linalg.norm(y - ref) / math.sqrt(y.size)))
+            log(f"  {name} controller {'learned' if ctl else 'standard'}: {res[ctl]['time_to_t_end_s']:.3f} s, "
+                f"{res[ctl]['n_fev']} RHS, {res[ctl]['rejected']} rejected, {res[ctl]['learned_steps']} learned, "
+                f"error {res[ctl]['final_error']}")
+        s.set_controller(0)
+        kms = s.time_contraction(0, repeat=20)
+        kname = s.kernel_name(0, st["tile"])
+        per[name] = dict(standard=res[0], learned=res[1], contraction_ms=kms, kernel=kname,
+                         speedup_vs_standard=res[0]["time_to_t_end_s"] / res[1]["time_to_t_end_s"],
+                         rhs_ratio=res[1]["n_fev"] / res[0]["n_fev"])
+    s.close()
+    k = per["kuramoto"]
+    line = base_line(args, k["learned"]["pairs_per_s"], k["learned"]["ms_per_step"], "f64",
+                     {"workload": f"kuramoto-dense N={n} K=2 t=[0,50] and osc2 N={n} t=[0,10], rtol=atol={rtol:g}, "
+                                  f"learned proposer vs standard controller", "precision_mode": "fp64",
+                      "global_batch": 1, "seq_len": None})
+    line.update({
+        "time_to_t_end_s": k["learned"]["time_to_t_end_s"],
+        "standard_time_to_t_end_s": k["standard"]["time_to_t_end_s"],
+        "speedup_vs_standard": k["speedup_vs_standard"],
+        "systems": per,
+        "training": {"samples": int(len(F)), "epochs": 60, "batch": 256, "lr": 1e-3,
+                     "loss_first": float(losses[0]), "loss_last": float(losses[-1]), "seconds": train_s},
+        "reference_rtol": None if args.no_ref else ref_rtol,
+        "roofline": roofline(k["contraction_ms"], n * n * 8, k["kernel"],
+                             traffic_lookup(f"kuramoto_n{n}", "fp64", k["kernel"])),
+        "cpu_baseline": None,
+    })
+    return line
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the path would shard rows of A with one all-gather per stage).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2605_23727_amd as bs
+    import workloads
+
+    dev = torch.device("cuda:0")
+    calib_copy(torch, dev, args.calib_copy)
+    modes = None if args.modes is None else [int(m) for m in args.modes.split(",") if m != ""]
+    if args.config == "c2":
+        n = args.n or 4096
+        w = workloads.kuramoto(n, seed=2000, K=2.0, t1=args.t1 or 50.0, rtol=args.rtol or 1e-6)
+        w["seed"] = 2000
+        line = bench_single(args, torch, bs, f"kuramoto_n{n}", w, modes if modes is not None else [0, 1, 2, 3, 4],
+                            args.ref_rtol or 1e-12)
+    elif args.config == "c3":
+        n = args.n or 16384
+        w = workloads.goodwin3_device(n, seed=3000, t1=args.t1 or 500.0, rtol=args.rtol or 1e-6)
+        w["seed"] = 3000
+        line = bench_single(args, torch, bs, f"goodwin3_n{n}", w, modes if modes is not None else [0, 1, 2, 3, 4],
+                            args.ref_rtol or 1e-9)
+    elif args.config == "c4":
+        line = bench_ensemble(args, torch, bs, modes if modes is not None else [0, 2], args.ref_rtol or 1e-9)
+    else:
+        line = bench_learned(args, torch, bs, args.ref_rtol or 1e-10)
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

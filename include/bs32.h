@@ -96,6 +96,9 @@ typedef struct {
   double kernel_ms;                  /* device time between the first and last kernel of the solve */
   int32_t status;                    /* bs32_status of the last solve */
   int32_t mode;                      /* precision mode of the last solve */
+  int64_t n_learned;                 /* steps whose size the learned proposer chose */
+  int32_t tile;                      /* contraction tile used (index as in options.tile) */
+  int32_t reserved;
 } bs32_stats_t;
 
 typedef struct {
@@ -149,9 +152,17 @@ bs32_status bs32_rhs(bs32_ctx* ctx, const double* y, int precision_mode, int rep
 /* Time the N^2 contraction kernel of one stage evaluation (the hot kernel of
    eq. (Stage-ODE23)) in a precision mode, at the launch configuration bs32_solve
    uses: `repeat` back-to-back launches between two HIP events on the context's
-   stream; *avg_ms receives the mean duration of one launch.  Overwrites the
-   context's stage buffers (call between solves). */
+   stream; *avg_ms receives the mean duration of one launch.  With an ensemble
+   set, times the grouped launch over every instance.  Overwrites the context's
+   stage buffers (call between solves). */
 bs32_status bs32_time_contraction(bs32_ctx* ctx, int precision_mode, int repeat, double* avg_ms);
+
+/* Name of the contraction kernel instance that precision_mode (0-4) runs with
+   candidate tile `tile` (the index options.tile and bs32_stats_t.tile use) on the
+   context's system or ensemble, as profilers list it without namespace and
+   parameter list, e.g. "k_contract_f64<2, 2, 1, 4, 2, false>"; NUL-terminated
+   into buf (cap bytes).  For matching profiler output to a solve. */
+bs32_status bs32_kernel_name(bs32_ctx* ctx, int precision_mode, int tile, char* buf, size_t cap);
 
 /* Copy the coupling matrix as stored for a precision mode (packing it first if
    needed): N rows of N elements of the storage format (8, 4, 2, 2, 1 bytes for

@@ -42,7 +42,8 @@ class Stats(C.Structure):
     _fields_ = [("n_accept", C.c_int64), ("n_reject", C.c_int64), ("n_fev", C.c_int64),
                 ("pair_interactions", C.c_double), ("t_reached", C.c_double), ("h_last", C.c_double),
                 ("h_min_seen", C.c_double), ("err_last", C.c_double), ("solve_ms", C.c_double),
-                ("kernel_ms", C.c_double), ("status", C.c_int32), ("mode", C.c_int32)]
+                ("kernel_ms", C.c_double), ("status", C.c_int32), ("mode", C.c_int32),
+                ("n_learned", C.c_int64), ("tile", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -81,6 +82,7 @@ _SIGS = {
     "bs32_rhs": ([C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p], C.c_int),
     "bs32_get_trace": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "bs32_time_contraction": ([C.c_void_p, C.c_int, C.c_int, C.c_void_p], C.c_int),
+    "bs32_kernel_name": ([C.c_void_p, C.c_int, C.c_int, C.c_char_p, C.c_size_t], C.c_int),
     "bs32_get_packed_coupling": ([C.c_void_p, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "bs32_set_ensemble": ([C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
     "bs32_solve_batch": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_int,
@@ -100,6 +102,14 @@ def lib():
     """Load libbs32.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # One HIP runtime per process: torch ships its own libamdhip64 under the same
+        # soname as ROCm's.  Loaded first, it satisfies the library's dependency, so
+        # device pointers and streams are shared with torch; loaded after the library,
+        # it would bring a second HIP/HSA runtime that then finds no GPU.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2605_23727_amd.build`")
         L = C.CDLL(LIB_PATH)
@@ -304,6 +314,12 @@ class Solver:
         s = Stats()
         self._check(lib().bs32_batch_stats(self._ctx, int(instance), C.byref(s)))
         return s.as_dict()
+
+    def kernel_name(self, mode, tile):
+        """Contraction kernel instance of a precision mode and candidate tile (profiler naming)."""
+        buf = C.create_string_buffer(256)
+        self._check(lib().bs32_kernel_name(self._ctx, int(mode), int(tile), buf, 256))
+        return buf.value.decode()
 
     def packed_coupling(self, mode):
         """(stored N x N matrix as raw format values, power-of-two scale) for a precision mode."""

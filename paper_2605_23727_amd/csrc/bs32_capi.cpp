@@ -358,6 +358,14 @@ bs32_status autotune(bs32_ctx* c, int fmt) {
   return BS32_OK;
 }
 
+// index of a tile in the format's candidate list (the value options.tile takes)
+int tile_index(int fmt, const Tile& t) {
+  const std::vector<Tile> cand = candidates(fmt);
+  for (size_t q = 0; q < cand.size(); ++q)
+    if (std::memcmp(&cand[q], &t, sizeof(Tile)) == 0) return (int)q;
+  return -1;
+}
+
 // picks the tile: explicit option index into the candidate list, else the autotuned one
 bs32_status prepare(bs32_ctx* c, int mode, Geom* g, int* fmt) {
   if (!c->has_sys) return fail(c, BS32_ESTATE, "no system set");
@@ -429,6 +437,9 @@ bs32_status run_chunk(bs32_ctx* c, int fmt, const Geom& g, int attempts) {
   HIPCHK(c, hipGraphLaunch(it->second, c->stream));
   return BS32_OK;
 }
+
+bs32_status ens_time_contraction(bs32_ctx* c, int mode, int repeat, double* avg_ms);  // bs32_ensemble.inc
+int ens_vcols(const bs32_ctx* c);                                                     // bs32_ensemble.inc
 
 }  // namespace
 
@@ -611,6 +622,7 @@ bs32_status bs32_time_contraction(bs32_ctx* c, int mode, int repeat, double* avg
   if (!c || !avg_ms) return fail(c, BS32_EINVAL, "null argument");
   if (repeat < 1) return fail(c, BS32_EINVAL, "repeat must be >= 1");
   HIPCHK(c, hipSetDevice(c->device));
+  if (c->ens) return ens_time_contraction(c, mode, repeat, avg_ms);
   Geom g;
   int fmt;
   bs32_status s = prepare(c, mode, &g, &fmt);
@@ -627,6 +639,22 @@ bs32_status bs32_time_contraction(bs32_ctx* c, int mode, int repeat, double* avg
   float ms = 0.f;
   HIPCHK(c, hipEventElapsedTime(&ms, c->ev_start, c->ev_stop));
   *avg_ms = (double)ms / repeat;
+  return BS32_OK;
+}
+
+bs32_status bs32_kernel_name(bs32_ctx* c, int mode, int tile, char* buf, size_t cap) {
+  if (!c || !buf || cap == 0) return fail(c, BS32_EINVAL, "null argument");
+  if (mode < 0 || mode >= BS32_PREC_PAPER_SINGLE) return fail(c, BS32_EINVAL, "mode %d has no contraction tiles", mode);
+  int m = 0;
+  if (c->has_sys) m = c->m;
+  else if (c->ens) m = ens_vcols(c);
+  else return fail(c, BS32_ESTATE, "no system set");
+  const int fmt = mode_fmt(mode);
+  const std::vector<Tile> cand = candidates(fmt);
+  if (tile < 0 || tile >= (int)cand.size()) return fail(c, BS32_EINVAL, "tile index %d out of range", tile);
+  const int r = kernel_name(fmt, m, cand[(size_t)tile], buf, cap);
+  if (r < 0) return fail(c, BS32_EUNSUPPORTED, "tile %d is not instantiated for this system", tile);
+  if ((size_t)r >= cap) return fail(c, BS32_EINVAL, "buffer too small");
   return BS32_OK;
 }
 
@@ -777,6 +805,8 @@ bs32_status bs32_solve(bs32_ctx* c, const double* y0, double t0, double t1, doub
   c->st.h_last = fin.h_last;
   c->st.h_min_seen = fin.h_min_seen;
   c->st.err_last = fin.err;
+  c->st.n_learned = fin.n_mlp;
+  c->st.tile = tile_index(fmt, g.t);
   c->st.kernel_ms = kms;
   c->st.status = fin.status;
   c->st.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();

@@ -118,6 +118,8 @@ size_t fmt_bytes(int fmt);
 int tile_rows(int fmt, const Tile& t);
 int tile_kalign(int fmt, const Tile& t);
 bool tile_supported(int fmt, int m, const Tile& t);
+// name of the contraction kernel instance (as profilers list it); < 0 if unsupported
+int kernel_name(int fmt, int m, const Tile& t, char* buf, size_t cap);
 hipError_t launch_prep(const Args& a, hipStream_t s);
 hipError_t launch_finalize(const Args& a, hipStream_t s);
 hipError_t launch_set_status(Ctl* c, int code, hipStream_t s);

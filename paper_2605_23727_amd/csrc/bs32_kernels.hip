@@ -1094,6 +1094,9 @@ static hipError_t launch_mma(const Launch& L, const Tile& t) {
 }
 #undef BS32_LAUNCH
 
+static hipError_t dispatch(const Launch& L, int m, int fmt, const Tile& t);
+bool tile_supported(int fmt, int m, const Tile& t);
+
 static hipError_t dispatch(const Launch& L, int m, int fmt, const Tile& t) {
   switch (fmt) {
     case F_F64: return m == 2 ? launch_f64<2>(L, t) : launch_f64<1>(L, t);
@@ -1105,6 +1108,16 @@ static hipError_t dispatch(const Launch& L, int m, int fmt, const Tile& t) {
     case F_E4M3: return m == 2 ? launch_mma<F_E4M3, 2, 3>(L, t) : launch_mma<F_E4M3, 1, 3>(L, t);
     default: return hipErrorInvalidValue;
   }
+}
+
+int kernel_name(int fmt, int m, const Tile& t, char* buf, size_t cap) {
+  if (!tile_supported(fmt, m, t)) return -1;
+  const char* nt = t.NT ? "true" : "false";
+  if (fmt == F_F64) return snprintf(buf, cap, "k_contract_f64<%d, %d, %d, %d, %d, %s>", m, t.R, t.WR, t.WK, t.U, nt);
+  if (fmt == F_F32 && !t.MM)
+    return snprintf(buf, cap, "k_contract_f32<%d, 2, %d, %d, %d, %d, %s>", m, t.R, t.WR, t.WK, t.U, nt);
+  const int T = fmt == F_E4M3 ? 3 : 2;
+  return snprintf(buf, cap, "k_contract_mfma<%d, %d, %d, %d, %d, %d, %d, %s>", fmt, m, T, t.R, t.WR, t.WK, t.U, nt);
 }
 
 bool tile_supported(int fmt, int m, const Tile& t) {

@@ -111,6 +111,24 @@ def test_graph_and_stream_launch_agree(bs):
     assert np.array_equal(y1, y2) and st1["n_accept"] == st2["n_accept"]
 
 
+def test_stats_name_the_tile_and_kernel(bs):
+    b, s = bs
+    w = workloads.kuramoto(300, seed=34, t1=0.5)
+    s.set_workload(w)
+    for mode, prefix in ((0, "k_contract_f64<2, "), (2, "k_contract_mfma<2, 2, 2, "), (4, "k_contract_mfma<4, 2, 3, ")):
+        _, st = s.solve(w["y0"], 0.0, 0.5, 1e-6, mode=mode)
+        assert st["tile"] >= 0 and st["n_learned"] == 0
+        assert s.kernel_name(mode, st["tile"]).startswith(prefix)
+    s.set_options(tile=3)
+    try:
+        _, st = s.solve(w["y0"], 0.0, 0.5, 1e-6)
+        assert st["tile"] == 3
+    finally:
+        s.set_options(tile=-1)
+    with pytest.raises(b.BS32Error):
+        s.kernel_name(0, 10_000)
+
+
 def test_device_pointers(bs):
     import torch
     b, s = bs

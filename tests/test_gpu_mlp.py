@@ -101,6 +101,7 @@ def test_learned_solve_matches_oracle(bs, orc, which):
     assert st["status"] == 0 and sto["status"] == 0
     assert np.all(tr["err"][tr["accepted"] == 1] < rtol)
     assert tr["proposer"].sum() > 0.5 * len(tr)
+    assert st["n_learned"] == tr["proposer"].sum()
     assert abs(st["n_accept"] - sto["n_accept"]) <= 0.01 * sto["n_accept"]
     rel = np.linalg.norm(y - yo) / np.linalg.norm(yo)
     say(f"   accepted {st['n_accept']} / {sto['n_accept']}, proposer {tr['proposer'].sum()}, rel {rel:.2e}")
