@@ -24,7 +24,8 @@ Other measurement configurations, one JSON line each:
   c3  Goodwin clock network N = 16384 (state 49152), t in [0, 500],
       rtol = atol = 1e-6, coupling stored FP64 / FP32 / BF16 / FP16 / FP8-e4m3.
   c4  ensemble of 512 Kuramoto instances, N log-uniform in [256, 8192],
-      K ~ U[0.5, 4), t in [0, 50], rtol = atol = 1e-6, BF16 contraction vs FP64.
+      K ~ U[0.5, 4), t in [0, 50], rtol = atol = 1e-6, FP32 / BF16 / FP16
+      contractions vs FP64 (errors on a stratified 32-instance subset).
   c5  learned step-size proposer trained on solver traces of the c1-c3 laws,
       run on Kuramoto N = 32768 (t in [0, 50]) and coupled oscillators
       N = 32768 (t in [0, 10]), FP64 coupling, rtol = atol = 1e-7, against the
@@ -354,9 +355,19 @@ def bench_ensemble(args, torch, bs, modes, ref_rtol):
                 e.append(float(np.linalg.norm(res["y"][offs[b]:offs[b] + n] - yr[off:off + n]) / math.sqrt(n)))
                 off += n
             errs[mode] = np.array(e)
-    head = args.head if args.head is not None else 2
+    # headline: the fastest mode whose median error ratio to FP64 over the checked
+    # subset is at most 2 (FP64 itself always qualifies); --head forces one
+    def med_ratio(m):
+        return float(np.median(errs[m] / np.maximum(errs[0], 1e-300)))
+    if args.head is not None:
+        head = args.head
+    else:
+        ok = [m for m, r in results.items() if r["failed"] == 0 and (errs is None or med_ratio(m) <= 2.0)]
+        head = min(ok, key=lambda m: results[m]["time_to_t_end_s"]) if ok else 0
     rh, r0 = results[head], results[0]
     ratio = None if errs is None else errs[head] / np.maximum(errs[0], 1e-300)
+    for m in results:
+        results[m]["error_ratio_vs_fp64_median"] = None if errs is None else med_ratio(m)
     roof = roofline(rh["contraction_ms"], pairs_total * BYTES[min(head, 4)],
                     rh["kernel"].replace("k_contract_", "k_group_") + f" over {B} instances",
                     traffic_lookup(f"kuramoto_ensemble{B}", rh["name"], rh["kernel"].replace("k_contract_", "k_group_")))
@@ -379,7 +390,8 @@ def bench_ensemble(args, torch, bs, modes, ref_rtol):
         "reference_rtol": None if errs is None else ref_rtol,
         "setup_ms": setup_ms,
         "modes": {v["name"]: {k: v[k] for k in ("time_to_t_end_s", "pairs_per_s", "accepted", "rejected", "n_fev",
-                                                 "failed", "contraction_ms", "contraction_gbs", "tile", "kernel")}
+                                                 "failed", "contraction_ms", "contraction_gbs", "tile", "kernel",
+                                                 "error_ratio_vs_fp64_median")}
                   for v in results.values()},
         "roofline": roof,
         "cpu_baseline": None,
@@ -524,7 +536,7 @@ def main():
         line = bench_single(args, torch, bs, f"goodwin3_n{n}", w, modes if modes is not None else [0, 1, 2, 3, 4],
                             args.ref_rtol or 1e-9)
     elif args.config == "c4":
-        line = bench_ensemble(args, torch, bs, modes if modes is not None else [0, 2], args.ref_rtol or 1e-9)
+        line = bench_ensemble(args, torch, bs, modes if modes is not None else [0, 1, 2, 3], args.ref_rtol or 1e-9)
     else:
         line = bench_learned(args, torch, bs, args.ref_rtol or 1e-10)
     print(json.dumps(line), flush=True)
