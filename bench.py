@@ -205,6 +205,7 @@ def bench_single(args, torch, bs, workload, w, modes, ref_rtol):
     results = {}
     for mode in sorted(set([0] + modes)):
         log(f"mode {bs.MODE_NAMES[mode]}: {args.warmup} warm-up + {args.steps} timed solves")
+        fmt_bytes = BYTES[1] if mode >= 5 else BYTES[mode]
         for _ in range(args.warmup):
             s.solve(y0, 0.0, t1, rtol, mode=mode, out=out)
         torch.cuda.synchronize()
@@ -218,13 +219,14 @@ def bench_single(args, torch, bs, workload, w, modes, ref_rtol):
             pairs += stats["pair_interactions"]
         y = out.cpu().numpy()
         kms = s.time_contraction(mode, repeat=100)
-        gbs = n * n * BYTES[min(mode, 4)] / (kms * 1e-3) / 1e9
+        gbs = n * n * fmt_bytes / (kms * 1e-3) / 1e9
         results[mode] = dict(
             name=bs.MODE_NAMES[mode], time_to_t_end_s=float(np.median(times)), ms_per_step=1e3 * sum(times) / len(times),
             pairs_per_s=pairs / sum(times), accepted=int(stats["n_accept"]), rejected=int(stats["n_reject"]),
             n_fev=int(stats["n_fev"]), accepted_steps_per_s=stats["n_accept"] / float(np.median(times)),
             final_error=final_err(y), status=int(stats["status"]), contraction_ms=kms, contraction_gbs=gbs,
-            kernel_ms=stats["kernel_ms"], tile=int(stats["tile"]), kernel=s.kernel_name(mode, stats["tile"]))
+            kernel_ms=stats["kernel_ms"], tile=int(stats["tile"]),
+            kernel=s.kernel_name(1 if mode >= 5 else mode, stats["tile"]), fmt_bytes=fmt_bytes)
         log(f"  {results[mode]['time_to_t_end_s'] * 1e3:.2f} ms, error {results[mode]['final_error']}, "
             f"contraction {kms * 1e3:.2f} us ({gbs:.0f} GB/s), tile {stats['tile']}")
 
@@ -238,15 +240,16 @@ def bench_single(args, torch, bs, workload, w, modes, ref_rtol):
             r0["final_error"] is None or r["final_error"] is None or r["final_error"] <= 2.0 * r0["final_error"])]
         head = min(ok, key=lambda m: results[m]["time_to_t_end_s"]) if ok else 0
     rh = results[head]
-    traffic = traffic_lookup(workload, rh["name"], rh["kernel"])
-    roof = roofline(rh["contraction_ms"], n * n * BYTES[min(head, 4)], rh["kernel"], traffic)
+    traffic = traffic_lookup(workload, "rhs_fp32" if head >= 5 else rh["name"], rh["kernel"])
+    roof = roofline(rh["contraction_ms"], n * n * rh["fmt_bytes"], rh["kernel"], traffic)
 
     cpu = None
     if not args.no_cpu:
         log(f"CPU oracle baseline (~{args.cpu_seconds:g} s)")
         cpu = cpu_baseline(w, args.cpu_seconds)
 
-    line = base_line(args, rh["pairs_per_s"], rh["ms_per_step"], DTYPE[min(head, 4)] + "+f64-update",
+    line = base_line(args, rh["pairs_per_s"], rh["ms_per_step"],
+                     ("f32-recipe" if head >= 5 else DTYPE[head] + "+f64-update"),
                      {"workload": workload_desc(workload, w), "precision_mode": rh["name"], "global_batch": 1,
                       "seq_len": None})
     line.update({
@@ -527,13 +530,14 @@ def main():
         n = args.n or 4096
         w = workloads.kuramoto(n, seed=2000, K=2.0, t1=args.t1 or 50.0, rtol=args.rtol or 1e-6)
         w["seed"] = 2000
-        line = bench_single(args, torch, bs, f"kuramoto_n{n}", w, modes if modes is not None else [0, 1, 2, 3, 4],
-                            args.ref_rtol or 1e-12)
+        line = bench_single(args, torch, bs, f"kuramoto_n{n}", w,
+                            modes if modes is not None else [0, 1, 2, 3, 4, 5, 6, 7], args.ref_rtol or 1e-12)
     elif args.config == "c3":
         n = args.n or 16384
         w = workloads.goodwin3_device(n, seed=3000, t1=args.t1 or 500.0, rtol=args.rtol or 1e-6)
         w["seed"] = 3000
-        line = bench_single(args, torch, bs, f"goodwin3_n{n}", w, modes if modes is not None else [0, 1, 2, 3, 4],
+        line = bench_single(args, torch, bs, f"goodwin3_n{n}", w,
+                            modes if modes is not None else [0, 1, 2, 3, 4, 5, 6, 7],
                             args.ref_rtol or 1e-9)
     elif args.config == "c4":
         line = bench_ensemble(args, torch, bs, modes if modes is not None else [0, 1, 2, 3], args.ref_rtol or 1e-9)

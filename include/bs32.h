@@ -64,19 +64,32 @@ typedef enum {
                              y' = x - b_i y, z' = y - b_i z                                d = 3 */
 } bs32_system_kind;
 
-/* Precision of the coupling contraction.  The stage combinations, the error
-   estimate and its norm, t, h and the controller are FP64 in every mode. */
+/* Precision of the coupling contraction (Sec. 2.3).  In modes 0-4 the stage
+   combinations, the error estimate and its norm, t, h and the controller are
+   FP64.  Modes 1-4 store A as Q(A / s), Q = round to nearest even from FP64,
+   s = 2^ceil(log2(max|A| / m)) with m = 448 for e4m3 and 1 otherwise, and split
+   the vector operand v into T terms of the storage format, term t = Q(r_t 2^(t S)),
+   r_0 = v, r_(t+1) = r_t - 2^(-t S) term_t (the later terms compensate the first);
+   products are summed in FP32 within groups of at most 128 (FP32), 256 (BF16,
+   FP16) or 512 (e4m3) products and in FP64 across groups; the diffusive terms use
+   FP64 row sums of the stored matrix.  A vector term outside the format's range
+   stops the solve with BS32_RANGE. */
 typedef enum {
   BS32_PREC_FP64 = 0,         /* the paper's "Double" */
-  BS32_PREC_RHS_FP32 = 1,     /* A stored FP32; vector operand split in two FP32 terms; FP32 products,
-                                 FP64 accumulation across 32-element chunks */
-  BS32_PREC_RHS_BF16 = 2,     /* A stored BF16 (power-of-two scale); vector split in two BF16 terms;
-                                 MFMA with FP32 accumulation, FP64 across chunks */
-  BS32_PREC_RHS_FP16 = 3,     /* as BF16 with IEEE binary16 storage */
-  BS32_PREC_RHS_FP8_E4M3 = 4, /* A stored OCP e4m3fn (power-of-two scale); FP32 vector terms */
-  BS32_PREC_PAPER_SINGLE = 5, /* the paper's recipes, Sec. 2.3 Table MP-Distrib */
-  BS32_PREC_PAPER_MIXED1 = 6,
-  BS32_PREC_PAPER_MIXED2 = 7
+  BS32_PREC_RHS_FP32 = 1,     /* FP32 storage, T = 2, S = 24 (vector ALU or 16x16x4 f32 matrix cores) */
+  BS32_PREC_RHS_BF16 = 2,     /* BF16 storage, T = 2, S = 8 (16x16x32 bf16 matrix cores) */
+  BS32_PREC_RHS_FP16 = 3,     /* IEEE binary16 storage, T = 2, S = 11 (16x16x32 f16 matrix cores) */
+  BS32_PREC_RHS_FP8_E4M3 = 4, /* OCP e4m3fn storage, T = 3, S = 4 (16x16x32 fp8 matrix cores) */
+  /* The paper's recipes (Table MP-Distrib, rows k2, k3, k4; the first K1, the
+     starting-step probe and bs32_rhs use the k4 row).  Pair terms G in single
+     everywhere: A stored FP32 and the vector operand one FP32 term.  "F in S":
+     the agent term and the coupling combination in FP32; "Sigma in S": the
+     interaction sum accumulated in FP32 throughout (else FP32 groups, FP64 across
+     them).  Not available for ensembles. */
+  BS32_PREC_PAPER_SINGLE = 5, /* k2, k3, k4 all single; solution and stage inputs stored FP32;
+                                 h_min = 100 eps of FP32 */
+  BS32_PREC_PAPER_MIXED1 = 6, /* k2, k3 all single; k4: F and Sigma double, G single */
+  BS32_PREC_PAPER_MIXED2 = 7  /* k2, k3, k4: F and Sigma double, G single */
 } bs32_precision_mode;
 
 typedef struct {

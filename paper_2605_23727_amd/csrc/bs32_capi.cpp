@@ -49,6 +49,9 @@ int mode_fmt(int mode) {
     case BS32_PREC_RHS_BF16: return F_BF16;
     case BS32_PREC_RHS_FP16: return F_F16;
     case BS32_PREC_RHS_FP8_E4M3: return F_E4M3;
+    case BS32_PREC_PAPER_SINGLE:
+    case BS32_PREC_PAPER_MIXED1:
+    case BS32_PREC_PAPER_MIXED2: return F_F32;  // the recipes' single-precision pair terms
     default: return F_F64;
   }
 }
@@ -77,6 +80,7 @@ struct bs32_ctx {
 
   // system
   bool has_sys = false;
+  int cur_mode = 0;  // precision mode of the current solve / evaluation
   int kind = 0, d = 0, m = 0;
   long long n = 0, np = 0, ld = 0;
   double gain = 1.0;
@@ -228,6 +232,22 @@ Geom geometry(const bs32_ctx* c, int fmt, const Tile& t) {
   return g;
 }
 
+// The paper's recipes (Sec. 2.3, Table MP-Distrib) on this path: the pair terms G
+// are single in every recipe (A stored FP32, the vector operand one FP32 term);
+// "F in S" evaluates the agent term and the coupling combination in FP32 and
+// "Sigma in S" accumulates the interaction sum in FP32; Single also keeps the
+// solution and stage inputs in FP32.  Rows k2, k3 are stages S2, S3; the k4 row
+// also serves the first K1, the starting-step probe and single evaluations.
+void set_recipe(Args& a, int mode, int stage) {
+  if (mode < BS32_PREC_PAPER_SINGLE) return;
+  const bool k23 = stage == ST_S2 || stage == ST_S3;
+  const bool single = mode == BS32_PREC_PAPER_SINGLE || (mode == BS32_PREC_PAPER_MIXED1 && k23);
+  a.vsingle = 1;
+  a.fsingle = single ? 1 : 0;
+  a.sum32 = single ? 1 : 0;
+  a.sstate = mode == BS32_PREC_PAPER_SINGLE ? 1 : 0;
+}
+
 Args make_args(bs32_ctx* c, int fmt, const Geom& g, int stage) {
   Args a{};
   a.A = c->Aq[fmt];
@@ -256,6 +276,7 @@ Args make_args(bs32_ctx* c, int fmt, const Geom& g, int stage) {
   a.vfmt = vs.vfmt;
   a.vterms = vs.terms;
   a.vshift = vs.shift;
+  set_recipe(a, c->cur_mode, stage);
   a.n = c->n;
   a.np = c->np;
   a.ld = c->ld;
@@ -370,8 +391,8 @@ int tile_index(int fmt, const Tile& t) {
 bs32_status prepare(bs32_ctx* c, int mode, Geom* g, int* fmt) {
   if (!c->has_sys) return fail(c, BS32_ESTATE, "no system set");
   if (mode < 0 || mode > 7) return fail(c, BS32_EINVAL, "unknown precision mode %d", mode);
-  if (mode >= BS32_PREC_PAPER_SINGLE) return fail(c, BS32_EUNSUPPORTED, "precision mode %d not available", mode);
   *fmt = mode_fmt(mode);
+  c->cur_mode = mode;
   bs32_status s = ensure_state(c);
   if (s != BS32_OK) return s;
   s = ensure_packed(c, *fmt);
@@ -719,7 +740,8 @@ bs32_status bs32_solve(bs32_ctx* c, const double* y0, double t0, double t1, doub
   h->rtol = rtol;
   h->atol = atol;
   h->h_max = o.h_max > 0.0 ? o.h_max : 0.1 * std::fabs(t1 - t0);
-  h->h_min = 100.0 * 2.220446049250313e-16;  // 100 eps of the FP64 format holding h (Sec. 2.2)
+  // 100 eps of the format holding h (Sec. 2.2): FP32 in the Single recipe, FP64 otherwise
+  h->h_min = 100.0 * (mode == BS32_PREC_PAPER_SINGLE ? 1.1920928955078125e-07 : 2.220446049250313e-16);
   h->snap = 4.0 * 2.220446049250313e-16 * std::fabs(t1);
   h->safety = o.safety;
   h->facmin = o.facmin;
@@ -737,6 +759,7 @@ bs32_status bs32_solve(bs32_ctx* c, const double* y0, double t0, double t1, doub
   HIPCHK(c, hipMemsetAsync((char*)c->scratch + 32, 0, sizeof(unsigned), c->stream));
   s = upload_state(c, y0, c->X[0]);
   if (s != BS32_OK) return s;
+  if (mode == BS32_PREC_PAPER_SINGLE) HIPCHK(c, launch_round_f32(c->X[0], (long long)c->d * c->np, c->stream));
   HIPCHK(c, hipEventRecord(c->ev_start, c->stream));
   {
     // first stage K1 = f(t0, y0), then the starting-step probe (a2)

@@ -87,6 +87,11 @@ struct Args {
   int vfmt;               // format of the vector terms (F_F64 = no terms)
   int vterms;             // split terms of the vector operand
   int vshift;             // exponent shift between consecutive terms
+  // the paper's recipes (Sec. 2.3, Table MP-Distrib), per stage
+  int vsingle;            // pair terms in single: the vector operand is one FP32 term
+  int fsingle;            // agent term F and the coupling combination in FP32
+  int sum32;              // the interaction sum accumulated in FP32 throughout
+  int sstate;             // solution and stage inputs stored in FP32 (Single)
 };
 
 // Ensembles: one work item = (instance, row block) for a contraction, or
@@ -135,6 +140,7 @@ hipError_t launch_mlp_reduce(const float* part, int nparts, double* out, hipStre
 hipError_t launch_mlp_adam(float* master, float* m1, float* m2, float* wq, const float* part, int nparts, float lr,
                            float beta1, float beta2, float eps, float bc1, float bc2, hipStream_t s);
 hipError_t launch_bf16_copy(const float* src, float* dst, int n_round, int n, hipStream_t s);
+hipError_t launch_round_f32(double* x, long long n, hipStream_t s);
 hipError_t launch_to_soa(const double* src, double* dst, long long n, int d, long long np, hipStream_t s);
 hipError_t launch_from_soa(const double* src, double* dst, long long n, int d, long long np, hipStream_t s);
 hipError_t launch_pack_f64(const double* src, double* dst, long long n, long long ld, long long rows, int uniform,

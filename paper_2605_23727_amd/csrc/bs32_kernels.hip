@@ -47,6 +47,11 @@ __device__ __forceinline__ double nanmax(double a, double b) {
   if (a != a || b != b) return __builtin_nan("");
   return a > b ? a : b;
 }
+__device__ __forceinline__ float wave_sum_f32(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -159,7 +164,7 @@ __device__ void write_vq(const Args& a, void* Vq, long long i, const double* v) 
       const double x = ldexp(r, t * a.vshift);
       double qv;
       if (a.vfmt == F_F32) {
-        const float f = (float)x;
+        const float f = (a.vsingle && t > 0) ? 0.0f : (float)x;  // pair terms in single: one term
         ((float*)Vq)[idx] = f;
         qv = (double)f;
       } else {
@@ -208,6 +213,52 @@ __device__ __forceinline__ void rhs_agent(const Args& a, long long i, const doub
   }
 }
 
+// The same right-hand sides with the agent term and the coupling combination in
+// FP32 (the recipes' "F in single"): inputs rounded to FP32, FP32 arithmetic.
+__device__ __forceinline__ void rhs_agent_f32(const Args& a, long long i, const double* y, const double* P,
+                                              const double* vself, double* k) {
+  const float p = (float)a.param[i];
+  const float invN = (float)a.invN, g = (float)a.gain;
+  const float y0 = (float)y[0];
+  switch (a.kind) {
+    case 1: {
+      const float inter = invN * ((float)P[0] - y0 * (float)a.rsum[i]);
+      k[0] = (double)(float)y[1];
+      k[1] = (double)((-p * p * y0) + inter);
+      break;
+    }
+    case 2: {
+      const float inter = invN * ((float)P[0] - y0 * (float)a.rsum[i]);
+      k[0] = (double)((float)y[1] + inter);
+      k[1] = (double)(-y0);
+      break;
+    }
+    case 3: {
+      const float inter = g * invN * ((float)vself[1] * (float)P[0] - (float)vself[0] * (float)P[1]);
+      k[0] = (double)(p + inter);
+      break;
+    }
+    default: {
+      const float y1 = (float)y[1], y2 = (float)y[2];
+      const float z2 = y2 * y2, z4 = z2 * z2, z8 = z4 * z4;
+      const float inter = g * invN * ((float)P[0] - y0 * (float)a.rsum[i]);
+      k[0] = (double)((1.0f / (1.0f + z8 * z2) - p * y0) + inter);
+      k[1] = (double)(y0 - p * y1);
+      k[2] = (double)(y1 - p * y2);
+      break;
+    }
+  }
+}
+
+__device__ __forceinline__ void rhs_eval(const Args& a, long long i, const double* y, const double* P,
+                                         const double* vself, double* k) {
+  if (a.fsingle) rhs_agent_f32(a, i, y, P, vself, k);
+  else rhs_agent(a, i, y, P, vself, k);
+}
+
+// Single keeps its solution and stage inputs in FP32
+__device__ __forceinline__ double sstore(const Args& a, double v) { return a.sstate ? (double)(float)v : v; }
+
 __device__ __forceinline__ int vin_of(int stage) { return stage == ST_S3 ? 1 : 0; }
 
 // ---------------------------------------------------------------------------
@@ -228,7 +279,7 @@ __device__ void epilogue(const Args& a, const Ctl* ctl, long long i, const doubl
     case ST_INIT:
     case ST_RHS: {
       for (int c = 0; c < d; ++c) y[c] = X[c * np + i];
-      rhs_agent(a, i, y, P, vself, k);
+      rhs_eval(a, i, y, P, vself, k);
       double* K = a.Kf[ctl->ki];
       for (int c = 0; c < d; ++c) {
         K[c * np + i] = k[c];
@@ -240,7 +291,7 @@ __device__ void epilogue(const Args& a, const Ctl* ctl, long long i, const doubl
     }
     case ST_H0: {
       for (int c = 0; c < d; ++c) y[c] = X[c * np + i] + ctl->h0probe * K1[c * np + i];
-      rhs_agent(a, i, y, P, vself, k);
+      rhs_eval(a, i, y, P, vself, k);
       for (int c = 0; c < d; ++c) {
         const double sc = ctl->atol + ctl->rtol * fabs(X[c * np + i]);
         *r0 = nanmax(*r0, fabs(k[c] - K1[c * np + i]) / sc);
@@ -248,20 +299,21 @@ __device__ void epilogue(const Args& a, const Ctl* ctl, long long i, const doubl
       break;
     }
     case ST_S2: {
-      for (int c = 0; c < d; ++c) y[c] = X[c * np + i] + ha * (kA21 * K1[c * np + i]);
-      rhs_agent(a, i, y, P, vself, k);
+      for (int c = 0; c < d; ++c) y[c] = sstore(a, X[c * np + i] + ha * (kA21 * K1[c * np + i]));
+      rhs_eval(a, i, y, P, vself, k);
       for (int c = 0; c < d; ++c) a.K2[c * np + i] = k[c];
-      write_operand(a, 1, i, X[i] + ha * (kA32 * k[0]));  // stage-3 input of this agent
+      write_operand(a, 1, i, sstore(a, X[i] + ha * (kA32 * k[0])));  // stage-3 input of this agent
       break;
     }
     case ST_S3: {
       const double* K2 = a.K2;
       double* Xn = a.X[1 - ctl->xi];
-      for (int c = 0; c < d; ++c) y[c] = X[c * np + i] + ha * (kA32 * K2[c * np + i]);
-      rhs_agent(a, i, y, P, vself, k);
+      for (int c = 0; c < d; ++c) y[c] = sstore(a, X[c * np + i] + ha * (kA32 * K2[c * np + i]));
+      rhs_eval(a, i, y, P, vself, k);
       for (int c = 0; c < d; ++c) {
         a.K3[c * np + i] = k[c];
-        const double xn = X[c * np + i] + ha * (kB1 * K1[c * np + i] + kB2 * K2[c * np + i] + kB3 * k[c]);
+        const double xn =
+            sstore(a, X[c * np + i] + ha * (kB1 * K1[c * np + i] + kB2 * K2[c * np + i] + kB3 * k[c]));
         Xn[c * np + i] = xn;
         y[c] = xn;
       }
@@ -272,7 +324,7 @@ __device__ void epilogue(const Args& a, const Ctl* ctl, long long i, const doubl
       const double* Xn = a.X[1 - ctl->xi];
       double* K4 = a.Kf[1 - ctl->ki];
       for (int c = 0; c < d; ++c) y[c] = Xn[c * np + i];
-      rhs_agent(a, i, y, P, vself, k);
+      rhs_eval(a, i, y, P, vself, k);
       const double floor_w = ctl->atol / ctl->rtol;
       for (int c = 0; c < d; ++c) {
         K4[c * np + i] = k[c];
@@ -432,10 +484,14 @@ __device__ __forceinline__ void contract_f32(const Args& a, int rb) {
   const long long jb = (long long)wk * a.KW;
   const long long je = min(jb + (long long)a.KW, a.ld);
   double acc[R][NC];
+  float accf[R][NC];  // the recipes' single sum
 #pragma unroll
   for (int r = 0; r < R; ++r)
 #pragma unroll
-    for (int c = 0; c < NC; ++c) acc[r][c] = 0.0;
+    for (int c = 0; c < NC; ++c) {
+      acc[r][c] = 0.0;
+      accf[r][c] = 0.0f;
+    }
   long long j0 = jb;
   for (; j0 < je; j0 += 256 * U) {
     const int uu = (int)min((long long)U, (je - j0) / 256);
@@ -465,24 +521,31 @@ __device__ __forceinline__ void contract_f32(const Args& a, int rb) {
             s = fmaf(av[u][r].w, vv[u][c].w, s);
           }
         }
-        acc[r][c] += (double)s;
+        if (a.sum32) accf[r][c] += s;
+        else acc[r][c] += (double)s;
       }
   }
 #pragma unroll
   for (int r = 0; r < R; ++r)
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const double s = wave_sum(acc[r][c]);
+      const double s = a.sum32 ? (double)wave_sum_f32(accf[r][c]) : wave_sum(acc[r][c]);
       if (lane == 0) sPart[wk][wr * R + r][c] = s;
     }
   __syncthreads();
   for (int e = threadIdx.x; e < RB * M; e += blockDim.x) {
     const int row = e / M, cc = e % M;
     double p = 0.0;
-    for (int t = 0; t < T; ++t) {
-      double s = 0.0;
-      for (int q = 0; q < WK; ++q) s += sPart[q][row][cc * T + t];
-      p += ldexp(s, -t * a.vshift);
+    if (a.sum32) {  // single sum: one FP32 term (vsingle), wave slices added in FP32
+      float s = 0.0f;
+      for (int q = 0; q < WK; ++q) s += (float)sPart[q][row][cc * T];
+      p = (double)s;
+    } else {
+      for (int t = 0; t < T; ++t) {
+        double s = 0.0;
+        for (int q = 0; q < WK; ++q) s += sPart[q][row][cc * T + t];
+        p += ldexp(s, -t * a.vshift);
+      }
     }
     sP[row][cc] = a.scale * p;
   }
@@ -574,7 +637,7 @@ __device__ __forceinline__ void contract_mfma(const Args& a, int rb) {
 #pragma unroll
       for (int t = 0; t < RT; ++t) c[t] = mma<FMT>(av[u][t], bv[u], c[t]);
     kc += U;
-    if (kc >= KC) {
+    if (kc >= KC && !a.sum32) {  // FP64 flush (the recipes' single sum keeps FP32 throughout)
 #pragma unroll
       for (int t = 0; t < RT; ++t) {
         for (int i = 0; i < 4; ++i) dacc[t][i] += (double)c[t][i];
@@ -605,10 +668,16 @@ __device__ __forceinline__ void contract_mfma(const Args& a, int rb) {
   for (int e = threadIdx.x; e < RB * M; e += blockDim.x) {
     const int row = e / M, cc = e % M;
     double p = 0.0;
-    for (int t = 0; t < T; ++t) {
-      double s = 0.0;
-      for (int q = 0; q < WK; ++q) s += sPart[q][row][cc * T + t];
-      p += ldexp(s, -t * a.vshift);
+    if (a.sum32) {  // single sum: one FP32 term (vsingle), wave slices added in FP32
+      float s = 0.0f;
+      for (int q = 0; q < WK; ++q) s += (float)sPart[q][row][cc * T];
+      p = (double)s;
+    } else {
+      for (int t = 0; t < T; ++t) {
+        double s = 0.0;
+        for (int q = 0; q < WK; ++q) s += sPart[q][row][cc * T + t];
+        p += ldexp(s, -t * a.vshift);
+      }
     }
     sP[row][cc] = a.scale * p;
   }
@@ -629,7 +698,7 @@ __device__ __forceinline__ void prep_block(const Args& a, int blk) {
   const double* K1 = a.Kf[ctl->ki];
   double y = X[i];
   if (a.stage == ST_H0) y = X[i] + ctl->h0probe * K1[i];
-  else if (a.stage == ST_S2) y = X[i] + ctl->ha * (kA21 * K1[i]);
+  else if (a.stage == ST_S2) y = sstore(a, X[i] + ctl->ha * (kA21 * K1[i]));
   write_operand(a, 0, i, y);
 }
 __global__ void k_prep(Args a) { prep_block(a, blockIdx.x); }
@@ -872,7 +941,7 @@ __device__ __forceinline__ void finalize_block(const Args& a, int blk) {
   if (sc.status != kRunning) return;
   if (i < a.n) {
     const double x = xc[sc.xi], k1 = kc[sc.ki];
-    const double y = (s_next == ST_H0) ? x + sc.h0probe * k1 : x + sc.ha * (kA21 * k1);
+    const double y = (s_next == ST_H0) ? x + sc.h0probe * k1 : sstore(a, x + sc.ha * (kA21 * k1));
     write_operand(a, 0, i, y);
   }
 }
@@ -961,6 +1030,17 @@ __global__ void k_rowsum(const void* __restrict__ A, int fmt, double scale, doub
 // host launchers
 // ---------------------------------------------------------------------------
 static unsigned grid_for(long long count) { return (unsigned)std::min<long long>((count + 255) / 256, 65536); }
+
+// values rounded to FP32 in place (the Single recipe's initial state)
+__global__ void k_round_f32(double* __restrict__ x, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = (double)(float)x[i];
+}
+hipError_t launch_round_f32(double* x, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_round_f32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, n);
+  return hipGetLastError();
+}
 
 hipError_t launch_to_soa(const double* src, double* dst, long long n, int d, long long np, hipStream_t s) {
   k_to_soa<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, dst, n, d, np);
