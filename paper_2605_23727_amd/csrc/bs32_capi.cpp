@@ -99,6 +99,7 @@ struct bs32_ctx {
   double* K3 = nullptr;
   double* V64[2] = {nullptr, nullptr};
   void* Vq[2] = {nullptr, nullptr};
+  int vq_fmt = -1;  // storage format the split-operand buffers were last cleared for
   double* ep0 = nullptr;
   double* ep1 = nullptr;
   double* stage_buf = nullptr;  // d*n staging for host <-> device copies
@@ -212,6 +213,7 @@ bs32_status ensure_state(bs32_ctx* c) {
     HIPCHK(c, alloc0((void**)&c->Kf[q], sv));
     HIPCHK(c, alloc0((void**)&c->V64[q], sizeof(double) * (size_t)(2 * c->ld)));
     HIPCHK(c, alloc0((void**)&c->Vq[q], sizeof(float) * 6 * (size_t)c->ld));
+    c->vq_fmt = -1;
   }
   HIPCHK(c, alloc0((void**)&c->K2, sv));
   HIPCHK(c, alloc0((void**)&c->K3, sv));
@@ -408,6 +410,13 @@ bs32_status prepare(bs32_ctx* c, int mode, Geom* g, int* fmt) {
     t = c->best[*fmt];
   }
   *g = geometry(c, *fmt, t);
+  // The contraction reads the operand terms over the padded row length, where A is
+  // zero; bytes another format left in the padding could decode as Inf or NaN
+  // (0 * Inf = NaN), so the buffers start from zero whenever the format changes.
+  if (*fmt != F_F64 && c->vq_fmt != *fmt) {
+    for (int q = 0; q < 2; ++q) HIPCHK(c, hipMemsetAsync(c->Vq[q], 0, sizeof(float) * 6 * (size_t)c->ld, c->stream));
+    c->vq_fmt = *fmt;
+  }
   char key[128];
   snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%p", mode, t.R, t.WR, t.WK, t.U, t.NT, t.MM, (void*)c->trace_d);
   if (c->graph_key != key) {

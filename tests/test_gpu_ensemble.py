@@ -129,3 +129,45 @@ def test_batch_rejects_mixed_kinds(bs):
     b, s = bs
     with pytest.raises(b.BS32Error):
         s.set_ensemble([workloads.kuramoto(40, seed=1), workloads.osc2(40, seed=2)])
+
+
+def test_format_switch_leaves_no_stale_operand_bytes(bs):
+    """Padding columns of the operand buffers are read against zero weights; after
+    a solve in another storage format they must not hold that format's bytes (an
+    FP32 value's low half read as BF16 / FP16 can be Inf or NaN, and 0 * Inf = NaN)."""
+    b, s = bs
+    ws = _members(12, 9)
+    y0 = np.concatenate([w["y0"] for w in ws])
+    s.set_options(tile=7)
+    try:
+        fresh = {}
+        for mode in (2, 3):
+            s.set_ensemble(ws)
+            y, st, _ = s.solve_batch(y0, 0.0, 2.0, 1e-6, mode=mode)
+            assert np.all(st == 0)
+            fresh[mode] = y
+        s.set_ensemble(ws)
+        for mode in (1, 2, 1, 3):
+            say(f"[format switch] ensemble mode {mode}")
+            y, st, _ = s.solve_batch(y0, 0.0, 2.0, 1e-6, mode=mode)
+            assert np.all(st == 0), (mode, st)
+            if mode in fresh:
+                np.testing.assert_array_equal(y, fresh[mode])
+    finally:
+        s.set_options(tile=-1)
+
+
+def test_format_switch_single_system(bs):
+    b, s = bs
+    w = workloads.kuramoto(300, seed=71, t1=2.0)   # N not a multiple of 256: padded rows
+    s.set_options(tile=0)
+    try:
+        s.set_workload(w)
+        y2, st2 = s.solve(w["y0"], 0.0, 2.0, 1e-6, mode=2)
+        s.set_workload(w)
+        for mode in (1, 2, 4, 3, 2):
+            y, st = s.solve(w["y0"], 0.0, 2.0, 1e-6, mode=mode)
+            assert st["status"] == 0, (mode, st["status"])
+        np.testing.assert_array_equal(y, y2)
+    finally:
+        s.set_options(tile=-1)
