@@ -145,59 +145,87 @@ __device__ inline double decode_bits(uint32_t b, FmtDesc f) {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void vec_of(int kind, double y, double* v) {
   if (kind == 3) {
-    v[0] = sin(y);
-    v[1] = cos(y);
+    sincos(y, &v[0], &v[1]);
   } else {
     v[0] = y;
   }
 }
 
-// Vq layout: [c * T + t][ld]; term t holds Q(r_t 2^(t shift)), r_0 = v,
-// r_{t+1} = r_t - 2^(-t shift) Q(r_t 2^(t shift)).
-__device__ void write_vq(const Args& a, void* Vq, long long i, const double* v) {
-  if (a.vfmt == F_F64 || Vq == nullptr) return;
-  for (int c = 0; c < a.m; ++c) {
-    double r = v[c];
-    if (fabs(r) > a.vmax && isfinite(r)) *a.rflag = 1u;
-    for (int t = 0; t < a.vterms; ++t) {
-      const long long idx = (long long)(c * a.vterms + t) * a.ld + i;
-      const double x = ldexp(r, t * a.vshift);
-      double qv;
-      if (a.vfmt == F_F32) {
-        const float f = (a.vsingle && t > 0) ? 0.0f : (float)x;  // pair terms in single: one term
-        ((float*)Vq)[idx] = f;
-        qv = (double)f;
-      } else {
-        const FmtDesc fd = fmt_desc(a.vfmt);
-        const uint32_t b = encode_rne(x, fd);
-        if (a.vfmt == F_E4M3) ((uint8_t*)Vq)[idx] = (uint8_t)b;
-        else ((uint16_t*)Vq)[idx] = (uint16_t)b;
-        qv = decode_bits(b, fd);
+// split terms of a storage format: count and exponent shift between terms
+template <int VF>
+struct VSplit {
+  static constexpr int T = VF == F_E4M3 ? 3 : 2;
+  static constexpr int S = VF == F_F32 ? 24 : VF == F_BF16 ? 8 : VF == F_F16 ? 11 : 4;
+};
+
+// Vq layout: [c * T + t][ld]; term t holds Q(r_t 2^(t S)), r_0 = v,
+// r_{t+1} = r_t - 2^(-t S) Q(r_t 2^(t S)).  (Scaling by a power of two is exact,
+// so the products below equal ldexp.)
+template <int VF>
+__device__ void write_vq_t(const Args& a, void* Vq, long long i, const double* v) {
+  if constexpr (VF == F_F64) {
+    return;
+  } else {
+    if (Vq == nullptr) return;
+    constexpr int T = VSplit<VF>::T, S = VSplit<VF>::S;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (c >= a.m) break;
+      double r = v[c];
+      if (fabs(r) > a.vmax && isfinite(r)) *a.rflag = 1u;
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const long long idx = (long long)(c * T + t) * a.ld + i;
+        const double x = r * __builtin_ldexp(1.0, t * S);
+        double qv;
+        if constexpr (VF == F_F32) {
+          const float f = (a.vsingle && t > 0) ? 0.0f : (float)x;  // pair terms in single: one term
+          ((float*)Vq)[idx] = f;
+          qv = (double)f;
+        } else {
+          constexpr FmtDesc fd = fmt_desc(VF);
+          const uint32_t b = encode_rne(x, fd);
+          if constexpr (VF == F_E4M3) ((uint8_t*)Vq)[idx] = (uint8_t)b;
+          else ((uint16_t*)Vq)[idx] = (uint16_t)b;
+          qv = decode_bits(b, fd);
+        }
+        r = r - qv * __builtin_ldexp(1.0, -t * S);
       }
-      r = r - ldexp(qv, -t * a.vshift);
     }
   }
 }
 
-__device__ __forceinline__ void write_operand(const Args& a, int buf, long long i, double y) {
+template <int VF>
+__device__ __forceinline__ void write_operand_t(const Args& a, int buf, long long i, double y) {
   double v[2];
   vec_of(a.kind, y, v);
   for (int c = 0; c < a.m; ++c) a.V64[buf][i * a.m + c] = v[c];
-  write_vq(a, a.Vq[buf], i, v);
+  write_vq_t<VF>(a, a.Vq[buf], i, v);
+}
+
+// the same with the format known only at run time (prep and finalize serve every format)
+__device__ __forceinline__ void write_operand(const Args& a, int buf, long long i, double y) {
+  switch (a.vfmt) {
+    case F_F32: write_operand_t<F_F32>(a, buf, i, y); break;
+    case F_BF16: write_operand_t<F_BF16>(a, buf, i, y); break;
+    case F_F16: write_operand_t<F_F16>(a, buf, i, y); break;
+    case F_E4M3: write_operand_t<F_E4M3>(a, buf, i, y); break;
+    default: write_operand_t<F_F64>(a, buf, i, y); break;
+  }
 }
 
 // F_i(Y_i) + coupling of agent i from the contraction P_i (Sec. 2.1 benchmarks with
-// weights A_ij/N).  vself: the agent's own vector operand (sin, cos of theta_i).
-__device__ __forceinline__ void rhs_agent(const Args& a, long long i, const double* y, const double* P,
-                                          const double* vself, double* k) {
-  const double p = a.param[i];
+// weights A_ij/N).  vself: the agent's own vector operand (sin, cos of theta_i);
+// p: its parameter (omega or b); rs: its row sum of the stored weights.
+__device__ __forceinline__ void rhs_agent(const Args& a, const double* y, const double* P, const double* vself,
+                                          double p, double rs, double* k) {
   switch (a.kind) {
     case 1:  // coupled oscillators: x' = v, v' = -w^2 x + (1/N) sum_j A_ij (x_j - x_i)
       k[0] = y[1];
-      k[1] = -p * p * y[0] + a.invN * (P[0] - y[0] * a.rsum[i]);
+      k[1] = -p * p * y[0] + a.invN * (P[0] - y[0] * rs);
       break;
     case 2:  // paper eq. (LCO): x' = v + (1/N) sum_j A_ij (x_j - x_i), v' = -x
-      k[0] = y[1] + a.invN * (P[0] - y[0] * a.rsum[i]);
+      k[0] = y[1] + a.invN * (P[0] - y[0] * rs);
       k[1] = -y[0];
       break;
     case 3:  // paper eq. (Kuramoto): sum_j A_ij sin(th_j - th_i) = cos th_i (A sin th)_i - sin th_i (A cos th)_i
@@ -205,7 +233,7 @@ __device__ __forceinline__ void rhs_agent(const Args& a, long long i, const doub
       break;
     default: {  // Goodwin clock: x' = 1/(1+z^10) - b x + (kappa/N) sum_j C_ij (x_j - x_i)
       const double z2 = y[2] * y[2], z4 = z2 * z2, z8 = z4 * z4;
-      k[0] = 1.0 / (1.0 + z8 * z2) - p * y[0] + a.gain * a.invN * (P[0] - y[0] * a.rsum[i]);
+      k[0] = 1.0 / (1.0 + z8 * z2) - p * y[0] + a.gain * a.invN * (P[0] - y[0] * rs);
       k[1] = y[0] - p * y[1];
       k[2] = y[1] - p * y[2];
       break;
@@ -215,20 +243,20 @@ __device__ __forceinline__ void rhs_agent(const Args& a, long long i, const doub
 
 // The same right-hand sides with the agent term and the coupling combination in
 // FP32 (the recipes' "F in single"): inputs rounded to FP32, FP32 arithmetic.
-__device__ __forceinline__ void rhs_agent_f32(const Args& a, long long i, const double* y, const double* P,
-                                              const double* vself, double* k) {
-  const float p = (float)a.param[i];
+__device__ __forceinline__ void rhs_agent_f32(const Args& a, const double* y, const double* P, const double* vself,
+                                              double pd, double rsd, double* k) {
+  const float p = (float)pd, rs = (float)rsd;
   const float invN = (float)a.invN, g = (float)a.gain;
   const float y0 = (float)y[0];
   switch (a.kind) {
     case 1: {
-      const float inter = invN * ((float)P[0] - y0 * (float)a.rsum[i]);
+      const float inter = invN * ((float)P[0] - y0 * rs);
       k[0] = (double)(float)y[1];
       k[1] = (double)((-p * p * y0) + inter);
       break;
     }
     case 2: {
-      const float inter = invN * ((float)P[0] - y0 * (float)a.rsum[i]);
+      const float inter = invN * ((float)P[0] - y0 * rs);
       k[0] = (double)((float)y[1] + inter);
       k[1] = (double)(-y0);
       break;
@@ -241,7 +269,7 @@ __device__ __forceinline__ void rhs_agent_f32(const Args& a, long long i, const 
     default: {
       const float y1 = (float)y[1], y2 = (float)y[2];
       const float z2 = y2 * y2, z4 = z2 * z2, z8 = z4 * z4;
-      const float inter = g * invN * ((float)P[0] - y0 * (float)a.rsum[i]);
+      const float inter = g * invN * ((float)P[0] - y0 * rs);
       k[0] = (double)((1.0f / (1.0f + z8 * z2) - p * y0) + inter);
       k[1] = (double)(y0 - p * y1);
       k[2] = (double)(y1 - p * y2);
@@ -250,10 +278,10 @@ __device__ __forceinline__ void rhs_agent_f32(const Args& a, long long i, const 
   }
 }
 
-__device__ __forceinline__ void rhs_eval(const Args& a, long long i, const double* y, const double* P,
-                                         const double* vself, double* k) {
-  if (a.fsingle) rhs_agent_f32(a, i, y, P, vself, k);
-  else rhs_agent(a, i, y, P, vself, k);
+__device__ __forceinline__ void rhs_eval(const Args& a, const double* y, const double* P, const double* vself,
+                                         double p, double rs, double* k) {
+  if (a.fsingle) rhs_agent_f32(a, y, P, vself, p, rs, k);
+  else rhs_agent(a, y, P, vself, p, rs, k);
 }
 
 // Single keeps its solution and stage inputs in FP32
@@ -262,26 +290,58 @@ __device__ __forceinline__ double sstore(const Args& a, double v) { return a.sst
 __device__ __forceinline__ int vin_of(int stage) { return stage == ST_S3 ? 1 : 0; }
 
 // ---------------------------------------------------------------------------
-// stage epilogue of row i; returns the row's contributions to the block maxima
+// stage epilogue of one row.  Its inputs are loaded by load_row before the
+// contraction loop, so that their latency hides behind the stream of A; the
+// epilogue returns the row's contributions to the block maxima.
 // ---------------------------------------------------------------------------
-__device__ void epilogue(const Args& a, const Ctl* ctl, long long i, const double* P, double* r0, double* r1) {
-  const int d = a.d;
+struct RowIn {
+  double x[3], xn[3], k1[3], k2[3], k3[3];  // X^n, X^{n+1}, K1, K2, K3 (those the stage reads)
+  double p, rs, vs[2];                      // parameter, row sum, own vector operand
+};
+
+__device__ __forceinline__ void load_row(const Args& a, const Ctl* ctl, long long i, RowIn& r) {
   const long long np = a.np;
+  const int st = a.stage;
   const double* X = a.X[ctl->xi];
   const double* K1 = a.Kf[ctl->ki];
-  const double* Vin = a.V64[vin_of(a.stage)];
-  const double vself[2] = {Vin[i * a.m], a.m > 1 ? Vin[i * a.m + 1] : 0.0};
-  double y[3], k[3];
+  const double* Vin = a.V64[vin_of(st)];
+  r.p = a.param[i];
+  r.rs = a.rsum[i];
+  r.vs[0] = Vin[i * a.m];
+  r.vs[1] = a.m > 1 ? Vin[i * a.m + 1] : 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    r.x[c] = r.xn[c] = r.k1[c] = r.k2[c] = r.k3[c] = 0.0;
+    if (c >= a.d) continue;
+    r.x[c] = X[c * np + i];
+    if (st != ST_INIT && st != ST_RHS) r.k1[c] = K1[c * np + i];
+    if (st == ST_S3 || st == ST_S4) r.k2[c] = a.K2[c * np + i];
+    if (st == ST_S4) {
+      r.k3[c] = a.K3[c * np + i];
+      r.xn[c] = a.X[1 - ctl->xi][c * np + i];
+    }
+  }
+}
+
+template <int VF>
+__device__ void epilogue(const Args& a, const Ctl* ctl, long long i, const double* P, const RowIn& r, double* r0,
+                         double* r1) {
+  const int d = a.d;
+  const long long np = a.np;
+  double y[3] = {0.0, 0.0, 0.0}, k[3] = {0.0, 0.0, 0.0};
   const double ha = ctl->ha;
   *r0 = 0.0;
   *r1 = 0.0;
   switch (a.stage) {
     case ST_INIT:
     case ST_RHS: {
-      for (int c = 0; c < d; ++c) y[c] = X[c * np + i];
-      rhs_eval(a, i, y, P, vself, k);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) y[c] = r.x[c];
+      rhs_eval(a, y, P, r.vs, r.p, r.rs, k);
       double* K = a.Kf[ctl->ki];
-      for (int c = 0; c < d; ++c) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (c >= d) break;
         K[c * np + i] = k[c];
         const double sc = ctl->atol + ctl->rtol * fabs(y[c]);
         *r0 = nanmax(*r0, fabs(y[c]) / sc);
@@ -290,74 +350,80 @@ __device__ void epilogue(const Args& a, const Ctl* ctl, long long i, const doubl
       break;
     }
     case ST_H0: {
-      for (int c = 0; c < d; ++c) y[c] = X[c * np + i] + ctl->h0probe * K1[c * np + i];
-      rhs_eval(a, i, y, P, vself, k);
-      for (int c = 0; c < d; ++c) {
-        const double sc = ctl->atol + ctl->rtol * fabs(X[c * np + i]);
-        *r0 = nanmax(*r0, fabs(k[c] - K1[c * np + i]) / sc);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) y[c] = r.x[c] + ctl->h0probe * r.k1[c];
+      rhs_eval(a, y, P, r.vs, r.p, r.rs, k);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (c >= d) break;
+        const double sc = ctl->atol + ctl->rtol * fabs(r.x[c]);
+        *r0 = nanmax(*r0, fabs(k[c] - r.k1[c]) / sc);
       }
       break;
     }
     case ST_S2: {
-      for (int c = 0; c < d; ++c) y[c] = sstore(a, X[c * np + i] + ha * (kA21 * K1[c * np + i]));
-      rhs_eval(a, i, y, P, vself, k);
-      for (int c = 0; c < d; ++c) a.K2[c * np + i] = k[c];
-      write_operand(a, 1, i, sstore(a, X[i] + ha * (kA32 * k[0])));  // stage-3 input of this agent
+#pragma unroll
+      for (int c = 0; c < 3; ++c) y[c] = sstore(a, r.x[c] + ha * (kA21 * r.k1[c]));
+      rhs_eval(a, y, P, r.vs, r.p, r.rs, k);
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        if (c < d) a.K2[c * np + i] = k[c];
+      write_operand_t<VF>(a, 1, i, sstore(a, r.x[0] + ha * (kA32 * k[0])));  // stage-3 input of this agent
       break;
     }
     case ST_S3: {
-      const double* K2 = a.K2;
       double* Xn = a.X[1 - ctl->xi];
-      for (int c = 0; c < d; ++c) y[c] = sstore(a, X[c * np + i] + ha * (kA32 * K2[c * np + i]));
-      rhs_eval(a, i, y, P, vself, k);
-      for (int c = 0; c < d; ++c) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) y[c] = sstore(a, r.x[c] + ha * (kA32 * r.k2[c]));
+      rhs_eval(a, y, P, r.vs, r.p, r.rs, k);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (c >= d) break;
         a.K3[c * np + i] = k[c];
-        const double xn =
-            sstore(a, X[c * np + i] + ha * (kB1 * K1[c * np + i] + kB2 * K2[c * np + i] + kB3 * k[c]));
+        const double xn = sstore(a, r.x[c] + ha * (kB1 * r.k1[c] + kB2 * r.k2[c] + kB3 * k[c]));
         Xn[c * np + i] = xn;
         y[c] = xn;
       }
-      write_operand(a, 0, i, y[0]);  // the FSAL stage is evaluated at X^{n+1}
+      write_operand_t<VF>(a, 0, i, y[0]);  // the FSAL stage is evaluated at X^{n+1}
       break;
     }
     case ST_S4: {
-      const double* Xn = a.X[1 - ctl->xi];
       double* K4 = a.Kf[1 - ctl->ki];
-      for (int c = 0; c < d; ++c) y[c] = Xn[c * np + i];
-      rhs_eval(a, i, y, P, vself, k);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) y[c] = r.xn[c];
+      rhs_eval(a, y, P, r.vs, r.p, r.rs, k);
       const double floor_w = ctl->atol / ctl->rtol;
-      for (int c = 0; c < d; ++c) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (c >= d) break;
         K4[c * np + i] = k[c];
         // difference of the two solutions formed from the stages (Sec. 2.2)
-        const double e = ha * ((kB1 - kBt1) * K1[c * np + i] + (kB2 - kBt2) * a.K2[c * np + i] +
-                               (kB3 - kBt3) * a.K3[c * np + i] + (0.0 - kBt4) * k[c]);
-        const double xa = fabs(X[c * np + i]);
+        const double e = ha * ((kB1 - kBt1) * r.k1[c] + (kB2 - kBt2) * r.k2[c] + (kB3 - kBt3) * r.k3[c] +
+                               (0.0 - kBt4) * k[c]);
+        const double xa = fabs(r.x[c]);
         const double W = fmax(fmax(xa, fabs(y[c])), floor_w);
         *r0 = nanmax(*r0, fabs(e) / W);
-        *r1 = nanmax(*r1, fabs(K1[c * np + i]) / fmax(xa, floor_w));
+        *r1 = nanmax(*r1, fabs(r.k1[c]) / fmax(xa, floor_w));
       }
       break;
     }
   }
 }
 
+// the row this thread finishes (at most one: every tile has fewer rows than threads)
+__device__ __forceinline__ long long tail_row(const Args& a, int rb, int RB) {
+  return threadIdx.x < RB ? (long long)rb * RB + threadIdx.x : -1;
+}
+
 // common tail of every contraction kernel: row epilogues and the block maxima
-template <int M>
-__device__ void contract_tail(const Args& a, int rb, double (*sP)[M], int RB) {
+template <int M, int VF>
+__device__ void contract_tail(const Args& a, int rb, double (*sP)[M], int RB, const RowIn& rin) {
   __shared__ double sRed0[16], sRed1[16];
   const Ctl* ctl = a.ctl;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const long long rowb = (long long)rb * RB;
+  const long long i = tail_row(a, rb, RB);
   double r0 = 0.0, r1 = 0.0;
-  for (int t = tid; t < RB; t += nthr) {
-    const long long i = rowb + t;
-    if (i < a.n) {
-      double q0, q1;
-      epilogue(a, ctl, i, sP[t], &q0, &q1);
-      r0 = nanmax(r0, q0);
-      r1 = nanmax(r1, q1);
-    }
-  }
+  if (i >= 0 && i < a.n) epilogue<VF>(a, ctl, i, sP[tid], rin, &r0, &r1);
   if (a.stage == ST_S2 || a.stage == ST_S3 || a.stage == ST_RHS) return;
   r0 = wave_nanmax(r0);
   r1 = wave_nanmax(r1);
@@ -378,6 +444,12 @@ __device__ void contract_tail(const Args& a, int rb, double (*sP)[M], int RB) {
   }
 }
 
+// loads the tail row's inputs (issued before the contraction loop)
+__device__ __forceinline__ void prefetch_row(const Args& a, int rb, int RB, RowIn& rin) {
+  const long long i = tail_row(a, rb, RB);
+  if (i >= 0 && i < a.n) load_row(a, a.ctl, i, rin);
+}
+
 // ---------------------------------------------------------------------------
 // FP64 contraction on the vector ALUs.  Wave (wr, wk) owns R rows and the k-slice
 // [wk KW, (wk+1) KW); lanes stride the row with 16-byte loads (2 doubles) and keep
@@ -389,6 +461,8 @@ __device__ __forceinline__ void contract_f64(const Args& a, int rb) {
   __shared__ double sPart[WK][RB][M];
   __shared__ double sP[RB][M];
   if (a.ctl->status != kRunning) return;
+  RowIn rin;
+  prefetch_row(a, rb, RB, rin);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w % WR, wk = w / WR;
   const long long row0 = (long long)rb * RB + wr * R;
@@ -461,7 +535,7 @@ __device__ __forceinline__ void contract_f64(const Args& a, int rb) {
     sP[e / M][e % M] = s;
   }
   __syncthreads();
-  contract_tail<M>(a, rb, sP, RB);
+  contract_tail<M, F_F64>(a, rb, sP, RB, rin);
 }
 
 // ---------------------------------------------------------------------------
@@ -476,6 +550,8 @@ __device__ __forceinline__ void contract_f32(const Args& a, int rb) {
   __shared__ double sPart[WK][RB][NC];
   __shared__ double sP[RB][M];
   if (a.ctl->status != kRunning) return;
+  RowIn rin;
+  prefetch_row(a, rb, RB, rin);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w % WR, wk = w / WR;
   const long long row0 = (long long)rb * RB + wr * R;
@@ -550,7 +626,7 @@ __device__ __forceinline__ void contract_f32(const Args& a, int rb) {
     sP[row][cc] = a.scale * p;
   }
   __syncthreads();
-  contract_tail<M>(a, rb, sP, RB);
+  contract_tail<M, F_F32>(a, rb, sP, RB, rin);
 }
 
 // ---------------------------------------------------------------------------
@@ -601,6 +677,8 @@ __device__ __forceinline__ void contract_mfma(const Args& a, int rb) {
   __shared__ double sPart[WK][RB][NC];
   __shared__ double sP[RB][M];
   if (a.ctl->status != kRunning) return;
+  RowIn rin;
+  prefetch_row(a, rb, RB, rin);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w % WR, wk = w / WR;
   const int r16 = lane & 15, g = lane >> 4;
@@ -624,18 +702,25 @@ __device__ __forceinline__ void contract_mfma(const Args& a, int rb) {
   int kc = 0;
   long long off = 0;  // byte offset from the slice start
   const long long span = (ke > kb) ? (ke - kb) * ES : 0;
-  for (; off + 64LL * U <= span; off += 64LL * U) {
-    u32x4 av[U][RT], bv[U];
+  // Software pipeline over batches of U 64-byte steps: the loads of the next batch
+  // are in flight while the matrix cores consume the current one (two register
+  // buffers, ping-pong).  Same products, same order as a plain loop.
+  constexpr long long BATCH = 64LL * U;
+  const long long full = span / BATCH * BATCH;
+  u32x4 a0[U][RT], b0[U], a1[U][RT], b1[U];
+  auto load = [&](u32x4 (&xa)[U][RT], u32x4 (&xb)[U], long long o) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
-      for (int t = 0; t < RT; ++t) av[u][t] = ldA<NT>((const u32x4*)(ap[t] + off + 64 * u));
-      bv[u] = bcol ? *(const u32x4*)(bp + off + 64 * u) : zero;
+      for (int t = 0; t < RT; ++t) xa[u][t] = ldA<NT>((const u32x4*)(ap[t] + o + 64 * u));
+      xb[u] = bcol ? *(const u32x4*)(bp + o + 64 * u) : zero;
     }
+  };
+  auto step = [&](const u32x4 (&xa)[U][RT], const u32x4 (&xb)[U]) {
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int t = 0; t < RT; ++t) c[t] = mma<FMT>(av[u][t], bv[u], c[t]);
+      for (int t = 0; t < RT; ++t) c[t] = mma<FMT>(xa[u][t], xb[u], c[t]);
     kc += U;
     if (kc >= KC && !a.sum32) {  // FP64 flush (the recipes' single sum keeps FP32 throughout)
 #pragma unroll
@@ -645,6 +730,16 @@ __device__ __forceinline__ void contract_mfma(const Args& a, int rb) {
       }
       kc = 0;
     }
+  };
+  if (full > 0) load(a0, b0, 0);
+  while (off < full) {
+    if (off + BATCH < full) load(a1, b1, off + BATCH);
+    step(a0, b0);
+    off += BATCH;
+    if (off >= full) break;
+    if (off + BATCH < full) load(a0, b0, off + BATCH);
+    step(a1, b1);
+    off += BATCH;
   }
   for (; off < span; off += 64) {
     u32x4 av[RT];
@@ -682,7 +777,7 @@ __device__ __forceinline__ void contract_mfma(const Args& a, int rb) {
     sP[row][cc] = a.scale * p;
   }
   __syncthreads();
-  contract_tail<M>(a, rb, sP, RB);
+  contract_tail<M, FMT>(a, rb, sP, RB, rin);
 }
 
 // ---------------------------------------------------------------------------
@@ -891,6 +986,7 @@ __device__ __forceinline__ void finalize_block(const Args& a, int blk) {
   // issue every independent load at once: the control block, the block maxima and
   // both candidate buffers of this agent (which one is current depends on the decision)
   if (tid < kWords) ((unsigned long long*)&sc)[tid] = ((const unsigned long long*)a.ctl)[tid];
+  const unsigned rflag = (tid == 0) ? *a.rflag : 0u;  // read by thread 0 after the reductions
   double xc[2] = {0.0, 0.0}, kc[2] = {0.0, 0.0};
   if (i < a.n) {
     xc[0] = a.X[0][i];
@@ -926,7 +1022,7 @@ __device__ __forceinline__ void finalize_block(const Args& a, int blk) {
       m1 = nanmax(m1, sR1[w]);
     }
     s_want = 0;
-    if (*a.rflag) c->status = kStatusRange;
+    if (rflag) c->status = kStatusRange;
     else s_want = finalize(a, c, m0, m1, writer, s_feat) ? 1 : 0;
     s_next = (a.stage == ST_INIT && !(c->h0user > 0.0)) ? ST_H0 : ST_S2;
   }
