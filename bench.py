@@ -133,22 +133,41 @@ def cpu_baseline(w, seconds):
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count()
-    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+    threads = min(oracle.threads(), cores)
     kw = dict(A=host(w["A"]), param=host(w["param"]), gain=w["gain"])
     y0 = host(w["y0"])
-    t0 = time.perf_counter()
-    _, st, _ = oracle.bs32_solve(w["kind"], n, y0, 0.0, w["t1"], w["rtol"], w["atol"], i_max=2, **kw)
-    dt = time.perf_counter() - t0
-    per_fev = dt / max(1, st["n_fev"])
-    attempts = max(2, int(seconds / per_fev / 3.0))
-    t0 = time.perf_counter()
-    _, st, _ = oracle.bs32_solve(w["kind"], n, y0, 0.0, w["t1"], w["rtol"], w["atol"], i_max=attempts, **kw)
-    dt = time.perf_counter() - t0
+
+    def sample(budget):
+        t0 = time.perf_counter()
+        _, st, _ = oracle.bs32_solve(w["kind"], n, y0, 0.0, w["t1"], w["rtol"], w["atol"], i_max=2, **kw)
+        per_fev = (time.perf_counter() - t0) / max(1, st["n_fev"])
+        attempts = max(2, int(budget / per_fev / 3.0))
+        t0 = time.perf_counter()
+        _, st, _ = oracle.bs32_solve(w["kind"], n, y0, 0.0, w["t1"], w["rtol"], w["atol"], i_max=attempts, **kw)
+        return st, time.perf_counter() - t0
+
+    st, dt = sample(seconds)
     pairs = st["n_fev"] * float(n) * n
-    return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": min(threads, cores), "kind": "oracle",
+    # the same oracle on one thread, on a shorter sample
+    oracle.set_threads(1)
+    try:
+        st1, dt1 = sample(seconds / 4.0)
+    finally:
+        oracle.set_threads(threads)
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": threads, "kind": "oracle",
             "sample": f"first {st['n_accept'] + st['n_reject']} attempts ({st['n_fev']} RHS evaluations, "
                       f"t reached {st['t_reached']:.3g} of {w['t1']:g}) of the same solve, {dt:.1f} s",
-            "seconds": dt}
+            "seconds": dt, "cpu_model": model, "value_1_thread": st1["n_fev"] * float(n) * n / dt1,
+            "sample_1_thread": f"first {st1['n_accept'] + st1['n_reject']} attempts, {dt1:.1f} s"}
 
 
 def base_line(args, value, ms_per_step, dtype, config):

@@ -21,12 +21,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liborc_bs32.so")
 SRC_PATH = os.path.join(_HERE, "bs32_oracle.c")
 
-OSC2, LCO_PAPER, KURAMOTO, GOODWIN3 = 1, 2, 3, 4
+OSC2, LCO_PAPER, KURAMOTO, GOODWIN3, CLOCK4 = 1, 2, 3, 4, 5
 FMT_F64, FMT_F32, FMT_BF16, FMT_F16, FMT_E4M3 = 0, 1, 2, 3, 4
 (PREC_FP64, PREC_RHS_FP32, PREC_RHS_BF16, PREC_RHS_FP16, PREC_RHS_FP8,
  PREC_PAPER_SINGLE, PREC_PAPER_MIXED1, PREC_PAPER_MIXED2) = range(8)
 OK, MAX_STEPS, MAX_REJECTS, H_TOO_SMALL, NONFINITE = 0, 1, 2, 3, 6
-DIM = {OSC2: 2, LCO_PAPER: 2, KURAMOTO: 1, GOODWIN3: 3}
+DIM = {OSC2: 2, LCO_PAPER: 2, KURAMOTO: 1, GOODWIN3: 3, CLOCK4: 4}
 MLP_IN, MLP_HID, MLP_PARAMS = 9, 64, 4883
 
 
@@ -42,7 +42,7 @@ def build(force: bool = True) -> str:
 
 class System(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n", C.c_int64), ("A", C.c_void_p), ("param", C.c_void_p),
-                ("gain", C.c_double)]
+                ("gain", C.c_double), ("stimulus", C.c_double)]
 
 
 class Options(C.Structure):
@@ -93,6 +93,8 @@ def lib():
         L.orc_dp54_solve.argtypes = [P, P, P, C.c_double, C.c_double, P, P]
         L.orc_bs32_attempt.argtypes = [P, C.c_double, C.c_double, P, P, C.c_double, C.c_double, P, P, P]
         L.orc_bs32_tableau.argtypes = [P, P, P, P]
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_get_threads.restype = C.c_int
         L.orc_mlp_forward.argtypes = [P, P]
         L.orc_mlp_forward.restype = C.c_double
         L.orc_dp54_tableau.argtypes = [P, P, P, P]
@@ -111,30 +113,30 @@ def _ptr(a):
 class _Sys:
     """Keeps the numpy buffers alive while the C struct points at them."""
 
-    def __init__(self, kind, n, A=None, param=None, gain=1.0):
+    def __init__(self, kind, n, A=None, param=None, gain=1.0, stimulus=0.0):
         self.A = None if A is None else _f64(A).reshape(-1)
         self.param = None if param is None else _f64(param)
         if self.A is not None:
             assert self.A.size == n * n
         if self.param is not None:
             assert self.param.size == n
-        self.s = System(kind, n, _ptr(self.A), _ptr(self.param), float(gain))
+        self.s = System(kind, n, _ptr(self.A), _ptr(self.param), float(gain), float(stimulus))
 
     @property
     def ref(self):
         return C.byref(self.s)
 
 
-def rhs(kind, n, y, A=None, param=None, gain=1.0, t=0.0):
-    s = _Sys(kind, n, A, param, gain)
+def rhs(kind, n, y, A=None, param=None, gain=1.0, stimulus=0.0, t=0.0):
+    s = _Sys(kind, n, A, param, gain, stimulus)
     y = _f64(y)
     f = np.empty_like(y)
     assert lib().orc_rhs(s.ref, t, _ptr(y), _ptr(f)) == 0
     return f
 
 
-def rhs_rows(kind, n, rows, y, A_rows=None, param=None, gain=1.0, t=0.0):
-    s = _Sys(kind, n, None, param, gain)
+def rhs_rows(kind, n, rows, y, A_rows=None, param=None, gain=1.0, stimulus=0.0, t=0.0):
+    s = _Sys(kind, n, None, param, gain, stimulus)
     rows = np.ascontiguousarray(rows, dtype=np.int64)
     y = _f64(y)
     Ar = None if A_rows is None else _f64(A_rows).reshape(-1)
@@ -145,16 +147,16 @@ def rhs_rows(kind, n, rows, y, A_rows=None, param=None, gain=1.0, t=0.0):
     return f
 
 
-def rhs_lowp(kind, n, y, fmt, A=None, param=None, gain=1.0, split_fmt=-1, split_terms=0, split_shift=0, t=0.0):
-    s = _Sys(kind, n, A, param, gain)
+def rhs_lowp(kind, n, y, fmt, A=None, param=None, gain=1.0, stimulus=0.0, split_fmt=-1, split_terms=0, split_shift=0, t=0.0):
+    s = _Sys(kind, n, A, param, gain, stimulus)
     y = _f64(y)
     f = np.empty_like(y)
     assert lib().orc_rhs_lowp(s.ref, fmt, split_fmt, split_terms, split_shift, t, _ptr(y), _ptr(f)) == 0
     return f
 
 
-def rhs_recipe(kind, n, y, pF, pS, pG, A=None, param=None, gain=1.0, t=0.0):
-    s = _Sys(kind, n, A, param, gain)
+def rhs_recipe(kind, n, y, pF, pS, pG, A=None, param=None, gain=1.0, stimulus=0.0, t=0.0):
+    s = _Sys(kind, n, A, param, gain, stimulus)
     y = _f64(y)
     f = np.empty_like(y)
     assert lib().orc_rhs_recipe(s.ref, pF, pS, pG, t, _ptr(y), _ptr(f)) == 0
@@ -193,12 +195,12 @@ def options(rtol, atol=None, h_max=0.0, h0=0.0, i_max=0, fixed_step=False, safet
                    facmax, split_terms, split_fmt, split_shift)
 
 
-def bs32_solve(kind, n, y0, t0, t1, rtol, atol=None, A=None, param=None, gain=1.0, mode=PREC_FP64,
+def bs32_solve(kind, n, y0, t0, t1, rtol, atol=None, A=None, param=None, gain=1.0, stimulus=0.0, mode=PREC_FP64,
                trace_cap=0, mlp_w=None, **opt):
     """Adaptive BS3(2)+FSAL solve.  Returns (y, stats dict, trace array or None).
 
     mlp_w: MLP_PARAMS weights of the learned step-size proposer (None: standard controller)."""
-    s = _Sys(kind, n, A, param, gain)
+    s = _Sys(kind, n, A, param, gain, stimulus)
     o = options(rtol, atol, **opt)
     w = None
     if mlp_w is not None:
@@ -210,14 +212,25 @@ def bs32_solve(kind, n, y0, t0, t1, rtol, atol=None, A=None, param=None, gain=1.
     st = Stats()
     tr = (TraceRec * trace_cap)() if trace_cap else None
     tl = C.c_int64(0)
-    lib().orc_bs32_solve(s.ref, C.byref(o), mode, _ptr(y0), t0, t1, _ptr(y), C.byref(st),
-                         C.cast(tr, C.c_void_p) if tr is not None else None, trace_cap, C.byref(tl))
+    rc = lib().orc_bs32_solve(s.ref, C.byref(o), mode, _ptr(y0), t0, t1, _ptr(y), C.byref(st),
+                              C.cast(tr, C.c_void_p) if tr is not None else None, trace_cap, C.byref(tl))
+    if rc < 0:
+        raise ValueError(f"oracle solve rejected its arguments (kind {kind}, mode {mode})")
     trace = None
     if tr is not None:
         trace = np.array([(r.t, r.h, r.err, r.fnorm, r.accepted, r.proposer) for r in tr[: tl.value]],
                          dtype=[("t", "f8"), ("h", "f8"), ("err", "f8"), ("fnorm", "f8"), ("accepted", "i4"),
                                 ("proposer", "i4")])
     return y, st.as_dict(), trace
+
+
+def set_threads(n):
+    """OpenMP threads of the oracle's row loops (n <= 0 keeps the current setting)."""
+    lib().orc_set_threads(int(n))
+
+
+def threads():
+    return int(lib().orc_get_threads())
 
 
 def mlp_forward(w, f):
@@ -228,8 +241,8 @@ def mlp_forward(w, f):
     return lib().orc_mlp_forward(_ptr(w), _ptr(f))
 
 
-def dp54_solve(kind, n, y0, t0, t1, rtol, atol=None, A=None, param=None, gain=1.0, **opt):
-    s = _Sys(kind, n, A, param, gain)
+def dp54_solve(kind, n, y0, t0, t1, rtol, atol=None, A=None, param=None, gain=1.0, stimulus=0.0, **opt):
+    s = _Sys(kind, n, A, param, gain, stimulus)
     o = options(rtol, atol, **opt)
     y0 = _f64(y0)
     y = np.empty_like(y0)
@@ -238,8 +251,8 @@ def dp54_solve(kind, n, y0, t0, t1, rtol, atol=None, A=None, param=None, gain=1.
     return y, st.as_dict()
 
 
-def bs32_attempt(kind, n, t, h, X, K1, rtol, atol=None, A=None, param=None, gain=1.0):
-    s = _Sys(kind, n, A, param, gain)
+def bs32_attempt(kind, n, t, h, X, K1, rtol, atol=None, A=None, param=None, gain=1.0, stimulus=0.0):
+    s = _Sys(kind, n, A, param, gain, stimulus)
     X = _f64(X)
     K1 = _f64(K1)
     Xn = np.empty_like(X)

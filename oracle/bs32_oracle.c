@@ -36,6 +36,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------------ */
 /* Bogacki-Shampine 3(2), Table Butcher-O23                                  */
@@ -84,12 +87,29 @@ void orc_dp54_tableau(double c[7], double a[49], double b[7], double bt[7]) {
   }
 }
 
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+int orc_get_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 int orc_dim(int kind) {
   switch (kind) {
     case ORC_OSC2: return 2;
     case ORC_LCO_PAPER: return 2;
     case ORC_KURAMOTO: return 1;
     case ORC_GOODWIN3: return 3;
+    case ORC_CLOCK4: return 4;
     default: return 0;
   }
 }
@@ -98,6 +118,28 @@ static double weight(const orc_system* s, int64_t i, int64_t j) {
   return s->A ? s->A[i * s->n + j] : 1.0;
 }
 static double agent_param(const orc_system* s, int64_t i) { return s->param ? s->param[i] : 1.0; }
+
+/* eq. (CC) constants (Sec. 2.1): k0, k2, k3, a, b, c, h = 4, epsilon; k1 per agent
+   (the parameter array), theta^h = k1 / (k0 - k1) per agent (reading). */
+#define CC_K0 2.0
+#define CC_K2 0.144832
+#define CC_K3 2.0
+#define CC_A 2.0
+#define CC_B 0.7
+#define CC_C 0.8
+#define CC_EPS 0.228249
+
+/* agent term of eq. (CC) and the prefactor of its pair term, FP64 */
+static void cc_agent(const double* x, double k1, double I0, double* F, double* pre) {
+  const double th = k1 / (CC_K0 - k1);
+  const double x2h = x[1] * x[1] * x[1] * x[1]; /* X_{i,2}^h, h = 4 */
+  const double q = CC_K0 * th / (th + x2h);
+  F[0] = q * (CC_A * x[0] * x[0] + 1.0) - k1 * x[0];
+  F[1] = CC_K2 * (x[0] - x[1]);
+  F[2] = x[2] * (1.0 - x[2] * x[2] / 3.0) - x[3] + I0 * (1.0 - CC_K3 * CC_K3 / (CC_K3 * CC_K3 + x[0] * x[0]));
+  F[3] = CC_EPS * (x[2] + CC_B - CC_C * x[3]);
+  *pre = q * CC_A; /* G_ij,1 = pre * K * arctan(X_j1 - X_i1) */
+}
 
 /* ------------------------------------------------------------------------ */
 /* FP64 right-hand side: agent term F_i plus sum_j M_ij * G_ij (eq. (1)).     */
@@ -144,6 +186,14 @@ int orc_rhs(const orc_system* s, double t, const double* X, double* F) {
         Fi[2] = Xi[1] - b * Xi[2];
         break;
       }
+      case ORC_CLOCK4: {
+        /* eq. (CC): G_ij = (k0 th a / (th + X_i2^h) K arctan(X_j1 - X_i1), 0, 0, 0), M_ij = (1/N, 0, 0, 0) */
+        double pre;
+        cc_agent(Xi, agent_param(s, i), s->stimulus, Fi, &pre);
+        for (int64_t j = 0; j < n; ++j) sum += weight(s, i, j) * (pre * s->gain * atan(X[j * 4] - Xi[0]));
+        Fi[0] += invN * sum;
+        break;
+      }
     }
   }
   return ORC_OK;
@@ -165,13 +215,17 @@ int orc_rhs_rows(const orc_system* s, const int64_t* rows, int64_t nrows, const 
     const double* Ai = Arows ? Arows + r * n : NULL;
     const double invN = 1.0 / (double)n;
     double sum = 0.0;
+    double pre = 0.0;
+    if (s->kind == ORC_CLOCK4) cc_agent(Xi, agent_param(s, i), s->stimulus, Fi, &pre);
     for (int64_t j = 0; j < n; ++j) {
       double w = Ai ? Ai[j] : 1.0;
       if (s->kind == ORC_KURAMOTO) sum += w * sin(X[j] - Xi[0]);
+      else if (s->kind == ORC_CLOCK4) sum += w * (pre * s->gain * atan(X[j * 4] - Xi[0]));
       else sum += w * (X[j * d] - Xi[0]);
     }
     double p = agent_param(s, i);
     switch (s->kind) {
+      case ORC_CLOCK4: Fi[0] += invN * sum; break;
       case ORC_OSC2: Fi[0] = Xi[1]; Fi[1] = -p * p * Xi[0] + invN * sum; break;
       case ORC_LCO_PAPER: Fi[0] = Xi[1] + invN * sum; Fi[1] = -Xi[0]; break;
       case ORC_KURAMOTO: Fi[0] = p + s->gain * invN * sum; break;
@@ -316,6 +370,9 @@ typedef struct {
 
 static int lowp_init(lowp_ctx* c, const orc_system* s, int fmt, int sfmt, int terms, int shift) {
   const int64_t n = s->n;
+  c->Ahat = NULL;
+  c->rsum = NULL;
+  if (s->kind == ORC_CLOCK4) return ORC_EINVAL; /* the arctan pair term has no matrix-vector form */
   c->s = s;
   int dfm, dt, dsh;
   split_defaults(fmt, &dfm, &dt, &dsh);
@@ -435,17 +492,29 @@ int orc_rhs_recipe(const orc_system* s, int pF, int pS, int pG, double t, const 
     float sumf = 0.0f;
     const float invNf = 1.0f / (float)n;
     const double invN = 1.0 / (double)n;
+    /* eq. (CC): the pair term's prefactor k0 th a / (th + X_i2^h) in the G precision */
+    double pre_d = 0.0;
+    float pre_f = 0.0f;
+    if (s->kind == ORC_CLOCK4) {
+      double Ftmp[4];
+      cc_agent(Xi, agent_param(s, i), s->stimulus, Ftmp, &pre_d);
+      const float k1f = (float)agent_param(s, i), x2f = (float)Xi[1];
+      const float thf = k1f / ((float)CC_K0 - k1f);
+      pre_f = (float)CC_K0 * thf / (thf + x2f * x2f * x2f * x2f) * (float)CC_A;
+    }
     for (int64_t j = 0; j < n; ++j) {
       double term;
       if (pG) {
         float g;
         if (s->kind == ORC_KURAMOTO) g = (float)s->gain * sinf((float)X[j] - (float)Xi[0]);
+        else if (s->kind == ORC_CLOCK4) g = pre_f * (float)s->gain * atanf((float)X[j * d] - (float)Xi[0]);
         else g = (float)X[j * d] - (float)Xi[0];
         float m = (float)weight(s, i, j) * invNf;
         term = (double)(m * g);
       } else {
         double g;
         if (s->kind == ORC_KURAMOTO) g = s->gain * sin(X[j] - Xi[0]);
+        else if (s->kind == ORC_CLOCK4) g = pre_d * s->gain * atan(X[j * d] - Xi[0]);
         else g = X[j * d] - Xi[0];
         term = (weight(s, i, j) * invN) * g;
       }
@@ -455,10 +524,20 @@ int orc_rhs_recipe(const orc_system* s, int pF, int pS, int pG, double t, const 
     double inter = pS ? (double)sumf : sumd;
     if (s->kind == ORC_GOODWIN3) inter = pG ? (double)((float)s->gain * (float)inter) : s->gain * inter;
     if (pF) {
-      float xf[3] = {(float)Xi[0], d > 1 ? (float)Xi[1] : 0.f, d > 2 ? (float)Xi[2] : 0.f};
+      float xf[4] = {(float)Xi[0], d > 1 ? (float)Xi[1] : 0.f, d > 2 ? (float)Xi[2] : 0.f, d > 3 ? (float)Xi[3] : 0.f};
       float intf = (float)inter;
       float pf = (float)agent_param(s, i);
       switch (s->kind) {
+        case ORC_CLOCK4: {
+          const float thf = pf / ((float)CC_K0 - pf);
+          const float q = (float)CC_K0 * thf / (thf + xf[1] * xf[1] * xf[1] * xf[1]);
+          const float k3s = (float)CC_K3 * (float)CC_K3;
+          Fi[0] = (q * ((float)CC_A * xf[0] * xf[0] + 1.0f) - pf * xf[0]) + intf;
+          Fi[1] = (float)CC_K2 * (xf[0] - xf[1]);
+          Fi[2] = xf[2] * (1.0f - xf[2] * xf[2] / 3.0f) - xf[3] + (float)s->stimulus * (1.0f - k3s / (k3s + xf[0] * xf[0]));
+          Fi[3] = (float)CC_EPS * (xf[2] + (float)CC_B - (float)CC_C * xf[3]);
+          break;
+        }
         case ORC_OSC2: Fi[0] = xf[1]; Fi[1] = (-pf * pf * xf[0]) + intf; break;
         case ORC_LCO_PAPER: Fi[0] = xf[1] + intf; Fi[1] = -xf[0]; break;
         case ORC_KURAMOTO: Fi[0] = pf + intf; break;
@@ -471,6 +550,12 @@ int orc_rhs_recipe(const orc_system* s, int pF, int pS, int pG, double t, const 
     } else {
       double p = agent_param(s, i);
       switch (s->kind) {
+        case ORC_CLOCK4: {
+          double pre;
+          cc_agent(Xi, p, s->stimulus, Fi, &pre);
+          Fi[0] += inter;
+          break;
+        }
         case ORC_OSC2: Fi[0] = Xi[1]; Fi[1] = -p * p * Xi[0] + inter; break;
         case ORC_LCO_PAPER: Fi[0] = Xi[1] + inter; Fi[1] = -Xi[0]; break;
         case ORC_KURAMOTO: Fi[0] = p + inter; break;

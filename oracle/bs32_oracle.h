@@ -28,6 +28,7 @@ extern "C" {
 #define ORC_LCO_PAPER 2 /* paper Benchmark 1: x' = v + (1/N)sum A_ij(x_j-x_i), v'=-x  d = 2 */
 #define ORC_KURAMOTO 3  /* paper Benchmark 2 with weights A_ij/N                    d = 1 */
 #define ORC_GOODWIN3 4  /* 3-variable Goodwin clock with diffusive x-coupling       d = 3 */
+#define ORC_CLOCK4 5    /* paper Benchmark 3, eq. (CC): clock/cell cycle, arctan coupling  d = 4 */
 
 /* storage formats of the coupling matrix / split vector terms */
 #define ORC_FMT_F64 0
@@ -59,7 +60,8 @@ typedef struct {
   int64_t n;           /* number of agents N */
   const double* A;     /* n*n row-major weights; NULL = all ones (the paper's uniform M_ij = 1/N) */
   const double* param; /* per agent: omega_i (OSC2, KURAMOTO) or b_i (GOODWIN3); NULL = all ones */
-  double gain;         /* K (KURAMOTO), kappa (GOODWIN3); ignored by OSC2 and LCO_PAPER */
+  double gain;         /* K (KURAMOTO, CLOCK4), kappa (GOODWIN3); ignored by OSC2 and LCO_PAPER */
+  double stimulus;     /* I_0 (CLOCK4); ignored by the others */
 } orc_system;
 
 typedef struct {
@@ -92,6 +94,10 @@ typedef struct {
 } orc_trace_rec;
 
 int orc_dim(int kind);
+
+/* OpenMP threads of the row loops (n <= 0 leaves the setting); the count in use. */
+void orc_set_threads(int n);
+int orc_get_threads(void);
 
 /* ---- right-hand sides -------------------------------------------------- */
 /* FP64 pairwise definition: F(t,X) + [M*G](t,X), sums over j in increasing order. */

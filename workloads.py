@@ -30,8 +30,8 @@ import math
 
 import numpy as np
 
-OSC2, LCO_PAPER, KURAMOTO, GOODWIN3 = 1, 2, 3, 4
-DIM = {OSC2: 2, LCO_PAPER: 2, KURAMOTO: 1, GOODWIN3: 3}
+OSC2, LCO_PAPER, KURAMOTO, GOODWIN3, CLOCK4 = 1, 2, 3, 4, 5
+DIM = {OSC2: 2, LCO_PAPER: 2, KURAMOTO: 1, GOODWIN3: 3, CLOCK4: 4}
 
 
 def _rng(seed):
@@ -83,6 +83,21 @@ def goodwin3(n, seed=3000, kappa=0.5, t1=500.0, rtol=1e-6, atol=None):
     y0 = (u * np.array([0.062, 0.310, 1.549])).reshape(-1)
     return dict(kind=GOODWIN3, n=n, A=C, param=b, gain=kappa, y0=y0, t0=0.0, t1=t1, rtol=rtol,
                 atol=rtol if atol is None else atol)
+
+
+def clock4(n, seed=6000, K=1.0, I0=1.5, t1=48.0, rtol=1e-6, atol=None, dense=False):
+    """Paper Benchmark 3 (clock / cell cycle, arctan coupling) as its appendix sets it
+    up: k1 ~ N(0.339278, 0.090909^2) per cell, X_i = (1, 1, -1.19, -0.62) +
+    0.2 (p1..p4) with p ~ U[-0.5, 0.5], uniform weights M_ij = 1/N (dense=True:
+    A ~ U[0,1) with zero diagonal).  K in {0.001, 0.1, 1, 10}, I0 in
+    {0.228249, 1.5, 10}, t1 in [48, 72] in the paper's campaign.  Draw order:
+    k1, initial values, A."""
+    g = _rng(seed)
+    k1 = 0.339278 + 0.090909 * g.standard_normal(n)
+    y0 = (np.array([1.0, 1.0, -1.19, -0.62]) + 0.2 * (g.random((n, 4)) - 0.5)).reshape(-1)
+    A = _zero_diag(g.random((n, n))) if dense else None
+    return dict(kind=CLOCK4, n=n, A=A, param=k1, gain=float(K), stimulus=float(I0), y0=y0, t0=0.0, t1=t1,
+                rtol=rtol, atol=rtol if atol is None else atol)
 
 
 def ensemble_sizes(count, seed=4000, nmin=256, nmax=8192):
