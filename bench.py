@@ -26,6 +26,10 @@ Other measurement configurations, one JSON line each:
   c4  ensemble of 512 Kuramoto instances, N log-uniform in [256, 8192],
       K ~ U[0.5, 4), t in [0, 50], rtol = atol = 1e-6, FP32 / BF16 / FP16
       contractions vs FP64 (errors on a stratified 32-instance subset).
+  f1  the paper's own pairwise benchmark form: clock / cell-cycle model
+      (eq. (CC), arctan pair term, uniform weights) N = 16384, t in [0, 48],
+      K = 1, I0 = 1.5, rtol = atol = 1e-6, FP64 vs the paper's recipes (pair
+      terms in FP32); bound by the vector ALUs, not by memory.
   c5  learned step-size proposer trained on solver traces of the c1-c3 laws,
       run on Kuramoto N = 32768 (t in [0, 50]) and coupled oscillators
       N = 32768 (t in [0, 10]), FP64 coupling, rtol = atol = 1e-7, against the
@@ -61,7 +65,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5", "f1"])
     ap.add_argument("--n", type=int, default=None, help="agents (single-system configs)")
     ap.add_argument("--rtol", type=float, default=None)
     ap.add_argument("--t1", type=float, default=None)
@@ -126,6 +130,8 @@ def cpu_baseline(w, seconds):
     import oracle
 
     def host(x):
+        if x is None:
+            return None
         return x.cpu().numpy() if hasattr(x, "cpu") else np.asarray(x)
 
     n = w["n"]
@@ -134,7 +140,7 @@ def cpu_baseline(w, seconds):
     except AttributeError:
         cores = os.cpu_count()
     threads = min(oracle.threads(), cores)
-    kw = dict(A=host(w["A"]), param=host(w["param"]), gain=w["gain"])
+    kw = dict(A=host(w["A"]), param=host(w["param"]), gain=w["gain"], stimulus=w.get("stimulus", 0.0))
     y0 = host(w["y0"])
 
     def sample(budget):
@@ -176,6 +182,45 @@ def base_line(args, value, ms_per_step, dtype, config):
             "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
 
 
+# vector-ALU peaks of MI355X in lane-operations per second (an FMA counts once):
+# FP32 157.3 TFLOP/s and FP64 78.6 TFLOP/s of fused multiply-adds
+VALU_PEAK = {"f32": 157.3e12 / 2, "f64": 78.6e12 / 2}
+
+
+def valu_ops_per_pair(workload, kernel):
+    """VALU lane-operations per pair evaluation of a pairwise kernel instance, from the
+    committed PMC summary (SQ_INSTS_VALU x 64 / pairs), or None."""
+    path = os.path.join(ROOT, "profiles", f"valu_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernel sources sha256: ([0-9a-f]+)", text)
+    if not m or m.group(1) != sources_hash():
+        return None
+    for line in text.splitlines():
+        cells = [c.strip().strip("`") for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 3 and cells[0] == kernel:
+            try:
+                return float(cells[-1])
+            except ValueError:
+                return None
+    return None
+
+
+def alu_roofline(workload, rh, n):
+    """Pairwise kernels are bound by the vector ALUs: achieved = pair evaluations per
+    launch x VALU lane-operations per pair / launch time, against the FP32 or FP64
+    VALU peak (the pair term's precision)."""
+    prec = "f32" if rh["name"].startswith("paper") else "f64"
+    ops = valu_ops_per_pair(workload, rh["kernel"])
+    pairs_per_s = n * n / (rh["contraction_ms"] * 1e-3)
+    ach = None if ops is None else pairs_per_s * ops
+    return dict(bound="alu", achieved=None if ach is None else round(ach / 1e12, 3),
+                peak=round(VALU_PEAK[prec] / 1e12, 2), unit="T VALU lane-ops/s",
+                frac=None if ach is None else round(ach / VALU_PEAK[prec], 4), traffic=None, kernel=rh["kernel"],
+                pair_evaluations_per_s=pairs_per_s, valu_ops_per_pair=ops, avg_launch_ms=rh["contraction_ms"])
+
+
 def roofline(kms, bytes_per_launch, kernel, traffic):
     gbs = bytes_per_launch / (kms * 1e-3) / 1e9
     return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4),
@@ -195,15 +240,18 @@ def bench_single(args, torch, bs, workload, w, modes, ref_rtol):
     out = torch.empty_like(y0)
 
     def dev_t(x):
+        if x is None:
+            return None
         return x.to(dev) if hasattr(x, "to") else torch.from_numpy(x).to(dev)
 
+    pairwise = w["kind"] == bs.CLOCK4 or bool(w.get("pairwise", False))
     s = bs.Solver(0)
     if args.no_graph:
         s.set_options(use_graph=0)
     A = dev_t(w["A"])
     torch.cuda.synchronize()
     t_setup = time.perf_counter()
-    s.set_system(w["kind"], n, A, dev_t(w["param"]), w["gain"])
+    s.set_system(w["kind"], n, A, dev_t(w["param"]), w["gain"], w.get("stimulus", 0.0), pairwise)
     torch.cuda.synchronize()
     setup_ms = (time.perf_counter() - t_setup) * 1e3
     del A
@@ -225,6 +273,8 @@ def bench_single(args, torch, bs, workload, w, modes, ref_rtol):
     for mode in sorted(set([0] + modes)):
         log(f"mode {bs.MODE_NAMES[mode]}: {args.warmup} warm-up + {args.steps} timed solves")
         fmt_bytes = BYTES[1] if mode >= 5 else BYTES[mode]
+        if pairwise and w["A"] is None:
+            fmt_bytes = 0  # uniform pair weights: no matrix is read
         for _ in range(args.warmup):
             s.solve(y0, 0.0, t1, rtol, mode=mode, out=out)
         torch.cuda.synchronize()
@@ -259,8 +309,11 @@ def bench_single(args, torch, bs, workload, w, modes, ref_rtol):
             r0["final_error"] is None or r["final_error"] is None or r["final_error"] <= 2.0 * r0["final_error"])]
         head = min(ok, key=lambda m: results[m]["time_to_t_end_s"]) if ok else 0
     rh = results[head]
-    traffic = traffic_lookup(workload, "rhs_fp32" if head >= 5 else rh["name"], rh["kernel"])
-    roof = roofline(rh["contraction_ms"], n * n * rh["fmt_bytes"], rh["kernel"], traffic)
+    if pairwise:
+        roof = alu_roofline(workload, rh, n)
+    else:
+        traffic = traffic_lookup(workload, "rhs_fp32" if head >= 5 else rh["name"], rh["kernel"])
+        roof = roofline(rh["contraction_ms"], n * n * rh["fmt_bytes"], rh["kernel"], traffic)
 
     cpu = None
     if not args.no_cpu:
@@ -294,6 +347,13 @@ def bench_single(args, torch, bs, workload, w, modes, ref_rtol):
 
 
 def workload_desc(workload, w):
+    if w["kind"] == 5:
+        return (f"clock4-pairwise N={w['n']} K={w['gain']:g} I0={w['stimulus']:g} weights="
+                f"{'dense' if w['A'] is not None else 'uniform'} t=[0,{w['t1']:g}] rtol=atol={w['rtol']:g} "
+                f"seed={w['seed']}")
+    if w["kind"] == 3 and w.get("pairwise"):
+        return (f"kuramoto-pairwise N={w['n']} K={w['gain']:g} weights={'dense' if w['A'] is not None else 'uniform'} "
+                f"t=[0,{w['t1']:g}] rtol=atol={w['rtol']:g} seed={w['seed']}")
     if w["kind"] == 3:
         return f"kuramoto-dense N={w['n']} K={w['gain']:g} t=[0,{w['t1']:g}] rtol=atol={w['rtol']:g} seed={w['seed']}"
     if w["kind"] == 4:
@@ -557,6 +617,12 @@ def main():
         w["seed"] = 3000
         line = bench_single(args, torch, bs, f"goodwin3_n{n}", w,
                             modes if modes is not None else [0, 1, 2, 3, 4, 5, 6, 7],
+                            args.ref_rtol or 1e-9)
+    elif args.config == "f1":
+        n = args.n or 16384
+        w = workloads.clock4(n, seed=6000, K=1.0, I0=1.5, t1=args.t1 or 48.0, rtol=args.rtol or 1e-6)
+        w["seed"] = 6000
+        line = bench_single(args, torch, bs, f"clock4_n{n}", w, modes if modes is not None else [0, 5, 6, 7],
                             args.ref_rtol or 1e-9)
     elif args.config == "c4":
         line = bench_ensemble(args, torch, bs, modes if modes is not None else [0, 1, 2, 3], args.ref_rtol or 1e-9)

@@ -60,8 +60,14 @@ typedef enum {
                              v' = -x                                                       d = 2 */
   BS32_SYS_KURAMOTO = 3,  /* paper Benchmark 2, eq. (Kuramoto):
                              th' = w_i + (K/N) sum_j A_ij sin(th_j - th_i)                 d = 1 */
-  BS32_SYS_GOODWIN3 = 4   /* x' = 1/(1+z^10) - b_i x + (kappa/N) sum_j A_ij (x_j - x_i),
+  BS32_SYS_GOODWIN3 = 4,  /* x' = 1/(1+z^10) - b_i x + (kappa/N) sum_j A_ij (x_j - x_i),
                              y' = x - b_i y, z' = y - b_i z                                d = 3 */
+  BS32_SYS_CLOCK4 = 5     /* paper Benchmark 3, eq. (CC), clock / cell cycle:
+                             X1' = q (a X1^2 + 1) - k1_i X1 + (K/N) sum_j A_ij q a arctan(X_j1 - X_i1),
+                             q = k0 th / (th + X2^4), th = k1_i / (k0 - k1_i),
+                             X2' = k2 (X1 - X2), X3' = X3 (1 - X3^2/3) - X4 + I0 (1 - k3^2/(k3^2 + X1^2)),
+                             X4' = eps (X3 + b - c X4); k0 = 2, k2 = 0.144832, k3 = 2, a = 2,
+                             b = 0.7, c = 0.8, eps = 0.228249                               d = 4 */
 } bs32_system_kind;
 
 /* Precision of the coupling contraction (Sec. 2.3).  In modes 0-4 the stage
@@ -97,8 +103,15 @@ typedef struct {
   int32_t coupling_on_device; /* ignored (pointers are classified by the runtime); kept for ABI stability */
   int64_t n;                  /* number of agents N >= 1 */
   const double* coupling;     /* N*N row-major FP64 A_ij, or NULL for uniform weights (all ones) */
-  const double* agent_param;  /* N values: w_i (OSC2, KURAMOTO), b_i (GOODWIN3); NULL = all ones */
-  double gain;                /* K (KURAMOTO), kappa (GOODWIN3); ignored by OSC2 and LCO_PAPER */
+  const double* agent_param;  /* N values: w_i (OSC2, KURAMOTO), b_i (GOODWIN3), k1_i (CLOCK4); NULL = ones */
+  double gain;                /* K (KURAMOTO, CLOCK4), kappa (GOODWIN3); ignored by OSC2 and LCO_PAPER */
+  double stimulus;            /* I0 (CLOCK4); ignored by the others */
+  int32_t pairwise;           /* KURAMOTO: 1 = evaluate K sin(th_j - th_i) pair by pair (N^2 sines, the
+                                 paper's own form) instead of the matrix-vector identity; CLOCK4 is
+                                 always pairwise (its arctan pair term has no such identity).  Pairwise
+                                 systems run in modes 0 and 5-7 only, and not in ensembles; with
+                                 coupling == NULL they store no matrix at all. */
+  int32_t reserved;           /* 0 */
 } bs32_system_desc;
 
 typedef struct {

@@ -22,8 +22,8 @@ LIB_PATH = os.path.join(_HERE, "libbs32.so")
 OK, MAX_STEPS, MAX_REJECTS, H_TOO_SMALL, TIMEOUT, TOO_SLOW, NONFINITE, RANGE = 0, 1, 2, 3, 4, 5, 6, 7
 EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSUPPORTED = -1, -2, -3, -4, -5
 # bs32_system_kind
-OSC2, LCO_PAPER, KURAMOTO, GOODWIN3 = 1, 2, 3, 4
-DIM = {OSC2: 2, LCO_PAPER: 2, KURAMOTO: 1, GOODWIN3: 3}
+OSC2, LCO_PAPER, KURAMOTO, GOODWIN3, CLOCK4 = 1, 2, 3, 4, 5
+DIM = {OSC2: 2, LCO_PAPER: 2, KURAMOTO: 1, GOODWIN3: 3, CLOCK4: 4}
 # bs32_precision_mode
 (PREC_FP64, PREC_RHS_FP32, PREC_RHS_BF16, PREC_RHS_FP16, PREC_RHS_FP8_E4M3,
  PREC_PAPER_SINGLE, PREC_PAPER_MIXED1, PREC_PAPER_MIXED2) = range(8)
@@ -35,7 +35,8 @@ MODE_NAMES = {0: "fp64", 1: "rhs_fp32", 2: "rhs_bf16", 3: "rhs_fp16", 4: "rhs_fp
 
 class SystemDesc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("coupling_on_device", C.c_int32), ("n", C.c_int64),
-                ("coupling", C.c_void_p), ("agent_param", C.c_void_p), ("gain", C.c_double)]
+                ("coupling", C.c_void_p), ("agent_param", C.c_void_p), ("gain", C.c_double),
+                ("stimulus", C.c_double), ("pairwise", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -235,15 +236,16 @@ class Solver:
         self._opt = o
 
     # -- system
-    def set_system(self, kind, n, A=None, param=None, gain=1.0):
+    def set_system(self, kind, n, A=None, param=None, gain=1.0, stimulus=0.0, pairwise=False):
         Ab = _Buf(A, n * n)
         pb = _Buf(param, n)
-        d = SystemDesc(kind, 0, n, Ab.ptr, pb.ptr, float(gain))
+        d = SystemDesc(kind, 0, n, Ab.ptr, pb.ptr, float(gain), float(stimulus), int(bool(pairwise)), 0)
         self._check(lib().bs32_set_system(self._ctx, C.byref(d)))
         self.kind, self.n = kind, n
 
     def set_workload(self, w):
-        self.set_system(w["kind"], w["n"], w["A"], w["param"], w["gain"])
+        self.set_system(w["kind"], w["n"], w["A"], w["param"], w["gain"], w.get("stimulus", 0.0),
+                        w.get("pairwise", False))
 
     # -- solve
     def solve(self, y0, t0, t1, rtol, atol=None, mode=PREC_FP64, out=None):
@@ -288,7 +290,8 @@ class Solver:
             Ab = _Buf(w.get("A"), w["n"] * w["n"])
             pb = _Buf(w.get("param"), w["n"])
             keep += [Ab, pb]
-            descs[q] = SystemDesc(w["kind"], 0, w["n"], Ab.ptr, pb.ptr, float(w.get("gain", 1.0)))
+            descs[q] = SystemDesc(w["kind"], 0, w["n"], Ab.ptr, pb.ptr, float(w.get("gain", 1.0)),
+                                  float(w.get("stimulus", 0.0)), int(bool(w.get("pairwise", False))), 0)
         self._check(lib().bs32_set_ensemble(self._ctx, len(systems), descs))
         self.kind = systems[0]["kind"]
         self.ens_n = [int(w["n"]) for w in systems]

@@ -81,6 +81,9 @@ struct bs32_ctx {
   // system
   bool has_sys = false;
   int cur_mode = 0;  // precision mode of the current solve / evaluation
+  int pairwise = 0;  // coupling evaluated pair by pair (clock / cell cycle; Kuramoto on request)
+  double stim = 0.0; // I_0 of the clock / cell-cycle model
+  bool uniform = false;  // pairwise system with uniform weights: no stored matrix
   int kind = 0, d = 0, m = 0;
   long long n = 0, np = 0, ld = 0;
   double gain = 1.0;
@@ -157,6 +160,17 @@ bool is_device_ptr(const void* p) {
 long long roundup(long long x, long long m) { return (x + m - 1) / m * m; }
 
 void ignore(hipError_t) {}
+
+// the context's candidate tiles: pairwise systems have their own kernels
+std::vector<Tile> candidates_for(const bs32_ctx* c, int fmt) {
+  if (c->pairwise) {
+    int cnt = 0;
+    const Tile* t = pair_tile_candidates(&cnt);
+    return std::vector<Tile>(t, t + cnt);
+  }
+  return candidates(fmt);
+}
+
 
 void free_graphs(bs32_ctx* c) {
   for (auto& kv : c->graphs) ignore(hipGraphExecDestroy(kv.second));
@@ -279,6 +293,13 @@ Args make_args(bs32_ctx* c, int fmt, const Geom& g, int stage) {
   a.vterms = vs.terms;
   a.vshift = vs.shift;
   set_recipe(a, c->cur_mode, stage);
+  a.pairwise = c->pairwise;
+  a.stim = c->stim;
+  if (c->pairwise) {  // the pair kernels read the FP64 operand; no split terms
+    a.vfmt = F_F64;
+    a.vterms = 1;
+    a.Vq[0] = a.Vq[1] = nullptr;
+  }
   a.n = c->n;
   a.np = c->np;
   a.ld = c->ld;
@@ -294,7 +315,7 @@ Args make_args(bs32_ctx* c, int fmt, const Geom& g, int stage) {
 
 // store the matrix in a reduced format: A_stored = Q(A / s), s = 2^ceil(log2(max|A| / m))
 bs32_status ensure_packed(bs32_ctx* c, int fmt) {
-  if (c->Aq[fmt]) return BS32_OK;
+  if (c->Aq[fmt] || c->uniform) return BS32_OK;
   const long long count = c->np * c->ld;
   double* Aq = nullptr;
   (void)Aq;
@@ -357,7 +378,7 @@ bs32_status autotune(bs32_ctx* c, int fmt) {
   float best_ms = 1e30f;
   Tile best{};
   bool found = false;
-  for (const Tile& t : candidates(fmt)) {
+  for (const Tile& t : candidates_for(c, fmt)) {
     if (!tile_supported(fmt, c->m, t)) continue;
     Geom g = geometry(c, fmt, t);
     Args a = make_args(c, fmt, g, ST_S2);
@@ -381,9 +402,9 @@ bs32_status autotune(bs32_ctx* c, int fmt) {
   return BS32_OK;
 }
 
-// index of a tile in the format's candidate list (the value options.tile takes)
-int tile_index(int fmt, const Tile& t) {
-  const std::vector<Tile> cand = candidates(fmt);
+// index of a tile in the context's candidate list (the value options.tile takes)
+int tile_index(const bs32_ctx* c, int fmt, const Tile& t) {
+  const std::vector<Tile> cand = candidates_for(c, fmt);
   for (size_t q = 0; q < cand.size(); ++q)
     if (std::memcmp(&cand[q], &t, sizeof(Tile)) == 0) return (int)q;
   return -1;
@@ -393,6 +414,8 @@ int tile_index(int fmt, const Tile& t) {
 bs32_status prepare(bs32_ctx* c, int mode, Geom* g, int* fmt) {
   if (!c->has_sys) return fail(c, BS32_ESTATE, "no system set");
   if (mode < 0 || mode > 7) return fail(c, BS32_EINVAL, "unknown precision mode %d", mode);
+  if (c->pairwise && mode >= BS32_PREC_RHS_FP32 && mode <= BS32_PREC_RHS_FP8_E4M3)
+    return fail(c, BS32_EUNSUPPORTED, "pairwise couplings have no stored-matrix formats (modes 0, 5-7)");
   *fmt = mode_fmt(mode);
   c->cur_mode = mode;
   bs32_status s = ensure_state(c);
@@ -400,7 +423,7 @@ bs32_status prepare(bs32_ctx* c, int mode, Geom* g, int* fmt) {
   s = ensure_packed(c, *fmt);
   if (s != BS32_OK) return s;
   Tile t;
-  const std::vector<Tile> cand = candidates(*fmt);
+  const std::vector<Tile> cand = candidates_for(c, *fmt);
   if (c->opt.tile >= 0) {
     if (c->opt.tile >= (int)cand.size()) return fail(c, BS32_EINVAL, "tile index %d out of range", c->opt.tile);
     t = cand[(size_t)c->opt.tile];
@@ -573,32 +596,39 @@ bs32_status bs32_set_system(bs32_ctx* c, const bs32_system_desc* sd) {
   if (d == 0) return fail(c, BS32_EINVAL, "unknown system kind %d", sd->kind);
   if (sd->n < 1 || sd->n > (1LL << 20)) return fail(c, BS32_EINVAL, "n out of range: %lld", (long long)sd->n);
   if (!std::isfinite(sd->gain)) return fail(c, BS32_EINVAL, "gain must be finite");
+  if (!std::isfinite(sd->stimulus)) return fail(c, BS32_EINVAL, "stimulus must be finite");
+  if (sd->pairwise != 0 && sd->pairwise != 1) return fail(c, BS32_EINVAL, "pairwise must be 0 or 1");
   HIPCHK(c, hipSetDevice(c->device));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   ens_free(c);
   free_system(c);
   c->kind = sd->kind;
   c->d = d;
-  c->m = vcols_of(sd->kind);
+  c->pairwise = (sd->kind == BS32_SYS_CLOCK4 || (sd->kind == BS32_SYS_KURAMOTO && sd->pairwise)) ? 1 : 0;
+  c->stim = sd->stimulus;
+  c->uniform = c->pairwise && sd->coupling == nullptr;
+  c->m = vcols_of(sd->kind, c->pairwise);
   c->n = sd->n;
   c->gain = sd->gain;
   c->np = roundup(c->n, 256);
   c->ld = roundup(c->n, 256);
   bs32_status s = ensure_state(c);
   if (s != BS32_OK) return s;
-  const size_t abytes = sizeof(double) * (size_t)c->np * (size_t)c->ld;
-  HIPCHK(c, hipMalloc(&c->Aq[F_F64], abytes));
-  const double* src = sd->coupling;
   double* tmp = nullptr;
-  if (src && !is_device_ptr(src)) {
-    HIPCHK(c, hipMalloc((void**)&tmp, sizeof(double) * (size_t)(c->n * c->n)));
-    HIPCHK(c, hipMemcpyAsync(tmp, src, sizeof(double) * (size_t)(c->n * c->n), hipMemcpyHostToDevice, c->stream));
-    src = tmp;
+  if (!c->uniform) {  // a pairwise system with uniform weights stores no matrix
+    const size_t abytes = sizeof(double) * (size_t)c->np * (size_t)c->ld;
+    HIPCHK(c, hipMalloc(&c->Aq[F_F64], abytes));
+    const double* src = sd->coupling;
+    if (src && !is_device_ptr(src)) {
+      HIPCHK(c, hipMalloc((void**)&tmp, sizeof(double) * (size_t)(c->n * c->n)));
+      HIPCHK(c, hipMemcpyAsync(tmp, src, sizeof(double) * (size_t)(c->n * c->n), hipMemcpyHostToDevice, c->stream));
+      src = tmp;
+    }
+    HIPCHK(c, launch_pack_f64(src, (double*)c->Aq[F_F64], c->n, c->ld, c->np, src == nullptr ? 1 : 0, c->stream));
+    HIPCHK(c, hipMalloc((void**)&c->rsum[F_F64], sizeof(double) * (size_t)c->np));
+    HIPCHK(c, hipMemsetAsync(c->rsum[F_F64], 0, sizeof(double) * (size_t)c->np, c->stream));
+    HIPCHK(c, launch_rowsum(c->Aq[F_F64], F_F64, 1.0, c->rsum[F_F64], c->n, c->ld, c->stream));
   }
-  HIPCHK(c, launch_pack_f64(src, (double*)c->Aq[F_F64], c->n, c->ld, c->np, src == nullptr ? 1 : 0, c->stream));
-  HIPCHK(c, hipMalloc((void**)&c->rsum[F_F64], sizeof(double) * (size_t)c->np));
-  HIPCHK(c, hipMemsetAsync(c->rsum[F_F64], 0, sizeof(double) * (size_t)c->np, c->stream));
-  HIPCHK(c, launch_rowsum(c->Aq[F_F64], F_F64, 1.0, c->rsum[F_F64], c->n, c->ld, c->stream));
   HIPCHK(c, hipMalloc((void**)&c->param, sizeof(double) * (size_t)c->np));
   std::vector<double> ones;
   if (sd->agent_param) {
@@ -674,13 +704,14 @@ bs32_status bs32_time_contraction(bs32_ctx* c, int mode, int repeat, double* avg
 
 bs32_status bs32_kernel_name(bs32_ctx* c, int mode, int tile, char* buf, size_t cap) {
   if (!c || !buf || cap == 0) return fail(c, BS32_EINVAL, "null argument");
-  if (mode < 0 || mode >= BS32_PREC_PAPER_SINGLE) return fail(c, BS32_EINVAL, "mode %d has no contraction tiles", mode);
+  if (mode < 0 || mode > BS32_PREC_PAPER_MIXED2) return fail(c, BS32_EINVAL, "unknown precision mode %d", mode);
   int m = 0;
   if (c->has_sys) m = c->m;
   else if (c->ens) m = ens_vcols(c);
   else return fail(c, BS32_ESTATE, "no system set");
+  if (c->pairwise && mode != BS32_PREC_FP64) mode = BS32_PREC_PAPER_MIXED2;  // every recipe: the FP32 pair term
   const int fmt = mode_fmt(mode);
-  const std::vector<Tile> cand = candidates(fmt);
+  const std::vector<Tile> cand = candidates_for(c, fmt);
   if (tile < 0 || tile >= (int)cand.size()) return fail(c, BS32_EINVAL, "tile index %d out of range", tile);
   const int r = kernel_name(fmt, m, cand[(size_t)tile], buf, cap);
   if (r < 0) return fail(c, BS32_EUNSUPPORTED, "tile %d is not instantiated for this system", tile);
@@ -692,6 +723,7 @@ bs32_status bs32_get_packed_coupling(bs32_ctx* c, int mode, void* dst, size_t by
   if (!c || !dst || !scale) return fail(c, BS32_EINVAL, "null argument");
   if (!c->has_sys) return fail(c, BS32_ESTATE, "no system set");
   if (mode < 0 || mode > BS32_PREC_RHS_FP8_E4M3) return fail(c, BS32_EINVAL, "mode %d has no packed matrix", mode);
+  if (c->uniform) return fail(c, BS32_ESTATE, "a pairwise system with uniform weights stores no matrix");
   HIPCHK(c, hipSetDevice(c->device));
   const int fmt = mode_fmt(mode);
   const size_t es = fmt_bytes(fmt);
@@ -838,7 +870,7 @@ bs32_status bs32_solve(bs32_ctx* c, const double* y0, double t0, double t1, doub
   c->st.h_min_seen = fin.h_min_seen;
   c->st.err_last = fin.err;
   c->st.n_learned = fin.n_mlp;
-  c->st.tile = tile_index(fmt, g.t);
+  c->st.tile = tile_index(c, fmt, g.t);
   c->st.kernel_ms = kms;
   c->st.status = fin.status;
   c->st.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();

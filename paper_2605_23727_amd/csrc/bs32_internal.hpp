@@ -92,6 +92,8 @@ struct Args {
   int fsingle;            // agent term F and the coupling combination in FP32
   int sum32;              // the interaction sum accumulated in FP32 throughout
   int sstate;             // solution and stage inputs stored in FP32 (Single)
+  int pairwise;           // coupling evaluated pair by pair (g(x_j - x_i)); operand = the coupled component
+  double stim;            // I_0 of the clock / cell-cycle model
 };
 
 // Ensembles: one work item = (instance, row block) for a contraction, or
@@ -109,16 +111,18 @@ struct Group {
 
 // Contraction tile: WR row groups x WK k-slices of waves per workgroup; each wave
 // owns R rows (VALU kernels) or R tiles of 16 rows (matrix-core kernels) and
-// keeps U loads per row in flight.
+// keeps U loads per row in flight.  Pairwise kernels: WR waves of R rows, U
+// column chunks of 64 per step.
 struct Tile {
   int R, WR, WK, U, NT;  // NT: non-temporal loads of A
-  int MM;                // 1: matrix-core kernel (rows come in 16-row tiles)
+  int MM;                // 0: vector-ALU kernel, 1: matrix-core kernel (16-row tiles), 2: pairwise kernel
 };
 const Tile* tile_candidates(int fmt, int* count);
+const Tile* pair_tile_candidates(int* count);
 
 // host launchers (bs32_kernels.hip)
 int dim_of(int kind);
-int vcols_of(int kind);
+int vcols_of(int kind, int pairwise);
 size_t fmt_bytes(int fmt);
 int tile_rows(int fmt, const Tile& t);
 int tile_kalign(int fmt, const Tile& t);

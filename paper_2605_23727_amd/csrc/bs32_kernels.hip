@@ -36,8 +36,14 @@ __device__ __forceinline__ T ldA(const T* p) {
   else return *p;
 }
 
-int dim_of(int kind) { return kind == 1 ? 2 : kind == 2 ? 2 : kind == 3 ? 1 : kind == 4 ? 3 : 0; }
-int vcols_of(int kind) { return kind == 3 ? 2 : 1; }
+int dim_of(int kind) {
+  return kind == 1 ? 2 : kind == 2 ? 2 : kind == 3 ? 1 : kind == 4 ? 3 : kind == 5 ? 4 : 0;
+}
+int vcols_of(int kind, int pairwise) { return (kind == 3 && !pairwise) ? 2 : 1; }
+
+// constants of the clock / cell-cycle model, paper eq. (CC) (Sec. 2.1); k1 is per cell
+constexpr double kCcK0 = 2.0, kCcK2 = 0.144832, kCcK3 = 2.0, kCcA = 2.0, kCcB = 0.7, kCcC = 0.8,
+                 kCcEps = 0.228249;
 size_t fmt_bytes(int fmt) { return fmt == F_F64 ? 8 : fmt == F_F32 ? 4 : (fmt == F_BF16 || fmt == F_F16) ? 2 : 1; }
 
 // ---------------------------------------------------------------------------
@@ -143,11 +149,11 @@ __device__ inline double decode_bits(uint32_t b, FmtDesc f) {
 // ---------------------------------------------------------------------------
 // vector operand of one agent and its split into reduced-format terms
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void vec_of(int kind, double y, double* v) {
-  if (kind == 3) {
+__device__ __forceinline__ void vec_of(const Args& a, double y, double* v) {
+  if (a.kind == 3 && !a.pairwise) {
     sincos(y, &v[0], &v[1]);
   } else {
-    v[0] = y;
+    v[0] = y;  // linear couplings and the pairwise forms read the coupled component itself
   }
 }
 
@@ -198,7 +204,7 @@ __device__ void write_vq_t(const Args& a, void* Vq, long long i, const double* v
 template <int VF>
 __device__ __forceinline__ void write_operand_t(const Args& a, int buf, long long i, double y) {
   double v[2];
-  vec_of(a.kind, y, v);
+  vec_of(a, y, v);
   for (int c = 0; c < a.m; ++c) a.V64[buf][i * a.m + c] = v[c];
   write_vq_t<VF>(a, a.Vq[buf], i, v);
 }
@@ -229,8 +235,18 @@ __device__ __forceinline__ void rhs_agent(const Args& a, const double* y, const 
       k[1] = -y[0];
       break;
     case 3:  // paper eq. (Kuramoto): sum_j A_ij sin(th_j - th_i) = cos th_i (A sin th)_i - sin th_i (A cos th)_i
-      k[0] = p + a.gain * a.invN * (vself[1] * P[0] - vself[0] * P[1]);
+      if (a.pairwise) k[0] = p + a.gain * a.invN * P[0];  // P = sum_j A_ij sin(th_j - th_i) pair by pair
+      else k[0] = p + a.gain * a.invN * (vself[1] * P[0] - vself[0] * P[1]);
       break;
+    case 5: {  // paper eq. (CC): P = sum_j A_ij arctan(X_j1 - X_i1), the pair prefactor depends on X_i2
+      const double th = p / (kCcK0 - p);
+      const double q = kCcK0 * th / (th + y[1] * y[1] * y[1] * y[1]);
+      k[0] = q * (kCcA * y[0] * y[0] + 1.0) - p * y[0] + (q * kCcA) * a.gain * a.invN * P[0];
+      k[1] = kCcK2 * (y[0] - y[1]);
+      k[2] = y[2] * (1.0 - y[2] * y[2] / 3.0) - y[3] + a.stim * (1.0 - kCcK3 * kCcK3 / (kCcK3 * kCcK3 + y[0] * y[0]));
+      k[3] = kCcEps * (y[2] + kCcB - kCcC * y[3]);
+      break;
+    }
     default: {  // Goodwin clock: x' = 1/(1+z^10) - b x + (kappa/N) sum_j C_ij (x_j - x_i)
       const double z2 = y[2] * y[2], z4 = z2 * z2, z8 = z4 * z4;
       k[0] = 1.0 / (1.0 + z8 * z2) - p * y[0] + a.gain * a.invN * (P[0] - y[0] * rs);
@@ -262,8 +278,21 @@ __device__ __forceinline__ void rhs_agent_f32(const Args& a, const double* y, co
       break;
     }
     case 3: {
-      const float inter = g * invN * ((float)vself[1] * (float)P[0] - (float)vself[0] * (float)P[1]);
+      const float inter = a.pairwise ? g * invN * (float)P[0]
+                                     : g * invN * ((float)vself[1] * (float)P[0] - (float)vself[0] * (float)P[1]);
       k[0] = (double)(p + inter);
+      break;
+    }
+    case 5: {
+      const float y1 = (float)y[1], y2 = (float)y[2], y3 = (float)y[3];
+      const float th = p / ((float)kCcK0 - p);
+      const float q = (float)kCcK0 * th / (th + y1 * y1 * y1 * y1);
+      const float k3s = (float)kCcK3 * (float)kCcK3;
+      const float inter = (q * (float)kCcA) * g * invN * (float)P[0];
+      k[0] = (double)((q * ((float)kCcA * y0 * y0 + 1.0f) - p * y0) + inter);
+      k[1] = (double)((float)kCcK2 * (y0 - y1));
+      k[2] = (double)(y2 * (1.0f - y2 * y2 / 3.0f) - y3 + (float)a.stim * (1.0f - k3s / (k3s + y0 * y0)));
+      k[3] = (double)((float)kCcEps * (y2 + (float)kCcB - (float)kCcC * y3));
       break;
     }
     default: {
@@ -295,7 +324,7 @@ __device__ __forceinline__ int vin_of(int stage) { return stage == ST_S3 ? 1 : 0
 // epilogue returns the row's contributions to the block maxima.
 // ---------------------------------------------------------------------------
 struct RowIn {
-  double x[3], xn[3], k1[3], k2[3], k3[3];  // X^n, X^{n+1}, K1, K2, K3 (those the stage reads)
+  double x[4], xn[4], k1[4], k2[4], k3[4];  // X^n, X^{n+1}, K1, K2, K3 (those the stage reads)
   double p, rs, vs[2];                      // parameter, row sum, own vector operand
 };
 
@@ -306,11 +335,11 @@ __device__ __forceinline__ void load_row(const Args& a, const Ctl* ctl, long lon
   const double* K1 = a.Kf[ctl->ki];
   const double* Vin = a.V64[vin_of(st)];
   r.p = a.param[i];
-  r.rs = a.rsum[i];
+  r.rs = a.rsum ? a.rsum[i] : 0.0;  // pairwise systems with uniform weights keep no row sums
   r.vs[0] = Vin[i * a.m];
   r.vs[1] = a.m > 1 ? Vin[i * a.m + 1] : 0.0;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
+  for (int c = 0; c < 4; ++c) {
     r.x[c] = r.xn[c] = r.k1[c] = r.k2[c] = r.k3[c] = 0.0;
     if (c >= a.d) continue;
     r.x[c] = X[c * np + i];
@@ -328,7 +357,7 @@ __device__ void epilogue(const Args& a, const Ctl* ctl, long long i, const doubl
                          double* r1) {
   const int d = a.d;
   const long long np = a.np;
-  double y[3] = {0.0, 0.0, 0.0}, k[3] = {0.0, 0.0, 0.0};
+  double y[4] = {0.0, 0.0, 0.0, 0.0}, k[4] = {0.0, 0.0, 0.0, 0.0};
   const double ha = ctl->ha;
   *r0 = 0.0;
   *r1 = 0.0;
@@ -336,11 +365,11 @@ __device__ void epilogue(const Args& a, const Ctl* ctl, long long i, const doubl
     case ST_INIT:
     case ST_RHS: {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) y[c] = r.x[c];
+      for (int c = 0; c < 4; ++c) y[c] = r.x[c];
       rhs_eval(a, y, P, r.vs, r.p, r.rs, k);
       double* K = a.Kf[ctl->ki];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
+      for (int c = 0; c < 4; ++c) {
         if (c >= d) break;
         K[c * np + i] = k[c];
         const double sc = ctl->atol + ctl->rtol * fabs(y[c]);
@@ -351,10 +380,10 @@ __device__ void epilogue(const Args& a, const Ctl* ctl, long long i, const doubl
     }
     case ST_H0: {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) y[c] = r.x[c] + ctl->h0probe * r.k1[c];
+      for (int c = 0; c < 4; ++c) y[c] = r.x[c] + ctl->h0probe * r.k1[c];
       rhs_eval(a, y, P, r.vs, r.p, r.rs, k);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
+      for (int c = 0; c < 4; ++c) {
         if (c >= d) break;
         const double sc = ctl->atol + ctl->rtol * fabs(r.x[c]);
         *r0 = nanmax(*r0, fabs(k[c] - r.k1[c]) / sc);
@@ -363,10 +392,10 @@ __device__ void epilogue(const Args& a, const Ctl* ctl, long long i, const doubl
     }
     case ST_S2: {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) y[c] = sstore(a, r.x[c] + ha * (kA21 * r.k1[c]));
+      for (int c = 0; c < 4; ++c) y[c] = sstore(a, r.x[c] + ha * (kA21 * r.k1[c]));
       rhs_eval(a, y, P, r.vs, r.p, r.rs, k);
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
+      for (int c = 0; c < 4; ++c)
         if (c < d) a.K2[c * np + i] = k[c];
       write_operand_t<VF>(a, 1, i, sstore(a, r.x[0] + ha * (kA32 * k[0])));  // stage-3 input of this agent
       break;
@@ -374,10 +403,10 @@ __device__ void epilogue(const Args& a, const Ctl* ctl, long long i, const doubl
     case ST_S3: {
       double* Xn = a.X[1 - ctl->xi];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) y[c] = sstore(a, r.x[c] + ha * (kA32 * r.k2[c]));
+      for (int c = 0; c < 4; ++c) y[c] = sstore(a, r.x[c] + ha * (kA32 * r.k2[c]));
       rhs_eval(a, y, P, r.vs, r.p, r.rs, k);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
+      for (int c = 0; c < 4; ++c) {
         if (c >= d) break;
         a.K3[c * np + i] = k[c];
         const double xn = sstore(a, r.x[c] + ha * (kB1 * r.k1[c] + kB2 * r.k2[c] + kB3 * k[c]));
@@ -390,11 +419,11 @@ __device__ void epilogue(const Args& a, const Ctl* ctl, long long i, const doubl
     case ST_S4: {
       double* K4 = a.Kf[1 - ctl->ki];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) y[c] = r.xn[c];
+      for (int c = 0; c < 4; ++c) y[c] = r.xn[c];
       rhs_eval(a, y, P, r.vs, r.p, r.rs, k);
       const double floor_w = ctl->atol / ctl->rtol;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
+      for (int c = 0; c < 4; ++c) {
         if (c >= d) break;
         K4[c * np + i] = k[c];
         // difference of the two solutions formed from the stages (Sec. 2.2)
@@ -781,6 +810,77 @@ __device__ __forceinline__ void contract_mfma(const Args& a, int rb) {
 }
 
 // ---------------------------------------------------------------------------
+// Pairwise coupling, the paper's own form of its benchmarks (Sec. 2.1, eq. (1)):
+// P_i = sum_j w_ij g(x_j - x_i) with one transcendental per pair, g = sin
+// (Kuramoto) or arctan (clock / cell cycle).  Each wave owns R rows and sweeps
+// every column with its 64 lanes; x_j is read once per lane step and shared by
+// the R rows.  G32: the pair term in FP32 (the recipes' "G in single": FP32
+// difference, FP32 function, FP32 weight); otherwise FP64.  DENSE: the weights
+// come from the stored matrix; uniform weights read nothing.  The sum is FP64,
+// or FP32 throughout with sum32.
+// ---------------------------------------------------------------------------
+template <bool ATAN, bool G32>
+__device__ __forceinline__ auto pair_g(double xj, double xi) {
+  if constexpr (G32) {
+    const float d = (float)xj - (float)xi;
+    return ATAN ? atanf(d) : sinf(d);
+  } else {
+    const double d = xj - xi;
+    return ATAN ? atan(d) : sin(d);
+  }
+}
+
+template <bool ATAN, bool G32, bool DENSE, int R, int WV, int UJ>
+__device__ __forceinline__ void contract_pair(const Args& a, int rb) {
+  constexpr int RB = R * WV;
+  __shared__ double sP[RB][1];
+  if (a.ctl->status != kRunning) return;
+  RowIn rin;
+  prefetch_row(a, rb, RB, rin);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const long long row0 = (long long)rb * RB + (long long)w * R;
+  const double* __restrict__ V = a.V64[vin_of(a.stage)];
+  double xi[R], accd[R];
+  float accf[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    xi[r] = (row0 + r < a.n) ? V[row0 + r] : 0.0;
+    accd[r] = 0.0;
+    accf[r] = 0.0f;
+  }
+  for (long long j0 = 0; j0 < a.n; j0 += 64 * UJ) {
+#pragma unroll
+    for (int u = 0; u < UJ; ++u) {
+      const long long j = j0 + 64 * u + lane;
+      if (j < a.n) {
+        const double xj = V[j];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          auto g = pair_g<ATAN, G32>(xj, xi[r]);
+          if constexpr (DENSE) {
+            using WT = decltype(g);
+            g = ((const WT*)a.A)[(row0 + r) * a.ld + j] * g;
+          }
+          if constexpr (G32) {
+            if (a.sum32) accf[r] += g;
+            else accd[r] += (double)g;
+          } else {
+            accd[r] += g;
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const double s = a.sum32 ? (double)wave_sum_f32(accf[r]) : wave_sum(accd[r]);
+    if (lane == 0) sP[w * R + r][0] = a.scale * s;  // the stored matrix's power-of-two scale
+  }
+  __syncthreads();
+  contract_tail<1, F_F64>(a, rb, sP, RB, rin);
+}
+
+// ---------------------------------------------------------------------------
 // prep: vector operand of an evaluation from the current state (used for the
 // first evaluation of a solve, for bs32_rhs and for kernel timing).
 // ---------------------------------------------------------------------------
@@ -836,6 +936,10 @@ __global__ __launch_bounds__(WR* WK * 64) void k_contract_mfma(Args a) {
 template <int FMT, int M, int T, int RT, int WR, int WK, int U, bool NT>
 __global__ __launch_bounds__(WR* WK * 64) void k_group_mfma(Group g) {
   BS32_GROUP_LOOP((contract_mfma<FMT, M, T, RT, WR, WK, U, NT>))
+}
+template <bool ATAN, bool G32, bool DENSE, int R, int WV, int UJ>
+__global__ __launch_bounds__(WV * 64) void k_contract_pair(Args a) {
+  contract_pair<ATAN, G32, DENSE, R, WV, UJ>(a, block_row(a));
 }
 __global__ __launch_bounds__(256) void k_group_prep(Group g) { BS32_GROUP_LOOP(prep_block) }
 
@@ -1179,10 +1283,11 @@ hipError_t launch_set_status(Ctl* c, int code, hipStream_t s) {
   return hipGetLastError();
 }
 
-int tile_rows(int fmt, const Tile& t) { return t.MM ? 16 * t.R * t.WR : t.R * t.WR; }
+int tile_rows(int fmt, const Tile& t) { return t.MM == 1 ? 16 * t.R * t.WR : t.R * t.WR; }
 // columns one wave step covers: 64 lanes x 16 bytes (VALU), 4 lane groups x 16 bytes (matrix cores)
 int tile_kalign(int fmt, const Tile& t) {
-  if (t.MM) return 64 / (int)fmt_bytes(fmt);
+  if (t.MM == 1) return 64 / (int)fmt_bytes(fmt);
+  if (t.MM == 2) return 64;
   return fmt == F_F64 ? 128 : 256;
 }
 
@@ -1199,13 +1304,24 @@ int tile_kalign(int fmt, const Tile& t) {
   X(1, 1, 8, 2, 0) X(1, 1, 8, 4, 0) X(1, 1, 8, 8, 0) X(1, 1, 16, 4, 0) X(1, 1, 16, 8, 0) X(2, 1, 8, 4, 0)  \
   X(1, 1, 4, 8, 0) X(2, 1, 4, 4, 0) X(1, 1, 8, 4, 1) X(1, 1, 16, 4, 1) X(2, 1, 8, 4, 1) X(1, 2, 8, 4, 0)
 
+// pairwise kernels: (R rows per wave, WV waves, UJ column chunks per step)
+#define BS32_PAIR_TILES(X) X(2, 4, 1) X(4, 4, 1) X(8, 4, 1) X(4, 4, 2)
+
 #define BS32_TILE_VALU(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 0},
 #define BS32_TILE_MMA(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 1},
 static const Tile kF64Tiles[] = {BS32_F64_TILES(BS32_TILE_VALU)};
 static const Tile kF32Tiles[] = {BS32_F32_TILES(BS32_TILE_VALU) BS32_MMA_TILES(BS32_TILE_MMA)};
 static const Tile kMmaTiles[] = {BS32_MMA_TILES(BS32_TILE_MMA)};
+#define BS32_TILE_PAIR(R_, WV_, UJ_) Tile{R_, WV_, 1, UJ_, 0, 2},
+static const Tile kPairTiles[] = {BS32_PAIR_TILES(BS32_TILE_PAIR)};
+#undef BS32_TILE_PAIR
 #undef BS32_TILE_VALU
 #undef BS32_TILE_MMA
+
+const Tile* pair_tile_candidates(int* count) {
+  *count = (int)(sizeof(kPairTiles) / sizeof(Tile));
+  return kPairTiles;
+}
 
 const Tile* tile_candidates(int fmt, int* count) {
   if (fmt == F_F64) {
@@ -1268,12 +1384,38 @@ static hipError_t launch_mma(const Launch& L, const Tile& t) {
 #undef X
   return hipErrorInvalidValue;
 }
+template <bool ATAN, bool G32, bool DENSE>
+static hipError_t launch_pair_t(const Launch& L, const Tile& t) {
+#define X(R_, WV_, UJ_)                                                                                  \
+  if (t.R == R_ && t.WR == WV_ && t.U == UJ_) {                                                          \
+    if (L.dry) return hipSuccess;                                                                        \
+    if (L.g) return hipErrorInvalidValue; /* pairwise couplings are not grouped */                      \
+    k_contract_pair<ATAN, G32, DENSE, R_, WV_, UJ_><<<(unsigned)L.a->nrb, WV_ * 64, 0, L.s>>>(*L.a);    \
+    return hipGetLastError();                                                                            \
+  }
+  BS32_PAIR_TILES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+// fmt F_F32 selects the FP32 pair term (the recipes), F_F64 the FP64 one
+static hipError_t launch_pair(const Launch& L, int fmt, const Tile& t) {
+  if (L.dry) return launch_pair_t<false, false, false>(L, t);
+  if (L.g) return hipErrorInvalidValue;
+  const bool atn = L.a->kind == 5, g32 = fmt == F_F32, dense = L.a->A != nullptr;
+  if (atn) {
+    if (g32) return dense ? launch_pair_t<true, true, true>(L, t) : launch_pair_t<true, true, false>(L, t);
+    return dense ? launch_pair_t<true, false, true>(L, t) : launch_pair_t<true, false, false>(L, t);
+  }
+  if (g32) return dense ? launch_pair_t<false, true, true>(L, t) : launch_pair_t<false, true, false>(L, t);
+  return dense ? launch_pair_t<false, false, true>(L, t) : launch_pair_t<false, false, false>(L, t);
+}
 #undef BS32_LAUNCH
 
 static hipError_t dispatch(const Launch& L, int m, int fmt, const Tile& t);
 bool tile_supported(int fmt, int m, const Tile& t);
 
 static hipError_t dispatch(const Launch& L, int m, int fmt, const Tile& t) {
+  if (t.MM == 2) return (fmt == F_F64 || fmt == F_F32) ? launch_pair(L, fmt, t) : hipErrorInvalidValue;
   switch (fmt) {
     case F_F64: return m == 2 ? launch_f64<2>(L, t) : launch_f64<1>(L, t);
     case F_F32:
@@ -1289,6 +1431,9 @@ static hipError_t dispatch(const Launch& L, int m, int fmt, const Tile& t) {
 int kernel_name(int fmt, int m, const Tile& t, char* buf, size_t cap) {
   if (!tile_supported(fmt, m, t)) return -1;
   const char* nt = t.NT ? "true" : "false";
+  if (t.MM == 2)  // the system kind and weights also select the instance: name the family and tile
+    return snprintf(buf, cap, "k_contract_pair<*, %s, *, %d, %d, %d>", fmt == F_F32 ? "true" : "false", t.R, t.WR,
+                    t.U);
   if (fmt == F_F64) return snprintf(buf, cap, "k_contract_f64<%d, %d, %d, %d, %d, %s>", m, t.R, t.WR, t.WK, t.U, nt);
   if (fmt == F_F32 && !t.MM)
     return snprintf(buf, cap, "k_contract_f32<%d, 2, %d, %d, %d, %d, %s>", m, t.R, t.WR, t.WK, t.U, nt);
