@@ -108,3 +108,14 @@ def test_no_storage_formats_for_the_arctan_coupling(orc):
     with pytest.raises(ValueError):
         orc.bs32_solve(orc.CLOCK4, 8, w["y0"], 0.0, 1.0, 1e-6, param=w["param"], gain=w["gain"],
                        stimulus=w["stimulus"], mode=orc.PREC_RHS_BF16)
+
+
+def test_large_populations_keep_theta_positive(orc):
+    # k1 is redrawn into (0, k0), so theta^h = k1 / (k0 - k1) > 0 for every cell
+    # even where the untruncated normal law would put a few cells below zero
+    w = workloads.clock4(16384, seed=6000)
+    k1 = w["param"]
+    assert np.all(k1 > 0.0) and np.all(k1 < K0)
+    assert abs(np.mean(k1) - 0.339278) < 0.005 and abs(np.std(k1) - 0.090909) < 0.005
+    f = orc.rhs(orc.CLOCK4, 16384, w["y0"], param=k1, gain=0.0, stimulus=w["stimulus"])
+    assert np.all(np.isfinite(f))

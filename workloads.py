@@ -87,13 +87,21 @@ def goodwin3(n, seed=3000, kappa=0.5, t1=500.0, rtol=1e-6, atol=None):
 
 def clock4(n, seed=6000, K=1.0, I0=1.5, t1=48.0, rtol=1e-6, atol=None, dense=False):
     """Paper Benchmark 3 (clock / cell cycle, arctan coupling) as its appendix sets it
-    up: k1 ~ N(0.339278, 0.090909^2) per cell, X_i = (1, 1, -1.19, -0.62) +
+    up: k1 ~ N(0.339278, 0.090909^2) per cell (truncated to (0, k0)), X_i = (1, 1, -1.19, -0.62) +
     0.2 (p1..p4) with p ~ U[-0.5, 0.5], uniform weights M_ij = 1/N (dense=True:
     A ~ U[0,1) with zero diagonal).  K in {0.001, 0.1, 1, 10}, I0 in
     {0.228249, 1.5, 10}, t1 in [48, 72] in the paper's campaign.  Draw order:
     k1, initial values, A."""
     g = _rng(seed)
     k1 = 0.339278 + 0.090909 * g.standard_normal(n)
+    # truncated to (0, k0): theta^h = k1 / (k0 - k1) must stay positive, or theta^h +
+    # X_i2^4 can vanish (about one cell in 10^4 falls outside, so the paper's
+    # N <= 1000 rarely meets it); out-of-range draws are drawn again
+    while True:
+        bad = (k1 <= 0.0) | (k1 >= 2.0)
+        if not bad.any():
+            break
+        k1[bad] = 0.339278 + 0.090909 * g.standard_normal(int(bad.sum()))
     y0 = (np.array([1.0, 1.0, -1.19, -0.62]) + 0.2 * (g.random((n, 4)) - 0.5)).reshape(-1)
     A = _zero_diag(g.random((n, n))) if dense else None
     return dict(kind=CLOCK4, n=n, A=A, param=k1, gain=float(K), stimulus=float(I0), y0=y0, t0=0.0, t1=t1,
