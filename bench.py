@@ -30,6 +30,12 @@ Other measurement configurations, one JSON line each:
       (eq. (CC), arctan pair term, uniform weights) N = 16384, t in [0, 48],
       K = 1, I0 = 1.5, rtol = atol = 1e-6, FP64 vs the paper's recipes (pair
       terms in FP32); bound by the vector ALUs, not by memory.
+  f2  synthetic rerun of the paper's accuracy experiments (Sec. 3): normalized
+      final error against rtol (LCO N = 1000, Kuramoto N = 2000, clock model
+      N = 700) and against N, the BS3(2) estimate against the real local error
+      of the linear oscillators (eq. (LCO-Local-Error)), and the beta step-count
+      ratios (eq. (Beta-2MP)), for the paper's Single / Mixed1 / Mixed2 / FP64
+      solvers plus BF16 and e4m3 coupling storage where a matrix exists.
   c5  learned step-size proposer trained on solver traces of the c1-c3 laws,
       run on Kuramoto N = 32768 (t in [0, 50]) and coupled oscillators
       N = 32768 (t in [0, 10]), FP64 coupling, rtol = atol = 1e-7, against the
@@ -65,7 +71,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5", "f1"])
+    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5", "f1", "f2"])
+    ap.add_argument("--tests", type=int, default=6, help="f2: tests per benchmark and tolerance")
+    ap.add_argument("--tests-n", type=int, default=3, help="f2: tests per benchmark and system size")
+    ap.add_argument("--parts", default="rtol,size", help="f2: which sweeps to run (rtol, size)")
     ap.add_argument("--n", type=int, default=None, help="agents (single-system configs)")
     ap.add_argument("--rtol", type=float, default=None)
     ap.add_argument("--t1", type=float, default=None)
@@ -225,6 +234,198 @@ def roofline(kms, bytes_per_launch, kernel, traffic):
     gbs = bytes_per_launch / (kms * 1e-3) / 1e9
     return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4),
                 traffic=traffic, kernel=kernel, bytes_per_launch=bytes_per_launch, avg_launch_ms=kms)
+
+
+# ---------------------------------------------------------------------------
+# f2: synthetic rerun of the paper's accuracy experiments (Sec. 3)
+# ---------------------------------------------------------------------------
+PAPER_SOLVERS = [5, 6, 7, 0]  # Single, Mixed1, Mixed2, FP64 (Sec. 2.3, Table MP-Distrib)
+STORAGE_SOLVERS = [2, 4]      # BF16 and e4m3 coupling storage (a stored matrix of ones)
+
+
+def _pct(v, qs):
+    import numpy as np
+    return [float(x) for x in np.percentile(np.asarray(v, dtype=float), qs)] if len(v) else None
+
+
+class _Campaign:
+    """Runs solves of campaign tests on one library context and keeps the counts."""
+
+    def __init__(self, torch, bs):
+        self.torch, self.bs = torch, bs
+        self.s = bs.Solver(0)
+        self.key = None
+        self.pairs = 0.0
+        self.seconds = 0.0
+        self.solves = 0
+
+    def system(self, w, matrix):
+        """Set w's system: pairwise as the paper writes it, or (matrix=True) as a stored
+        matrix of ones evaluated by the matrix-vector path (storage formats apply there)."""
+        import numpy as np
+        key = (w["seed"], w["n"], w["kind"], matrix)
+        if key == self.key:
+            return
+        n = w["n"]
+        dev = self.torch.device("cuda:0")
+        A = None
+        if matrix or w["kind"] == self.bs.LCO_PAPER:
+            A = self.torch.ones(n * n, dtype=self.torch.float64, device=dev)
+        param = None if w["param"] is None else self.torch.from_numpy(np.asarray(w["param"], float)).to(dev)
+        pairwise = (not matrix) and (w["kind"] == self.bs.CLOCK4 or bool(w.get("pairwise", False)))
+        self.s.set_system(w["kind"], n, A, param, w["gain"], w.get("stimulus", 0.0), pairwise)
+        self.key = key
+        self.y0 = self.torch.from_numpy(np.asarray(w["y0"], float)).to(dev)
+        self.out = self.torch.empty_like(self.y0)
+        self.torch.cuda.synchronize()  # torch's fills are done before the library's stream reads them
+
+    def solve(self, w, mode, rtol, count=True):
+        self.s.solve(self.y0, 0.0, w["t1"], rtol, rtol, mode=mode, out=self.out)
+        st = self.s.stats()
+        if count:
+            self.pairs += st["pair_interactions"]
+            self.seconds += st["solve_ms"] * 1e-3
+            self.solves += 1
+        return self.out.cpu().numpy(), st
+
+
+def bench_accuracy(args, torch, bs):
+    import numpy as np
+    import workloads
+
+    camp = _Campaign(torch, bs)
+    s = camp.s
+    s.set_options(i_max=100000, time_limit_s=30.0)  # the paper's attempt limit; a wall-clock bound per solve
+    dev = torch.device("cuda:0")
+    ref_rtol = args.ref_rtol or 1e-11
+    parts = set(args.parts.split(","))
+    benches = {
+        "lco": dict(make=workloads.lco_campaign, n=1000, seed=7000, rtols=[1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8],
+                    sizes=[100, 500, 1000, 2000, 5000], solvers=PAPER_SOLVERS + STORAGE_SOLVERS),
+        "kuramoto": dict(make=workloads.kuramoto_campaign, n=2000, seed=8000,
+                         rtols=[1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8, 1e-9], sizes=[100, 500, 1000, 2000, 5000],
+                         solvers=PAPER_SOLVERS + STORAGE_SOLVERS),
+        "clock": dict(make=workloads.clock4_campaign, n=700, seed=9000, rtols=[1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8],
+                      sizes=[50, 200, 500, 700, 1000], solvers=PAPER_SOLVERS),
+    }
+    trace_cap = 1 << 17
+    rec_states = 40000
+    rec = None
+
+    def reference(name, w):
+        """Final state of the exact solution (LCO) or of an FP64 solve at ref_rtol, or None."""
+        n = w["n"]
+        camp.system(w, False)
+        if name == "lco":
+            h = torch.from_numpy(np.array([float(w["t1"])])).to(dev)
+            return s.lco_flow(n, camp.y0, h).cpu().numpy()
+        s.set_options(i_max=2_000_000, time_limit_s=60.0)
+        y, st = camp.solve(w, bs.PREC_FP64, ref_rtol, count=False)
+        s.set_options(i_max=100000, time_limit_s=30.0)
+        return y.copy() if st["status"] == 0 else None
+
+    def run_test(name, cfg, w, rtols, solvers, local=False):
+        """Every solver at every tolerance on one test; None if the reference fails."""
+        nonlocal rec
+        t0 = time.perf_counter()
+        ref = reference(name, w)
+        if ref is None:
+            log(f"  {name} N={w['n']} seed {w['seed']}: reference failed, test skipped")
+            return None
+        n = w["n"]
+        res = {}
+        for mode in solvers:
+            matrix = mode in STORAGE_SOLVERS and name == "kuramoto"
+            camp.system(w, matrix)
+            for rtol in rtols:
+                lo = local and name == "lco"
+                if lo:
+                    if rec is None:
+                        rec = torch.empty(rec_states * 2 * n, dtype=torch.float64, device=dev)
+                    s.set_options(trace=1, trace_cap=trace_cap)
+                    s.set_record(rec)
+                y, st = camp.solve(w, mode, rtol)
+                r = dict(status=int(st["status"]), steps=int(st["n_accept"] + st["n_reject"]),
+                         error=float(np.linalg.norm(y - ref) / math.sqrt(n)))
+                if lo:
+                    s.set_record(None)
+                    tr = s.trace(trace_cap)
+                    s.set_options(trace=0)
+                    na = int(st["n_accept"])
+                    if r["status"] == 0 and len(tr) == r["steps"] and na + 1 <= rec_states:
+                        acc = tr[tr["accepted"] == 1]
+                        h = torch.from_numpy(np.ascontiguousarray(acc["h"])).to(dev)
+                        e_real = s.lco_local_error(n, rec, h, 1.0).cpu().numpy()   # delta = Abs / Rel = 1
+                        r["local_estimate"] = float(np.mean(acc["err"]))
+                        r["local_real"] = float(np.mean(e_real))
+                res[(mode, rtol)] = r
+        log(f"  {name} N={n} t1={w['t1']:.1f} seed {w['seed']}: {len(res)} solves, "
+            f"{time.perf_counter() - t0:.1f} s")
+        return res
+
+    out = {}
+    if "rtol" in parts:
+        for name, cfg in benches.items():
+            log(f"f2 error vs rtol: {name} N={cfg['n']}, {args.tests} tests")
+            runs = []
+            for q in range(args.tests):
+                w = cfg["make"](cfg["n"], cfg["seed"] + 10 * q)
+                w["seed"] = cfg["seed"] + 10 * q
+                r = run_test(name, cfg, w, cfg["rtols"], cfg["solvers"], local=True)
+                if r is not None:
+                    runs.append(r)
+            table, beta, local = {}, {}, {}
+            for rtol in cfg["rtols"]:
+                done = [r for r in runs if all(r[(m, rtol)]["status"] == 0 for m in cfg["solvers"])]
+                for m in cfg["solvers"]:
+                    errs = [r[(m, rtol)]["error"] for r in done]
+                    table[f"{bs.MODE_NAMES[m]}@{rtol:g}"] = dict(
+                        tests=len(done), launched=len(runs), median=_pct(errs, [50])[0] if errs else None,
+                        p5=_pct(errs, [5])[0] if errs else None, p95=_pct(errs, [95])[0] if errs else None)
+                    if name == "lco":
+                        le = [(r[(m, rtol)].get("local_estimate"), r[(m, rtol)].get("local_real")) for r in done
+                              if "local_real" in r[(m, rtol)]]
+                        if le:
+                            local[f"{bs.MODE_NAMES[m]}@{rtol:g}"] = dict(
+                                tests=len(le), estimate=_pct([a for a, _ in le], [5, 50, 95]),
+                                real=_pct([b for _, b in le], [5, 50, 95]))
+            for m in cfg["solvers"]:
+                if m == 0:
+                    continue
+                bv = [r[(0, rt)]["steps"] / r[(m, rt)]["steps"] for r in runs for rt in cfg["rtols"]
+                      if all(r[(mm, rt)]["status"] == 0 for mm in cfg["solvers"])]
+                if bv:
+                    beta[bs.MODE_NAMES[m]] = dict(tests=len(bv), quantiles=_pct(bv, [0, 25, 50, 75, 100]))
+            out[name] = dict(n=cfg["n"], error_vs_rtol=table, beta=beta, local_error=local or None)
+    if "size" in parts:
+        for name, cfg in benches.items():
+            rtols = [1e-3, 1e-6, 1e-7, 1e-8]
+            log(f"f2 error vs N: {name} sizes {cfg['sizes']}, {args.tests_n} tests each")
+            bysize = {}
+            for n in cfg["sizes"]:
+                runs = []
+                for q in range(args.tests_n):
+                    w = cfg["make"](n, cfg["seed"] + 500 + 10 * q)
+                    w["seed"] = cfg["seed"] + 500 + 10 * q
+                    r = run_test(name, cfg, w, rtols, PAPER_SOLVERS)
+                    if r is not None:
+                        runs.append(r)
+                for rtol in rtols:
+                    done = [r for r in runs if all(r[(m, rtol)]["status"] == 0 for m in PAPER_SOLVERS)]
+                    for m in PAPER_SOLVERS:
+                        errs = [r[(m, rtol)]["error"] for r in done]
+                        bysize[f"{bs.MODE_NAMES[m]}@{rtol:g}@N={n}"] = dict(
+                            tests=len(done), launched=len(runs), quantiles=_pct(errs, [0, 50, 100]) if errs else None)
+            out.setdefault(name, {})["error_vs_n"] = bysize
+    s.close()
+    value = camp.pairs / camp.seconds if camp.seconds > 0 else 0.0
+    line = base_line(args, value, 1e3 * camp.seconds / max(1, camp.solves), "mixed",
+                     {"workload": f"accuracy campaign (paper Sec. 3, synthetic): LCO / Kuramoto / clock model, "
+                                  f"{args.tests} tests per tolerance, {args.tests_n} per size, reference FP64 "
+                                  f"rtol {ref_rtol:g} (LCO: analytic)", "global_batch": 1, "seq_len": None})
+    line.update({"solves": camp.solves, "solve_seconds": camp.seconds, "accuracy": out,
+                 "roofline": None, "cpu_baseline": None})
+    return line
 
 
 # ---------------------------------------------------------------------------
@@ -624,6 +825,8 @@ def main():
         w["seed"] = 6000
         line = bench_single(args, torch, bs, f"clock4_n{n}", w, modes if modes is not None else [0, 5, 6, 7],
                             args.ref_rtol or 1e-9)
+    elif args.config == "f2":
+        line = bench_accuracy(args, torch, bs)
     elif args.config == "c4":
         line = bench_ensemble(args, torch, bs, modes if modes is not None else [0, 1, 2, 3], args.ref_rtol or 1e-9)
     else:

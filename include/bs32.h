@@ -225,6 +225,39 @@ bs32_status bs32_batch_stats(const bs32_ctx* ctx, int32_t instance, bs32_stats_t
 /* Trace records of the last solve, oldest first; *n_records receives the count copied. */
 bs32_status bs32_get_trace(bs32_ctx* ctx, bs32_trace_rec* buf, size_t cap, size_t* n_records);
 
+/* ---- accuracy diagnostics -----------------------------------------------------
+   The paper studies the solvers' accuracy through the real local error of each
+   step of the coupled linear oscillators (Sec. 2.4, eq. (LCO-Local-Error)): the
+   numerical solution after a step against the analytic solution started from the
+   solution before it.  These calls provide the trajectory and that analytic flow. */
+
+/* Record the solution of later bs32_solve calls into `states` (device memory,
+   cap * d * N doubles, agent-major like y0): slot 0 receives the initial value
+   as the solver holds it (rounded to FP32 in the Single recipe), slot k the
+   state after the k-th accepted step; slots beyond cap - 1 are not written.  A
+   solve ending after n_accept steps fills min(n_accept + 1, cap) slots (the
+   last one equals y_out).  states = NULL or cap = 0 stops recording.  Needs a
+   single system (ESTATE otherwise); bs32_set_system and bs32_set_ensemble stop
+   recording.  The buffer stays owned by the caller and must outlive the solves. */
+bs32_status bs32_set_record(bs32_ctx* ctx, double* states, int64_t cap);
+
+/* Analytic solution of the coupled linear oscillators (paper Benchmark 1,
+   eq. (LCO), uniform weights M_ij = 1/N, in FP64): out[k] = exp(h[k] L) X[k] for
+   `count` states of 2N agent-major doubles each.  X, h (count values) and out
+   are device memory; out must not overlap X.  Runs on the context's stream and
+   returns when done; any system set on the context is left alone. */
+bs32_status bs32_lco_flow(bs32_ctx* ctx, int64_t n, int64_t count, const double* X, const double* h, double* out);
+
+/* Real local error of eq. (LCO-Local-Error) for `steps` consecutive steps of a
+   recorded trajectory: err[k] = max over the 2N components of
+   |states[k+1] - X_ex| / max(|X_ex|, delta), with X_ex = exp(h[k] L) states[k]
+   and delta > 0 (the paper takes Abs / Rel).  states holds steps + 1 states of
+   2N agent-major doubles (as bs32_set_record writes them), h the accepted step
+   sizes (bs32_get_trace records with accepted = 1), err receives `steps`
+   values; all device memory.  A non-finite state gives NaN. */
+bs32_status bs32_lco_local_error(bs32_ctx* ctx, int64_t n, int64_t steps, const double* states, const double* h,
+                                 double delta, double* err);
+
 /* ---- learned step-size proposer ---------------------------------------------
    The paper says only that the error estimate drives the step-size correction
    (Sec. 2.2).  This extension lets a small network propose the next step while

@@ -89,6 +89,10 @@ _SIGS = {
     "bs32_solve_batch": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_int,
                           C.c_void_p, C.c_void_p], C.c_int),
     "bs32_batch_stats": ([C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
+    "bs32_set_record": ([C.c_void_p, C.c_void_p, C.c_int64], C.c_int),
+    "bs32_lco_flow": ([C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "bs32_lco_local_error": ([C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p],
+                             C.c_int),
     "bs32_mlp_features": ([C.c_void_p, C.c_size_t, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "bs32_mlp_train": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_int, C.c_float, C.c_uint64,
                         C.c_void_p, C.c_void_p], C.c_int),
@@ -337,6 +341,43 @@ class Solver:
         n = C.c_size_t(0)
         self._check(lib().bs32_get_trace(self._ctx, buf.ctypes.data, cap, C.byref(n)))
         return buf[: n.value].copy()
+
+    # -- accuracy diagnostics
+    def set_record(self, states):
+        """Record later solves into `states` (a float64 CUDA tensor of cap x d*N values, or
+        None to stop): slot 0 the initial value, slot k the state after k accepted steps."""
+        if states is None:
+            self._check(lib().bs32_set_record(self._ctx, None, 0))
+            self._rec = None
+            return
+        m = DIM[self.kind] * self.n
+        if states.numel() % m != 0:
+            raise ValueError(f"record size {states.numel()} is not a multiple of the state size {m}")
+        b = _Buf(states, writable=True)
+        self._check(lib().bs32_set_record(self._ctx, b.ptr, states.numel() // m))
+        self._rec = states  # the library writes into it; keep it alive
+
+    def lco_flow(self, n, X, h, out=None):
+        """Analytic flow of eq. (LCO) (uniform weights): out[k] = exp(h[k] L) X[k] (CUDA tensors)."""
+        import torch
+        count = h.numel()
+        if out is None:
+            out = torch.empty(count * 2 * n, dtype=torch.float64, device=X.device)
+        xb, hb, ob = _Buf(X, count * 2 * n), _Buf(h, count), _Buf(out, count * 2 * n, writable=True)
+        self._check(lib().bs32_lco_flow(self._ctx, int(n), int(count), xb.ptr, hb.ptr, ob.ptr))
+        return out
+
+    def lco_local_error(self, n, states, h, delta, out=None):
+        """eq. (LCO-Local-Error) of consecutive recorded states (CUDA tensors); returns err [steps]."""
+        import torch
+        steps = h.numel()
+        if out is None:
+            out = torch.empty(steps, dtype=torch.float64, device=h.device)
+        sb, hb, ob = _Buf(states, None), _Buf(h, steps), _Buf(out, steps, writable=True)
+        if states.numel() < (steps + 1) * 2 * n:
+            raise ValueError("states must hold steps + 1 states")
+        self._check(lib().bs32_lco_local_error(self._ctx, int(n), int(steps), sb.ptr, hb.ptr, float(delta), ob.ptr))
+        return out
 
     # -- learned step-size proposer
     def set_controller(self, kind, weights=None):

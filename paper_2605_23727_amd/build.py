@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbs32.so")
-SOURCES = ["bs32_kernels.hip", "bs32_mlp.hip", "bs32_capi.cpp"]
+SOURCES = ["bs32_kernels.hip", "bs32_mlp.hip", "bs32_lco.hip", "bs32_capi.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950",

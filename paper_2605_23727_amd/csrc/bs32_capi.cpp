@@ -121,6 +121,11 @@ struct bs32_ctx {
 
   bs32_stats_t st{};
 
+  // solution record (bs32_set_record): written by solves only
+  double* rec = nullptr;
+  long long rec_cap = 0;
+  bool in_solve = false;
+
   struct EnsembleState* ens = nullptr;  // set by bs32_set_ensemble (bs32_ensemble.inc)
   float* mlp_w = nullptr;               // learned proposer weights (BF16 values), bs32_set_controller
 };
@@ -211,6 +216,8 @@ void free_system(bs32_ctx* c) {
   }
   dfree(c->param);
   c->has_sys = false;
+  c->rec = nullptr;  // the record's layout belongs to the system it was set for
+  c->rec_cap = 0;
 }
 
 bs32_status ensure_state(bs32_ctx* c) {
@@ -295,6 +302,10 @@ Args make_args(bs32_ctx* c, int fmt, const Geom& g, int stage) {
   set_recipe(a, c->cur_mode, stage);
   a.pairwise = c->pairwise;
   a.stim = c->stim;
+  if (c->in_solve && c->rec) {
+    a.rec = c->rec;
+    a.rec_cap = c->rec_cap;
+  }
   if (c->pairwise) {  // the pair kernels read the FP64 operand; no split terms
     a.vfmt = F_F64;
     a.vterms = 1;
@@ -441,7 +452,8 @@ bs32_status prepare(bs32_ctx* c, int mode, Geom* g, int* fmt) {
     c->vq_fmt = *fmt;
   }
   char key[128];
-  snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%p", mode, t.R, t.WR, t.WK, t.U, t.NT, t.MM, (void*)c->trace_d);
+  snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%p/%p/%lld", mode, t.R, t.WR, t.WK, t.U, t.NT, t.MM,
+           (void*)c->trace_d, (void*)(c->in_solve ? c->rec : nullptr), c->rec_cap);
   if (c->graph_key != key) {
     free_graphs(c);
     c->graph_key = key;
@@ -746,6 +758,11 @@ bs32_status bs32_solve(bs32_ctx* c, const double* y0, double t0, double t1, doub
     return fail(c, BS32_EINVAL, "need rtol > 0 and atol >= 0");
   if (!std::isfinite(t0) || !std::isfinite(t1) || !(t1 >= t0)) return fail(c, BS32_EINVAL, "need t1 >= t0");
   HIPCHK(c, hipSetDevice(c->device));
+  struct InSolve {  // the record is written by this solve's kernels only
+    bs32_ctx* c;
+    explicit InSolve(bs32_ctx* x) : c(x) { c->in_solve = true; }
+    ~InSolve() { c->in_solve = false; }
+  } in_solve(c);
   const bs32_options& o = c->opt;
   if (o.trace && c->trace_alloc < o.trace_cap) {
     dfree(c->trace_d);
@@ -875,6 +892,51 @@ bs32_status bs32_solve(bs32_ctx* c, const double* y0, double t0, double t1, doub
   c->st.status = fin.status;
   c->st.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
   return (bs32_status)fin.status;
+}
+
+bs32_status bs32_set_record(bs32_ctx* c, double* states, int64_t cap) {
+  if (!c) return BS32_EINVAL;
+  if (cap < 0) return fail(c, BS32_EINVAL, "record capacity must be >= 0");
+  if (!states || cap == 0) {
+    c->rec = nullptr;
+    c->rec_cap = 0;
+    return BS32_OK;
+  }
+  if (!c->has_sys || c->ens) return fail(c, BS32_ESTATE, "the record needs a single system (bs32_set_system)");
+  if (!is_device_ptr(states)) return fail(c, BS32_EINVAL, "the record must be device memory");
+  c->rec = states;
+  c->rec_cap = cap;
+  return BS32_OK;
+}
+
+bs32_status bs32_lco_flow(bs32_ctx* c, int64_t n, int64_t count, const double* X, const double* h, double* out) {
+  if (!c) return BS32_EINVAL;
+  if (n < 1 || n > (1LL << 30)) return fail(c, BS32_EINVAL, "n out of range: %lld", (long long)n);
+  if (count < 0 || count > 0x7fffffffLL) return fail(c, BS32_EINVAL, "count out of range");
+  if (count == 0) return BS32_OK;
+  if (!X || !h || !out) return fail(c, BS32_EINVAL, "null argument");
+  if (!is_device_ptr(X) || !is_device_ptr(h) || !is_device_ptr(out))
+    return fail(c, BS32_EINVAL, "states, steps and output must be device memory");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, launch_lco_flow(X, h, n, count, out, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return BS32_OK;
+}
+
+bs32_status bs32_lco_local_error(bs32_ctx* c, int64_t n, int64_t steps, const double* states, const double* h,
+                                 double delta, double* err) {
+  if (!c) return BS32_EINVAL;
+  if (n < 1 || n > (1LL << 30)) return fail(c, BS32_EINVAL, "n out of range: %lld", (long long)n);
+  if (steps < 0 || steps > 0x7fffffffLL) return fail(c, BS32_EINVAL, "steps out of range");
+  if (!(delta > 0.0) || !std::isfinite(delta)) return fail(c, BS32_EINVAL, "delta must be positive and finite");
+  if (steps == 0) return BS32_OK;
+  if (!states || !h || !err) return fail(c, BS32_EINVAL, "null argument");
+  if (!is_device_ptr(states) || !is_device_ptr(h) || !is_device_ptr(err))
+    return fail(c, BS32_EINVAL, "states, steps and output must be device memory");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, launch_lco_local_error(states, h, n, steps, delta, err, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return BS32_OK;
 }
 
 bs32_status bs32_get_trace(bs32_ctx* c, bs32_trace_rec* buf, size_t cap, size_t* n_records) {

@@ -94,6 +94,8 @@ struct Args {
   int sstate;             // solution and stage inputs stored in FP32 (Single)
   int pairwise;           // coupling evaluated pair by pair (g(x_j - x_i)); operand = the coupled component
   double stim;            // I_0 of the clock / cell-cycle model
+  double* rec;            // solution record (initial value, then one state per accepted step), or null
+  long long rec_cap;      // states the record holds (d * n agent-major doubles each)
 };
 
 // Ensembles: one work item = (instance, row block) for a contraction, or
@@ -145,6 +147,11 @@ hipError_t launch_mlp_adam(float* master, float* m1, float* m2, float* wq, const
                            float beta1, float beta2, float eps, float bc1, float bc2, hipStream_t s);
 hipError_t launch_bf16_copy(const float* src, float* dst, int n_round, int n, hipStream_t s);
 hipError_t launch_round_f32(double* x, long long n, hipStream_t s);
+// analytic solution of the coupled linear oscillators and the real local error (bs32_lco.hip)
+hipError_t launch_lco_flow(const double* X, const double* h, long long n, long long count, double* out,
+                           hipStream_t s);
+hipError_t launch_lco_local_error(const double* states, const double* h, long long n, long long steps, double delta,
+                                  double* err, hipStream_t s);
 hipError_t launch_to_soa(const double* src, double* dst, long long n, int d, long long np, hipStream_t s);
 hipError_t launch_from_soa(const double* src, double* dst, long long n, int d, long long np, hipStream_t s);
 hipError_t launch_pack_f64(const double* src, double* dst, long long n, long long ld, long long rows, int uniform,

@@ -1104,6 +1104,7 @@ __device__ __forceinline__ void finalize_block(const Args& a, int blk) {
     m1 = nanmax(m1, a.ep1[q]);
   }
   __syncthreads();
+  const long long na0 = sc.n_accept;  // read before workgroup thread 0 updates the copy
   if (sc.status != kRunning) {
     if (writer && tid < kWords) ((unsigned long long*)a.ctl_out)[tid] = ((const unsigned long long*)&sc)[tid];
     return;
@@ -1138,6 +1139,15 @@ __device__ __forceinline__ void finalize_block(const Args& a, int blk) {
     __syncthreads();
   }
   if (writer && tid < kWords) ((unsigned long long*)a.ctl_out)[tid] = ((const unsigned long long*)&sc)[tid];
+  // solution record: the initial value, then the state after every accepted step
+  if (a.rec && i < a.n && (a.stage == ST_INIT || (a.stage == ST_S4 && sc.n_accept != na0))) {
+    const long long slot = (a.stage == ST_INIT) ? 0 : sc.n_accept;
+    if (slot < a.rec_cap) {
+      const double* Xc = a.X[sc.xi];
+      double* dst = a.rec + (slot * a.n + i) * a.d;
+      for (int c = 0; c < a.d; ++c) dst[c] = Xc[c * a.np + i];
+    }
+  }
   if (sc.status != kRunning) return;
   if (i < a.n) {
     const double x = xc[sc.xi], k1 = kc[sc.ki];

@@ -23,6 +23,8 @@ weight matrix A in place of the uniform weights M_ij = 1/N):
                 kappa = 0.5, (x,y,z)_0 = (0.062, 0.310, 1.549) * 2 U[0,1)^3
                 (uniform up to twice the b = 0.2 steady state).
 * ``ensemble``  Kuramoto instances with N log-uniform in [256, 8192], K ~ U[0.5,4).
+* ``clock4``    the paper's Benchmark 3 (clock / cell cycle, arctan pair term).
+* ``*_campaign`` one test of the paper's accuracy campaign per benchmark.
 """
 from __future__ import annotations
 
@@ -106,6 +108,43 @@ def clock4(n, seed=6000, K=1.0, I0=1.5, t1=48.0, rtol=1e-6, atol=None, dense=Fal
     A = _zero_diag(g.random((n, n))) if dense else None
     return dict(kind=CLOCK4, n=n, A=A, param=k1, gain=float(K), stimulus=float(I0), y0=y0, t0=0.0, t1=t1,
                 rtol=rtol, atol=rtol if atol is None else atol)
+
+
+# ---------------------------------------------------------------------------
+# the paper's test campaign (appendix parameter tables), uniform weights.
+# The paper draws its explored parameters from a Sobol set and its initial
+# values with Matlab's generator; here every draw is PCG64 over the same
+# intervals.
+# ---------------------------------------------------------------------------
+def lco_campaign(n, seed):
+    """Benchmark 1 test: T_f from {10 pi, 20 pi, 50 pi}, initial values 2 U(0,1)."""
+    g = _rng(seed)
+    t1 = float(g.choice([10.0, 20.0, 50.0])) * math.pi
+    y0 = g.random(2 * n) * 2.0
+    return dict(kind=LCO_PAPER, n=n, A=None, param=None, gain=1.0, y0=y0, t0=0.0, t1=t1, rtol=1e-6, atol=1e-6)
+
+
+def kuramoto_campaign(n, seed):
+    """Benchmark 2 test, pairwise sin with uniform weights: sigma ~ U(0,1], K ~ U[0, 3 sigma],
+    omega = sigma N(0,1), theta0 = 2 pi U(0,1), T_f = 4 pi / (median|omega| K + 0.001)."""
+    g = _rng(seed)
+    sigma = 1.0 - g.random()
+    K = 3.0 * sigma * g.random()
+    w = sigma * g.standard_normal(n)
+    th0 = g.random(n) * (2.0 * math.pi)
+    t1 = 4.0 * math.pi / (float(np.median(np.abs(w))) * K + 0.001)
+    return dict(kind=KURAMOTO, n=n, A=None, param=w, gain=K, y0=th0, t0=0.0, t1=t1, rtol=1e-6, atol=1e-6,
+                pairwise=True, sigma=sigma)
+
+
+def clock4_campaign(n, seed):
+    """Benchmark 3 test: K from {0.001, 0.1, 1, 10}, I0 from {0.228249, 1.5, 10},
+    T_f ~ U[48, 72], cells drawn as in ``clock4``."""
+    g = _rng(seed)
+    K = float(g.choice([0.001, 0.1, 1.0, 10.0]))
+    I0 = float(g.choice([0.228249, 1.5, 10.0]))
+    t1 = float(g.uniform(48.0, 72.0))
+    return clock4(n, seed=seed + 1, K=K, I0=I0, t1=t1)
 
 
 def ensemble_sizes(count, seed=4000, nmin=256, nmax=8192):
