@@ -36,6 +36,11 @@ Other measurement configurations, one JSON line each:
       of the linear oscillators (eq. (LCO-Local-Error)), and the beta step-count
       ratios (eq. (Beta-2MP)), for the paper's Single / Mixed1 / Mixed2 / FP64
       solvers plus BF16 and e4m3 coupling storage where a matrix exists.
+  f3  parameter sweep on one network: 256 Kuramoto instances sharing one dense
+      coupling (N = 8192, A ~ U[0,1) zero diagonal) with their own K ~ U[0.5, 4),
+      omega ~ N(0,1) and theta0, t in [0, 10], rtol = atol = 1e-6; every stage is
+      one matrix product A [V_1 ... V_256] on the matrix cores (FP64, FP32, BF16,
+      FP16 storage), against plain FP64 single-system solves of the instances.
   c5  learned step-size proposer trained on solver traces of the c1-c3 laws,
       run on Kuramoto N = 32768 (t in [0, 50]) and coupled oscillators
       N = 32768 (t in [0, 10]), FP64 coupling, rtol = atol = 1e-7, against the
@@ -71,7 +76,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5", "f1", "f2"])
+    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5", "f1", "f2", "f3"])
     ap.add_argument("--tests", type=int, default=6, help="f2: tests per benchmark and tolerance")
     ap.add_argument("--tests-n", type=int, default=3, help="f2: tests per benchmark and system size")
     ap.add_argument("--parts", default="rtol,size", help="f2: which sweeps to run (rtol, size)")
@@ -86,7 +91,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB of a plain device copy run first (calibrates PMC byte counters)")
-    ap.add_argument("--instances", type=int, default=512, help="c4: ensemble size")
+    ap.add_argument("--instances", type=int, default=None, help="c4 / f3: ensemble size (512 / 256)")
     ap.add_argument("--no-graph", action="store_true", help="launch attempts directly instead of from HIP graphs")
     return ap.parse_args()
 
@@ -570,7 +575,7 @@ def bench_ensemble(args, torch, bs, modes, ref_rtol):
     import numpy as np
     import workloads
 
-    B = args.instances
+    B = args.instances or 512
     rtol = args.rtol or 1e-6
     t1 = args.t1 or 50.0
     ns, ks = workloads.ensemble_sizes(B, seed=4000)
@@ -676,6 +681,134 @@ def bench_ensemble(args, torch, bs, modes, ref_rtol):
                                                  "failed", "contraction_ms", "contraction_gbs", "tile", "kernel",
                                                  "error_ratio_vs_fp64_median")}
                   for v in results.values()},
+        "roofline": roof,
+        "cpu_baseline": None,
+    })
+    s.close()
+    return line
+
+
+# ---------------------------------------------------------------------------
+# f3: parameter sweep on one network (shared-coupling product)
+# ---------------------------------------------------------------------------
+MFMA_PEAK_TFLOPS = {0: 78.6, 1: 157.3, 2: 2500.0, 3: 2500.0}  # dense matrix-core peaks of MI355X
+
+
+def bench_shared(args, torch, bs, modes, ref_rtol):
+    import numpy as np
+    import workloads
+
+    dev = torch.device("cuda:0")
+    n = args.n or 8192
+    B = args.instances or 256
+    t1 = args.t1 or 10.0
+    rtol = args.rtol or 1e-6
+    base = workloads.kuramoto_device(n, seed=10000, t1=t1, rtol=rtol)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(10001)
+    omega = torch.randn((B, n), generator=gen, device=dev, dtype=torch.float64)
+    theta0 = torch.rand((B, n), generator=gen, device=dev, dtype=torch.float64) * (2.0 * math.pi)
+    gains = np.random.default_rng(10002).uniform(0.5, 4.0, B)
+    torch.cuda.synchronize()
+    s = bs.Solver(0)
+    if args.no_graph:
+        s.set_options(use_graph=0)
+    t0s = time.perf_counter()
+    s.set_shared_ensemble(bs.KURAMOTO, n, B, A=base["A"], params=omega, gains=gains)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0s) * 1e3
+    y0 = theta0.reshape(-1).contiguous()
+    out = torch.empty_like(y0)
+    results = {}
+    for mode in modes:
+        log(f"mode {bs.MODE_NAMES[mode]}: {args.warmup} warm-up + {args.steps} timed batch solves (B={B}, N={n})")
+        for _ in range(args.warmup):
+            s.solve_batch(y0, 0.0, t1, rtol, mode=mode, out=out)
+        times, tot = [], None
+        for _ in range(args.steps):
+            torch.cuda.synchronize()
+            tt = time.perf_counter()
+            _, st, tot = s.solve_batch(y0, 0.0, t1, rtol, mode=mode, out=out)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - tt)
+        kms = s.time_contraction(mode, repeat=20)
+        flops = 2.0 * n * n * B * 2  # the contraction's multiply-adds: N^2 per column, m = 2 columns per instance
+        results[mode] = dict(
+            name=bs.MODE_NAMES[mode], time_to_t_end_s=float(np.median(times)), ms_per_step=1e3 * float(np.mean(times)),
+            pairs_per_s=tot["pair_interactions"] / float(np.median(times)), n_fev=int(tot["n_fev"]),
+            accepted=int(tot["n_accept"]), rejected=int(tot["n_reject"]), failed=int(np.sum(st != 0)),
+            contraction_ms=kms, contraction_tflops=flops / (kms * 1e-3) / 1e12, tile=int(tot["tile"]),
+            kernel=s.kernel_name(mode, tot["tile"]), y=out.clone())
+        log(f"  {results[mode]['time_to_t_end_s'] * 1e3:.1f} ms, {tot['n_accept']} accepted in all, product "
+            f"{kms * 1e3:.1f} us ({results[mode]['contraction_tflops']:.1f} TFLOP/s), {results[mode]['kernel']}")
+    # errors on the first 16 instances against an FP64 batch at ref_rtol
+    errs = None
+    if not args.no_ref:
+        R = min(B, 16)
+        log(f"reference: FP64 shared batch of {R} instances at rtol {ref_rtol:g}")
+        r = bs.Solver(0)
+        r.set_options(i_max=10_000_000)
+        r.set_shared_ensemble(bs.KURAMOTO, n, R, A=base["A"], params=omega[:R].contiguous(), gains=gains[:R])
+        yr, st, _ = r.solve_batch(theta0[:R].reshape(-1).contiguous(), 0.0, t1, ref_rtol, mode=bs.PREC_FP64)
+        r.close()
+        yr = yr.reshape(R, n)
+        errs = {}
+        for mode, res in results.items():
+            Y = res["y"].reshape(B, n)[:R].cpu().numpy()
+            errs[mode] = np.linalg.norm(Y - yr, axis=1) / math.sqrt(n)
+    # the plain FP64 GPU solver, one instance at a time (a bounded sample, scaled to B)
+    log("baseline: plain FP64 single-system solves of 4 instances")
+    single = bs.Solver(0)
+    single.set_system(bs.KURAMOTO, n, base["A"], omega[0].contiguous(), float(gains[0]))
+    tsum, pairs = 0.0, 0.0
+    for q in range(4):
+        single.set_system(bs.KURAMOTO, n, base["A"], omega[q].contiguous(), float(gains[q]))
+        yq = theta0[q].contiguous()
+        oq = torch.empty_like(yq)
+        torch.cuda.synchronize()
+        tt = time.perf_counter()
+        _, sst = single.solve(yq, 0.0, t1, rtol, mode=bs.PREC_FP64, out=oq)
+        torch.cuda.synchronize()
+        tsum += time.perf_counter() - tt
+        pairs += sst["pair_interactions"]
+    single.close()
+    single_s = tsum / 4 * B
+
+    def med_ratio(m):
+        return float(np.median(errs[m] / np.maximum(errs[0], 1e-300)))
+    if args.head is not None:
+        head = args.head
+    else:
+        ok = [m for m, r in results.items() if r["failed"] == 0 and (errs is None or med_ratio(m) <= 2.0)]
+        head = min(ok, key=lambda m: results[m]["time_to_t_end_s"]) if ok else modes[0]
+    rh = results[head]
+    r0 = results.get(0, rh)
+    peak = MFMA_PEAK_TFLOPS[head]
+    roof = {"bound": "mfma", "achieved": round(rh["contraction_tflops"], 2), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(rh["contraction_tflops"] / peak, 4), "traffic": None,
+            "kernel": rh["kernel"] + f" over {B} instances",
+            "flops_per_launch": 2.0 * n * n * B * 2, "avg_launch_ms": rh["contraction_ms"],
+            "executed_flops_per_launch": 2.0 * n * n * B * 2 * (1 if head == 0 else 2)}
+    line = base_line(args, rh["pairs_per_s"], rh["ms_per_step"],
+                     ("f64" if head == 0 else DTYPE[head]) + "+f64-update",
+                     {"workload": f"kuramoto-shared-network B={B} N={n} K=U[0.5,4) omega=N(0,1) t=[0,{t1:g}] "
+                                  f"rtol=atol={rtol:g} seed=10000", "precision_mode": rh["name"],
+                      "global_batch": B, "seq_len": None})
+    line.update({
+        "time_to_t_end_s": rh["time_to_t_end_s"],
+        "fp64_time_to_t_end_s": r0["time_to_t_end_s"],
+        "speedup_vs_fp64": r0["time_to_t_end_s"] / rh["time_to_t_end_s"],
+        "plain_fp64_single_solves_s": single_s,
+        "speedup_vs_plain_fp64_solves": single_s / rh["time_to_t_end_s"],
+        "final_error_median": None if errs is None else float(np.median(errs[head])),
+        "fp64_final_error_median": None if errs is None else float(np.median(errs[0])),
+        "error_ratio_vs_fp64_median": None if errs is None else med_ratio(head),
+        "reference_rtol": None if errs is None else ref_rtol,
+        "setup_ms": setup_ms,
+        "modes": {v["name"]: {k: v[k] for k in ("time_to_t_end_s", "pairs_per_s", "accepted", "rejected", "n_fev",
+                                                 "failed", "contraction_ms", "contraction_tflops", "tile", "kernel")}
+                  | {"error_ratio_vs_fp64_median": None if errs is None else med_ratio(m)}
+                  for m, v in results.items()},
         "roofline": roof,
         "cpu_baseline": None,
     })
@@ -827,6 +960,8 @@ def main():
                             args.ref_rtol or 1e-9)
     elif args.config == "f2":
         line = bench_accuracy(args, torch, bs)
+    elif args.config == "f3":
+        line = bench_shared(args, torch, bs, modes if modes is not None else [0, 1, 2, 3], args.ref_rtol or 1e-9)
     elif args.config == "c4":
         line = bench_ensemble(args, torch, bs, modes if modes is not None else [0, 1, 2, 3], args.ref_rtol or 1e-9)
     else:

@@ -222,6 +222,22 @@ bs32_status bs32_solve_batch(bs32_ctx* ctx, const double* y0_concat, const doubl
    totals: counts summed, time of the whole batch). */
 bs32_status bs32_batch_stats(const bs32_ctx* ctx, int32_t instance, bs32_stats_t* out);
 
+/* Ensemble of `count` instances that share one coupling matrix (parameter sweeps
+   on one network): desc gives the kind (a matrix-vector system: not
+   BS32_SYS_CLOCK4, pairwise = 0), N and the coupling A (host or device, NULL =
+   all ones); params holds count x N agent parameters, instance-major (host or
+   device; NULL = desc->agent_param for every instance, or ones); gains holds
+   count gains (host; NULL = desc->gain).  Each instance keeps its own state,
+   step size, counters and status; bs32_solve_batch and bs32_batch_stats work as
+   for bs32_set_ensemble, and precision modes 0-3 (FP64, FP32, BF16, FP16
+   storage of A) are available.  The contraction of a stage for all instances is
+   one matrix product A [V_1 ... V_B] on the matrix cores (B x m x T operand
+   columns), followed by each instance's row epilogue in the same launch; this
+   is the general model (Sec. 2.1, eq. (1)) evaluated for many parameter sets at
+   once.  Replaces any system or ensemble; count in [1, 65536]. */
+bs32_status bs32_set_shared_ensemble(bs32_ctx* ctx, const bs32_system_desc* desc, int32_t count,
+                                     const double* params, const double* gains);
+
 /* Trace records of the last solve, oldest first; *n_records receives the count copied. */
 bs32_status bs32_get_trace(bs32_ctx* ctx, bs32_trace_rec* buf, size_t cap, size_t* n_records);
 

@@ -86,6 +86,7 @@ _SIGS = {
     "bs32_kernel_name": ([C.c_void_p, C.c_int, C.c_int, C.c_char_p, C.c_size_t], C.c_int),
     "bs32_get_packed_coupling": ([C.c_void_p, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "bs32_set_ensemble": ([C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
+    "bs32_set_shared_ensemble": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p], C.c_int),
     "bs32_solve_batch": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_int,
                           C.c_void_p, C.c_void_p], C.c_int),
     "bs32_batch_stats": ([C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
@@ -299,6 +300,19 @@ class Solver:
         self._check(lib().bs32_set_ensemble(self._ctx, len(systems), descs))
         self.kind = systems[0]["kind"]
         self.ens_n = [int(w["n"]) for w in systems]
+        self.n = None
+
+    def set_shared_ensemble(self, kind, n, count, A=None, params=None, gains=None):
+        """`count` instances sharing one coupling A (n x n); params: count x n agent
+        parameters (or None), gains: count values (or None = 1)."""
+        Ab = _Buf(A, n * n)
+        pb = _Buf(params, count * n) if params is not None else _Buf(None)
+        g = None if gains is None else np.ascontiguousarray(np.broadcast_to(np.asarray(gains, np.float64), (count,)))
+        d = SystemDesc(kind, 0, n, Ab.ptr, None, 1.0, 0.0, 0, 0)
+        self._check(lib().bs32_set_shared_ensemble(self._ctx, C.byref(d), int(count), pb.ptr,
+                                                   None if g is None else g.ctypes.data))
+        self.kind = kind
+        self.ens_n = [int(n)] * int(count)
         self.n = None
 
     def solve_batch(self, y0_concat, t0, t1, rtol, atol=None, mode=PREC_FP64, out=None):

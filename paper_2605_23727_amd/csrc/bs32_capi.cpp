@@ -127,6 +127,7 @@ struct bs32_ctx {
   bool in_solve = false;
 
   struct EnsembleState* ens = nullptr;  // set by bs32_set_ensemble (bs32_ensemble.inc)
+  bool shared_ens = false;              // the ensemble shares one coupling (bs32_set_shared_ensemble)
   float* mlp_w = nullptr;               // learned proposer weights (BF16 values), bs32_set_controller
 };
 void ens_free(bs32_ctx* c);
@@ -168,6 +169,11 @@ void ignore(hipError_t) {}
 
 // the context's candidate tiles: pairwise systems have their own kernels
 std::vector<Tile> candidates_for(const bs32_ctx* c, int fmt) {
+  if (c->shared_ens) {
+    int cnt = 0;
+    const Tile* t = shared_tile_candidates(&cnt);
+    return std::vector<Tile>(t, t + cnt);
+  }
   if (c->pairwise) {
     int cnt = 0;
     const Tile* t = pair_tile_candidates(&cnt);

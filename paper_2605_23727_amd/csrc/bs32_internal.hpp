@@ -111,16 +111,34 @@ struct Group {
   int stage, par;
 };
 
+// Shared-coupling ensembles: B instances with one coupling matrix; the stage
+// contraction of all of them is one matrix product A [V_1 ... V_B].
+struct Shared {
+  const void* A;          // the shared coupling, np x ld in the storage format
+  const Args* inst;       // per-instance arguments [(instance * kStages + stage) * 2 + parity]
+  const void* Bop[2];     // operand pools by buffer: split terms [Bpad][m T][ld] (FP64: [Bpad][ld][m])
+  long long ld, np;
+  int stage, par;
+  int B;                  // instances (the pools hold whole column tiles of zero-padded instances beyond)
+  int nrb, ncb;           // row and column blocks of the product
+  double scale;           // power-of-two scale of the stored coupling
+  int vshift;             // exponent shift between the operand's split terms
+};
+
 // Contraction tile: WR row groups x WK k-slices of waves per workgroup; each wave
 // owns R rows (VALU kernels) or R tiles of 16 rows (matrix-core kernels) and
 // keeps U loads per row in flight.  Pairwise kernels: WR waves of R rows, U
 // column chunks of 64 per step.
 struct Tile {
   int R, WR, WK, U, NT;  // NT: non-temporal loads of A
-  int MM;                // 0: vector-ALU kernel, 1: matrix-core kernel (16-row tiles), 2: pairwise kernel
+  int MM;                // 0: vector-ALU kernel, 1: matrix-core kernel (16-row tiles), 2: pairwise kernel,
+                         // 3: shared-coupling product (R: 16-row tiles per wave of 4, U: 16-column tiles)
 };
 const Tile* tile_candidates(int fmt, int* count);
 const Tile* pair_tile_candidates(int* count);
+const Tile* shared_tile_candidates(int* count);
+// columns of the shared product one instance occupies in a storage format (0: not supported)
+int shared_cols(int fmt, int m);
 
 // host launchers (bs32_kernels.hip)
 int dim_of(int kind);
@@ -138,6 +156,7 @@ hipError_t launch_contract(const Args& a, int fmt, const Tile& t, hipStream_t s)
 hipError_t launch_group_contract(const Group& g, int m, int fmt, const Tile& t, unsigned grid, hipStream_t s);
 hipError_t launch_group_prep(const Group& g, unsigned grid, hipStream_t s);
 hipError_t launch_group_finalize(const Group& g, unsigned grid, hipStream_t s);
+hipError_t launch_shared_contract(const Shared& sh, int m, int fmt, const Tile& t, hipStream_t s);
 
 // learned proposer training (bs32_mlp.hip)
 hipError_t launch_mlp_grad(const float* W, const float* X, const float* Y, const int* idx, int nb, float inv_n,

@@ -943,6 +943,271 @@ __global__ __launch_bounds__(WV * 64) void k_contract_pair(Args a) {
 }
 __global__ __launch_bounds__(256) void k_group_prep(Group g) { BS32_GROUP_LOOP(prep_block) }
 
+// ---------------------------------------------------------------------------
+// Shared-coupling ensembles: B instances with one coupling matrix A, each with
+// its own parameters, gain, state, step size and status.  The contraction of a
+// stage for all of them is one matrix product P = A [V_1 ... V_B] of N rows and
+// B C columns (C = m T operand columns per instance) on the matrix cores, and
+// each instance's row epilogue follows in the same launch.
+//
+// Workgroup tile: BM = 64 RT rows (four waves of 16 RT rows) by BN = 16 CT
+// columns (IB = BN / C instances).  A fragments go from memory straight into
+// the registers of the wave that owns those rows (A is read once per column
+// block); the operand tile of each 256-byte k-chunk is staged in LDS, double
+// buffered, and shared by the four waves.  BF16 / FP16 / FP32 storage: FP32
+// accumulation in the matrix core within a chunk, FP64 across chunks; FP64
+// storage: FP64 matrix cores throughout.  Workgroups are ordered so that the
+// eight XCDs each take a contiguous range of row blocks (the column blocks of a
+// row block share its A rows in that XCD's L2).
+// ---------------------------------------------------------------------------
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <int FMT>
+struct ShAcc {
+  using T = f32x4;
+};
+template <>
+struct ShAcc<F_F64> {
+  using T = f64x4;
+};
+
+template <int FMT>
+__device__ __forceinline__ typename ShAcc<FMT>::T sh_mma(u32x4 av, u32x4 bv, typename ShAcc<FMT>::T c) {
+  if constexpr (FMT == F_F64) {
+    // two 16x16x4 steps; lane group g holds k = 2g, 2g+1 of the 8-wide step on both operands
+    const f64x2 fa = __builtin_bit_cast(f64x2, av), fb = __builtin_bit_cast(f64x2, bv);
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[0], fb[0], c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(fa[1], fb[1], c, 0, 0, 0);
+  } else {
+    return mma<FMT>(av, bv, c);
+  }
+}
+
+constexpr int kShChunk = 256;          // bytes of k per operand column and chunk
+constexpr int kShPitch = kShChunk + 16;  // LDS pitch of one operand column (spreads the banks)
+
+template <int FMT, int RT, int CT>
+constexpr int sh_lds_bytes() {
+  constexpr int BM = 64 * RT, BN = 16 * CT;
+  constexpr int tiles = 2 * BN * kShPitch, part = BM * (BN + 1) * 8;
+  return tiles > part ? tiles : part;
+}
+
+int shared_cols(int fmt, int m) {
+  if (fmt == F_F64) return m;
+  if (fmt == F_F32 || fmt == F_BF16 || fmt == F_F16) return 2 * m;  // two split terms
+  return 0;  // e4m3's three terms do not tile the product's columns
+}
+
+template <int FMT, int M, int RT, int CT>
+__global__ __launch_bounds__(256) void k_shared_contract(Shared sh) {
+  constexpr int ES = FMT == F_F64 ? 8 : FMT == F_F32 ? 4 : 2;
+  constexpr int T = FMT == F_F64 ? 1 : 2;
+  constexpr int C = M * T;
+  constexpr int BM = 64 * RT, BN = 16 * CT, IB = BN / C;
+  constexpr int NSTEP = kShChunk / 64;  // 64-byte lane-group steps per chunk
+  constexpr int UNITS = BN * kShChunk / 16 / 256;  // 16-byte operand loads per thread and chunk
+  static_assert(BN % C == 0, "whole instances per column block");
+  using Acc = typename ShAcc<FMT>::T;
+  __shared__ __align__(16) char smem[sh_lds_bytes<FMT, RT, CT>()];
+  __shared__ double sRed0[4], sRed1[4];
+
+  // XCD-aware tile order: blockIdx.x % 8 selects the XCD
+  const int total = sh.nrb * sh.ncb;
+  const int per = (total + 7) / 8;
+  const int lin = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (lin >= total) return;
+  const int rb = lin / sh.ncb, cb = lin % sh.ncb;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int stage = sh.stage;
+
+  // nothing to do when every instance of the column block has finished
+  {
+    int live = 0;
+    if (tid < IB) {
+      const int b = cb * IB + tid;
+      if (b < sh.B) live = sh.inst[((size_t)b * kStages + stage) * 2 + sh.par].ctl->status == kRunning;
+    }
+    if (!__syncthreads_or(live)) return;
+  }
+
+  const long long ld = sh.ld;
+  const long long row_base = (long long)rb * BM + w * 16 * RT;
+  const char* ap[RT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) ap[t] = (const char*)sh.A + ((row_base + 16 * t + r16) * ld) * ES + g * 16;
+  const char* Bg = (const char*)sh.Bop[vin_of(stage)];
+  const long long nchunk = ld * ES / kShChunk;
+
+  // operand unit q of this thread in a chunk: global source and LDS destination(s)
+  auto load_units = [&](u32x4 (&v)[UNITS], long long ch) {
+#pragma unroll
+    for (int q = 0; q < UNITS; ++q) {
+      const int u = tid + 256 * q;
+      if constexpr (FMT == F_F64 && M == 2) {
+        // [b][ld][2] doubles: 16 bytes = both columns of one k
+        const int ib = u / 32, part = u % 32;
+        const long long b = (long long)cb * IB + ib;
+        v[q] = *(const u32x4*)(Bg + ((b * ld + ch * (kShChunk / 8) + part) * 2) * 8);
+      } else {
+        const int col = u / 16, part = u % 16;
+        v[q] = *(const u32x4*)(Bg + ((long long)(cb * BN + col) * ld) * ES + ch * kShChunk + part * 16);
+      }
+    }
+  };
+  auto store_units = [&](const u32x4 (&v)[UNITS], int buf) {
+    char* base = smem + buf * BN * kShPitch;
+#pragma unroll
+    for (int q = 0; q < UNITS; ++q) {
+      const int u = tid + 256 * q;
+      if constexpr (FMT == F_F64 && M == 2) {
+        const int ib = u / 32, part = u % 32;
+        const f64x2 x = __builtin_bit_cast(f64x2, v[q]);
+        *(double*)(base + (2 * ib) * kShPitch + part * 8) = x[0];
+        *(double*)(base + (2 * ib + 1) * kShPitch + part * 8) = x[1];
+      } else {
+        const int col = u / 16, part = u % 16;
+        *(u32x4*)(base + col * kShPitch + part * 16) = v[q];
+      }
+    }
+  };
+  auto load_a = [&](u32x4 (&av)[NSTEP][RT], long long ch) {
+#pragma unroll
+    for (int s = 0; s < NSTEP; ++s)
+#pragma unroll
+      for (int t = 0; t < RT; ++t) av[s][t] = *(const u32x4*)(ap[t] + ch * kShChunk + s * 64);
+  };
+
+  Acc c[RT][CT];
+  double dacc[RT][CT][4];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int u = 0; u < CT; ++u) {
+      c[t][u] = Acc{0, 0, 0, 0};
+      for (int i = 0; i < 4; ++i) dacc[t][u][i] = 0.0;
+    }
+
+  u32x4 bu[UNITS];
+  u32x4 a0[NSTEP][RT], a1[NSTEP][RT];
+  load_units(bu, 0);
+  load_a(a0, 0);
+  store_units(bu, 0);
+  __syncthreads();
+  auto compute = [&](const u32x4 (&av)[NSTEP][RT], int buf) {
+    const char* base = smem + buf * BN * kShPitch;
+#pragma unroll
+    for (int s = 0; s < NSTEP; ++s) {
+#pragma unroll
+      for (int u = 0; u < CT; ++u) {
+        const u32x4 bv = *(const u32x4*)(base + (16 * u + r16) * kShPitch + s * 64 + g * 16);
+#pragma unroll
+        for (int t = 0; t < RT; ++t) c[t][u] = sh_mma<FMT>(av[s][t], bv, c[t][u]);
+      }
+    }
+    if constexpr (FMT != F_F64) {  // FP64 across chunks
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int u = 0; u < CT; ++u) {
+          for (int i = 0; i < 4; ++i) dacc[t][u][i] += (double)c[t][u][i];
+          c[t][u] = Acc{0, 0, 0, 0};
+        }
+    }
+  };
+  for (long long ch = 0; ch < nchunk; ch += 2) {
+    // chunk ch from buffer 0 / registers a0 while chunk ch+1 is fetched, then the reverse
+    const bool more1 = ch + 1 < nchunk;
+    if (more1) {
+      load_units(bu, ch + 1);
+      load_a(a1, ch + 1);
+    }
+    compute(a0, 0);
+    if (!more1) break;
+    store_units(bu, 1);
+    __syncthreads();
+    const bool more2 = ch + 2 < nchunk;
+    if (more2) {
+      load_units(bu, ch + 2);
+      load_a(a0, ch + 2);
+    }
+    compute(a1, 1);
+    if (!more2) break;
+    store_units(bu, 0);
+    __syncthreads();
+  }
+  __syncthreads();  // every wave is done with the operand tiles: the LDS now takes P
+
+  // P tile [BM][BN] in FP64.  Lane (r16, g) holds column r16 of each 16x16 tile: rows
+  // 4g + i for the FP32-output instructions, rows g + 4i for the FP64 one (measured)
+  double* sP = (double*)smem;
+  constexpr int PP = BN + 1;
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int u = 0; u < CT; ++u)
+      for (int i = 0; i < 4; ++i) {
+        const int rr = (FMT == F_F64) ? g + 4 * i : 4 * g + i;
+        const int row = w * 16 * RT + 16 * t + rr, col = 16 * u + r16;
+        sP[row * PP + col] = (FMT == F_F64) ? (double)c[t][u][i] : dacc[t][u][i];
+      }
+  __syncthreads();
+
+  // row epilogues: BM consecutive threads serve one instance
+  const bool reduce = !(stage == ST_S2 || stage == ST_S3 || stage == ST_RHS);
+  for (int e0 = 0; e0 < BM * IB; e0 += 256) {
+    const int e = e0 + tid;
+    const int ib = e / BM, row = e % BM;
+    const int b = cb * IB + ib;
+    double r0 = 0.0, r1 = 0.0;
+    if (b < sh.B) {
+      const Args& a = sh.inst[((size_t)b * kStages + stage) * 2 + sh.par];
+      const Ctl* ctl = a.ctl;
+      const long long i = (long long)rb * BM + row;
+      if (ctl->status == kRunning && i < a.n) {
+        RowIn rin;
+        load_row(a, ctl, i, rin);
+        double P[2] = {0.0, 0.0};
+#pragma unroll
+        for (int mm = 0; mm < M; ++mm) {
+          double p = 0.0;
+#pragma unroll
+          for (int tt = 0; tt < T; ++tt) p += ldexp(sP[row * PP + ib * C + mm * T + tt], -tt * sh.vshift);
+          P[mm] = sh.scale * p;
+        }
+        epilogue<FMT>(a, ctl, i, P, rin, &r0, &r1);
+      }
+    }
+    if (!reduce) continue;
+    r0 = wave_nanmax(r0);
+    r1 = wave_nanmax(r1);
+    if (lane == 0) {
+      sRed0[w] = r0;
+      sRed1[w] = r1;
+    }
+    __syncthreads();
+    constexpr int WPI = BM / 64;  // waves per instance in one pass
+    if (tid < 4 && tid % WPI == 0) {
+      const int ibq = (e0 + 64 * tid) / BM;
+      const int bq = cb * IB + ibq;
+      double m0 = sRed0[tid], m1 = sRed1[tid];
+      for (int q = 1; q < WPI; ++q) {
+        m0 = nanmax(m0, sRed0[tid + q]);
+        m1 = nanmax(m1, sRed1[tid + q]);
+      }
+      if (bq < sh.B) {
+        const Args& a = sh.inst[((size_t)bq * kStages + stage) * 2 + sh.par];
+        if (a.ctl->status == kRunning) {
+          a.ep0[rb] = m0;
+          a.ep1[rb] = m1;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // elementary controller (reading of the unspecified step-size correction; the
 // estimate is O(h^3), so the exponent is 1/3)
 __device__ double control(const Ctl* c, double h, double E, bool accepted) {
@@ -1293,11 +1558,14 @@ hipError_t launch_set_status(Ctl* c, int code, hipStream_t s) {
   return hipGetLastError();
 }
 
-int tile_rows(int fmt, const Tile& t) { return t.MM == 1 ? 16 * t.R * t.WR : t.R * t.WR; }
+int tile_rows(int fmt, const Tile& t) {
+  return t.MM == 3 ? 64 * t.R : t.MM == 1 ? 16 * t.R * t.WR : t.R * t.WR;
+}
 // columns one wave step covers: 64 lanes x 16 bytes (VALU), 4 lane groups x 16 bytes (matrix cores)
 int tile_kalign(int fmt, const Tile& t) {
   if (t.MM == 1) return 64 / (int)fmt_bytes(fmt);
   if (t.MM == 2) return 64;
+  if (t.MM == 3) return 256;
   return fmt == F_F64 ? 128 : 256;
 }
 
@@ -1317,6 +1585,9 @@ int tile_kalign(int fmt, const Tile& t) {
 // pairwise kernels: (R rows per wave, WV waves, UJ column chunks per step)
 #define BS32_PAIR_TILES(X) X(2, 4, 1) X(4, 4, 1) X(8, 4, 1) X(4, 4, 2)
 
+// shared-coupling products: (RT 16-row tiles per wave, CT 16-column tiles), four waves
+#define BS32_SHARED_TILES(X) X(2, 4) X(1, 8) X(1, 4) X(2, 2)
+
 #define BS32_TILE_VALU(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 0},
 #define BS32_TILE_MMA(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 1},
 static const Tile kF64Tiles[] = {BS32_F64_TILES(BS32_TILE_VALU)};
@@ -1325,6 +1596,9 @@ static const Tile kMmaTiles[] = {BS32_MMA_TILES(BS32_TILE_MMA)};
 #define BS32_TILE_PAIR(R_, WV_, UJ_) Tile{R_, WV_, 1, UJ_, 0, 2},
 static const Tile kPairTiles[] = {BS32_PAIR_TILES(BS32_TILE_PAIR)};
 #undef BS32_TILE_PAIR
+#define BS32_TILE_SHARED(RT_, CT_) Tile{RT_, 4, 1, CT_, 0, 3},
+static const Tile kSharedTiles[] = {BS32_SHARED_TILES(BS32_TILE_SHARED)};
+#undef BS32_TILE_SHARED
 #undef BS32_TILE_VALU
 #undef BS32_TILE_MMA
 
@@ -1344,6 +1618,42 @@ const Tile* tile_candidates(int fmt, int* count) {
   }
   *count = (int)(sizeof(kMmaTiles) / sizeof(Tile));
   return kMmaTiles;
+}
+
+const Tile* shared_tile_candidates(int* count) {
+  *count = (int)(sizeof(kSharedTiles) / sizeof(Tile));
+  return kSharedTiles;
+}
+
+template <int FMT, int M>
+static hipError_t launch_shared_t(const Shared* sh, const Tile& t, hipStream_t s) {
+  const int total = sh ? sh->nrb * sh->ncb : 0;
+  const unsigned grid = 8u * (unsigned)((total + 7) / 8);
+#define X(RT_, CT_)                                                                       \
+  if (t.R == RT_ && t.U == CT_) {                                                         \
+    if (!sh) return hipSuccess;                                                           \
+    if (total > 0) k_shared_contract<FMT, M, RT_, CT_><<<grid, 256, 0, s>>>(*sh);        \
+    return hipGetLastError();                                                             \
+  }
+  BS32_SHARED_TILES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+// sh == nullptr: only whether the instance exists
+static hipError_t dispatch_shared(const Shared* sh, int m, int fmt, const Tile& t, hipStream_t s) {
+  if (t.MM != 3 || t.WR != 4) return hipErrorInvalidValue;
+  switch (fmt) {
+    case F_F64: return m == 2 ? launch_shared_t<F_F64, 2>(sh, t, s) : launch_shared_t<F_F64, 1>(sh, t, s);
+    case F_F32: return m == 2 ? launch_shared_t<F_F32, 2>(sh, t, s) : launch_shared_t<F_F32, 1>(sh, t, s);
+    case F_BF16: return m == 2 ? launch_shared_t<F_BF16, 2>(sh, t, s) : launch_shared_t<F_BF16, 1>(sh, t, s);
+    case F_F16: return m == 2 ? launch_shared_t<F_F16, 2>(sh, t, s) : launch_shared_t<F_F16, 1>(sh, t, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_shared_contract(const Shared& sh, int m, int fmt, const Tile& t, hipStream_t s) {
+  return dispatch_shared(&sh, m, fmt, t, s);
 }
 
 // one contraction launch: a single system (a) or an ensemble (g, ggrid workgroups)
@@ -1425,6 +1735,7 @@ static hipError_t dispatch(const Launch& L, int m, int fmt, const Tile& t);
 bool tile_supported(int fmt, int m, const Tile& t);
 
 static hipError_t dispatch(const Launch& L, int m, int fmt, const Tile& t) {
+  if (t.MM == 3) return L.dry ? dispatch_shared(nullptr, m, fmt, t, nullptr) : hipErrorInvalidValue;
   if (t.MM == 2) return (fmt == F_F64 || fmt == F_F32) ? launch_pair(L, fmt, t) : hipErrorInvalidValue;
   switch (fmt) {
     case F_F64: return m == 2 ? launch_f64<2>(L, t) : launch_f64<1>(L, t);
@@ -1441,6 +1752,7 @@ static hipError_t dispatch(const Launch& L, int m, int fmt, const Tile& t) {
 int kernel_name(int fmt, int m, const Tile& t, char* buf, size_t cap) {
   if (!tile_supported(fmt, m, t)) return -1;
   const char* nt = t.NT ? "true" : "false";
+  if (t.MM == 3) return snprintf(buf, cap, "k_shared_contract<%d, %d, %d, %d>", fmt, m, t.R, t.U);
   if (t.MM == 2)  // the system kind and weights also select the instance: name the family and tile
     return snprintf(buf, cap, "k_contract_pair<*, %s, *, %d, %d, %d>", fmt == F_F32 ? "true" : "false", t.R, t.WR,
                     t.U);

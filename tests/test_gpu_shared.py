@@ -1,0 +1,159 @@
+"""GPU tests of shared-coupling ensembles: many instances with one coupling
+matrix and their own parameters, gains, initial values and intervals, whose
+stage contractions run as one matrix product on the matrix cores.
+
+Every instance is checked against the oracle's solve of that instance alone:
+FP64 at the parity bar (relative l2 <= 1e-10, accepted steps within 1 %),
+the reduced storage formats against the oracle's reduced-precision solve (the
+oracle quantizes A and the operand terms the same way and sums exactly).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def bs():
+    import paper_2605_23727_amd as b
+    s = b.Solver(0)
+    yield b, s
+    s.close()
+
+
+def _sweep(kind, n, B, seed):
+    """B instances on one network: per-instance parameters, gains and initial values."""
+    g = np.random.default_rng(seed)
+    if kind == "kuramoto":
+        base = workloads.kuramoto(n, seed=seed, t1=2.0)
+        params = g.standard_normal((B, n))
+        gains = g.uniform(0.5, 4.0, B)
+        y0 = g.random((B, n)) * 2 * np.pi
+    elif kind == "osc2":
+        base = workloads.osc2(n, seed=seed, t1=2.0)
+        params = g.uniform(0.5, 1.5, (B, n))
+        gains = np.ones(B)
+        y0 = g.standard_normal((B, 2 * n))
+    elif kind == "goodwin3":
+        base = workloads.goodwin3(n, seed=seed, t1=20.0)
+        params = g.uniform(0.18, 0.22, (B, n))
+        gains = g.uniform(0.2, 1.0, B)
+        y0 = (g.random((B, n, 3)) * 2 * np.array([0.062, 0.310, 1.549])).reshape(B, -1)
+    else:
+        base = workloads.lco_paper(n, seed=seed, t1=2.0, dense=True)
+        params = None
+        gains = np.ones(B)
+        y0 = g.random((B, 2 * n)) * 2.0
+    return base, params, gains, y0
+
+
+def _check_against_oracle(b, s, orc, kind, base, params, gains, y0, t1, rtol, mode, rel_bar, acc_bar):
+    B = y0.shape[0]
+    n = base["n"]
+    s.set_shared_ensemble(base["kind"], n, B, A=base["A"], params=params, gains=gains)
+    y, st, tot = s.solve_batch(y0.reshape(-1), 0.0, t1, rtol, mode=mode)
+    assert np.all(st == 0), st
+    Y = y.reshape(B, -1)
+    worst = 0.0
+    for q in range(B):
+        bst = s.batch_stats(q)
+        if t1[q] == 0.0:
+            assert np.array_equal(Y[q], y0[q]) and bst["n_fev"] == 0
+            continue
+        ref, rst, _ = orc.bs32_solve(base["kind"], n, y0[q], 0.0, t1[q], rtol, A=base["A"],
+                                     param=None if params is None else params[q], gain=gains[q], mode=mode)
+        assert rst["status"] == 0
+        rel = np.linalg.norm(Y[q] - ref) / np.linalg.norm(ref)
+        worst = max(worst, rel)
+        assert rel <= rel_bar, (kind, mode, q, rel)
+        assert abs(bst["n_accept"] - rst["n_accept"]) <= max(acc_bar[0], acc_bar[1] * rst["n_accept"]), q
+    say(f"   worst rel {worst:.2e}")
+    assert tot["n_fev"] == sum(s.batch_stats(q)["n_fev"] for q in range(B))
+
+
+@pytest.mark.parametrize("kind,n,B", [("kuramoto", 300, 7), ("osc2", 257, 5), ("goodwin3", 130, 4),
+                                      ("lco", 200, 3), ("kuramoto", 1, 2)])
+def test_shared_fp64_matches_oracle(bs, orc, kind, n, B):
+    b, s = bs
+    base, params, gains, y0 = _sweep(kind, n, B, 400 + n)
+    t1 = np.full(B, base["t1"])
+    if B >= 4:
+        t1[1] = 0.0              # an empty interval returns y0
+        t1[2] = 0.4 * base["t1"]  # instances finish at different attempts
+    say(f"[shared fp64] {kind} n={n} B={B}")
+    _check_against_oracle(b, s, orc, kind, base, params, gains, y0, t1, 1e-7, 0, 1e-10, (1, 0.01))
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2, 3])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+def test_shared_every_tile(bs, orc, tile, mode):
+    """Every instantiated product tile in every storage format, on a ragged N and a
+    batch that does not fill the last column block."""
+    b, s = bs
+    base, params, gains, y0 = _sweep("kuramoto", 333, 37, 77)
+    y0 = y0[:37]
+    t1 = np.full(37, 0.5)
+    say(f"[shared tile {tile}] mode {mode}")
+    s.set_options(tile=tile)
+    try:
+        s.set_shared_ensemble(base["kind"], 333, 37, A=base["A"], params=params, gains=gains)
+        assert s.kernel_name(mode, tile).startswith("k_shared_contract<")
+        y, st, _ = s.solve_batch(y0.reshape(-1), 0.0, t1, 1e-6, mode=mode)
+        assert np.all(st == 0)
+        Y = y.reshape(37, -1)
+        for q in (0, 17, 36):
+            ref, rst, _ = orc.bs32_solve(base["kind"], 333, y0[q], 0.0, 0.5, 1e-6, A=base["A"], param=params[q],
+                                         gain=gains[q], mode=mode)
+            rel = np.linalg.norm(Y[q] - ref) / np.linalg.norm(ref)
+            assert rel <= (1e-10 if mode == 0 else 2e-5), (q, rel)
+    finally:
+        s.set_options(tile=-1)
+
+
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_shared_reduced_tracks_oracle(bs, orc, mode):
+    b, s = bs
+    base, params, gains, y0 = _sweep("kuramoto", 520, 6, 91)
+    t1 = np.full(6, 2.0)
+    say(f"[shared reduced] mode {mode}")
+    _check_against_oracle(b, s, orc, "kuramoto", base, params, gains, y0, t1, 1e-6, mode, 2e-5, (2, 0.03))
+
+
+def test_shared_equals_grouped_ensemble(bs):
+    """The product path and the grouped path (one matrix copy per instance) solve the
+    same instances to FP64 rounding."""
+    b, s = bs
+    base, params, gains, y0 = _sweep("osc2", 300, 5, 93)
+    s.set_shared_ensemble(base["kind"], 300, 5, A=base["A"], params=params, gains=gains)
+    y_sh, st_sh, _ = s.solve_batch(y0.reshape(-1), 0.0, 2.0, 1e-8)
+    ws = [dict(kind=base["kind"], n=300, A=base["A"], param=params[q], gain=gains[q]) for q in range(5)]
+    s.set_ensemble(ws)
+    y_gr, st_gr, _ = s.solve_batch(y0.reshape(-1), 0.0, 2.0, 1e-8)
+    assert np.all(st_sh == 0) and np.all(st_gr == 0)
+    assert np.linalg.norm(y_sh - y_gr) / np.linalg.norm(y_gr) <= 1e-11
+
+
+def test_shared_rejections(bs):
+    b, s = bs
+    base, params, gains, y0 = _sweep("kuramoto", 64, 3, 95)
+    s.set_shared_ensemble(base["kind"], 64, 3, A=base["A"], params=params, gains=gains)
+    with pytest.raises(b.BS32Error):   # e4m3's three operand terms do not tile the product
+        s.solve_batch(y0.reshape(-1), 0.0, 1.0, 1e-6, mode=4)
+    with pytest.raises(b.BS32Error):   # the recipes are single-system paths
+        s.solve_batch(y0.reshape(-1), 0.0, 1.0, 1e-6, mode=6)
+    w = workloads.clock4(32, seed=96)
+    with pytest.raises(b.BS32Error):
+        s.set_shared_ensemble(w["kind"], 32, 2)
+    # the context still works after the rejections
+    s.set_shared_ensemble(base["kind"], 64, 3, A=base["A"], params=params, gains=gains)
+    y, st, _ = s.solve_batch(y0.reshape(-1), 0.0, 1.0, 1e-6)
+    assert np.all(st == 0)
