@@ -93,6 +93,8 @@ def parse():
                     help="MiB of a plain device copy run first (calibrates PMC byte counters)")
     ap.add_argument("--instances", type=int, default=None, help="c4 / f3: ensemble size (512 / 256)")
     ap.add_argument("--no-graph", action="store_true", help="launch attempts directly instead of from HIP graphs")
+    ap.add_argument("--method", default="bs32", choices=["bs32", "dp54"],
+                    help="single-system configs: the embedded pair (dp54: Dormand-Prince 5(4), modes 0-4)")
     return ap.parse_args()
 
 
@@ -454,6 +456,9 @@ def bench_single(args, torch, bs, workload, w, modes, ref_rtol):
     s = bs.Solver(0)
     if args.no_graph:
         s.set_options(use_graph=0)
+    if args.method == "dp54":
+        s.set_options(method=bs.METHOD_DP54)
+        modes = [m for m in modes if m < 5]
     A = dev_t(w["A"])
     torch.cuda.synchronize()
     t_setup = time.perf_counter()
@@ -528,7 +533,8 @@ def bench_single(args, torch, bs, workload, w, modes, ref_rtol):
 
     line = base_line(args, rh["pairs_per_s"], rh["ms_per_step"],
                      ("f32-recipe" if head >= 5 else DTYPE[head] + "+f64-update"),
-                     {"workload": workload_desc(workload, w), "precision_mode": rh["name"], "global_batch": 1,
+                     {"workload": workload_desc(workload, w) + (" pair=dormand-prince-5(4)" if args.method == "dp54" else ""),
+                      "precision_mode": rh["name"], "global_batch": 1,
                       "seq_len": None})
     line.update({
         "time_to_t_end_s": rh["time_to_t_end_s"],

@@ -140,7 +140,21 @@ typedef struct {
   int32_t trace_cap;     /* ring capacity (default 65536) */
   int32_t controller;    /* 0 standard, 1 learned proposer (needs bs32_set_controller) */
   int32_t tile;          /* contraction tile configuration; -1 = autotuned default */
+  int32_t method;        /* bs32_method: the embedded pair (default BS32_METHOD_BS32) */
+  int32_t reserved;
 } bs32_options;
+
+/* Embedded Runge-Kutta pair of bs32_solve.  The paper's method is the
+   Bogacki-Shampine 3(2) pair with FSAL (Sec. 2.2); its reference solver uses the
+   Dormand-Prince 5(4) pair (Sec. 2.4, ode45) and its conclusion names other
+   embedded pairs as generalisations.  BS32_METHOD_DP54 runs the same contraction
+   kernels and storage formats (precision modes 0-4, pairwise couplings included)
+   with seven FSAL stages per attempt, the same weighted max norm and acceptance
+   rule (E < Rel) and the step factor safety * (Rel / E)^(1/5), clipped to
+   [facmin, facmax] (growth capped at 1 right after a rejection); the starting
+   step uses the exponent 1/6.  Not with the paper's recipes (modes 5-7), the
+   learned proposer or ensembles (EUNSUPPORTED). */
+typedef enum { BS32_METHOD_BS32 = 0, BS32_METHOD_DP54 = 1 } bs32_method;
 
 /* One record per step attempt of the last solve (when options.trace = 1). */
 typedef struct {

@@ -28,6 +28,7 @@ DIM = {OSC2: 2, LCO_PAPER: 2, KURAMOTO: 1, GOODWIN3: 3, CLOCK4: 4}
 (PREC_FP64, PREC_RHS_FP32, PREC_RHS_BF16, PREC_RHS_FP16, PREC_RHS_FP8_E4M3,
  PREC_PAPER_SINGLE, PREC_PAPER_MIXED1, PREC_PAPER_MIXED2) = range(8)
 MLP_PARAMS = 4883  # BS32_MLP_PARAMS
+METHOD_BS32, METHOD_DP54 = 0, 1  # bs32_method
 MLP_IN = 9
 MODE_NAMES = {0: "fp64", 1: "rhs_fp32", 2: "rhs_bf16", 3: "rhs_fp16", 4: "rhs_fp8_e4m3", 5: "paper_single",
               6: "paper_mixed1", 7: "paper_mixed2"}
@@ -55,7 +56,7 @@ class Options(C.Structure):
                 ("h_max", C.c_double), ("h0", C.c_double), ("safety", C.c_double), ("facmin", C.c_double),
                 ("facmax", C.c_double), ("fixed_step", C.c_int32), ("use_graph", C.c_int32),
                 ("trace", C.c_int32), ("trace_cap", C.c_int32), ("controller", C.c_int32),
-                ("tile", C.c_int32)]
+                ("tile", C.c_int32), ("method", C.c_int32), ("reserved", C.c_int32)]
 
 
 class TraceRec(C.Structure):

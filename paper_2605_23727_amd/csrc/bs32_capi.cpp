@@ -100,6 +100,7 @@ struct bs32_ctx {
   double* Kf[2] = {nullptr, nullptr};
   double* K2 = nullptr;
   double* K3 = nullptr;
+  double* Kd[3] = {nullptr, nullptr, nullptr};  // K4..K6 of the Dormand-Prince 5(4) pair
   double* V64[2] = {nullptr, nullptr};
   void* Vq[2] = {nullptr, nullptr};
   int vq_fmt = -1;  // storage format the split-operand buffers were last cleared for
@@ -205,6 +206,7 @@ void free_state(bs32_ctx* c) {
   }
   dfree(c->K2);
   dfree(c->K3);
+  for (int q = 0; q < 3; ++q) dfree(c->Kd[q]);
   dfree(c->ep0);
   dfree(c->ep1);
   dfree(c->stage_buf);
@@ -244,6 +246,7 @@ bs32_status ensure_state(bs32_ctx* c) {
   }
   HIPCHK(c, alloc0((void**)&c->K2, sv));
   HIPCHK(c, alloc0((void**)&c->K3, sv));
+  for (int q = 0; q < 3; ++q) HIPCHK(c, alloc0((void**)&c->Kd[q], sv));
   HIPCHK(c, alloc0((void**)&c->ep0, sizeof(double) * (size_t)np));
   HIPCHK(c, alloc0((void**)&c->ep1, sizeof(double) * (size_t)np));
   HIPCHK(c, alloc0((void**)&c->stage_buf, sv));
@@ -290,6 +293,7 @@ Args make_args(bs32_ctx* c, int fmt, const Geom& g, int stage) {
   }
   a.K2 = c->K2;
   a.K3 = c->K3;
+  for (int q = 0; q < 3; ++q) a.Kd[q] = c->Kd[q];
   a.ep0 = c->ep0;
   a.ep1 = c->ep1;
   a.ctl = c->ctlbuf[c->par];
@@ -458,8 +462,8 @@ bs32_status prepare(bs32_ctx* c, int mode, Geom* g, int* fmt) {
     c->vq_fmt = *fmt;
   }
   char key[128];
-  snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%p/%p/%lld", mode, t.R, t.WR, t.WK, t.U, t.NT, t.MM,
-           (void*)c->trace_d, (void*)(c->in_solve ? c->rec : nullptr), c->rec_cap);
+  snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%p/%p/%lld/%d", mode, t.R, t.WR, t.WK, t.U, t.NT, t.MM,
+           (void*)c->trace_d, (void*)(c->in_solve ? c->rec : nullptr), c->rec_cap, c->opt.method);
   if (c->graph_key != key) {
     free_graphs(c);
     c->graph_key = key;
@@ -469,12 +473,18 @@ bs32_status prepare(bs32_ctx* c, int mode, Geom* g, int* fmt) {
 
 hipError_t enqueue_attempt(bs32_ctx* c, int fmt, const Geom& g) {
   hipError_t e;
-  Args a = make_args(c, fmt, g, ST_S2);
-  if ((e = launch_contract(a, fmt, g.t, c->stream)) != hipSuccess) return e;
-  a.stage = ST_S3;
-  if ((e = launch_contract(a, fmt, g.t, c->stream)) != hipSuccess) return e;
-  a.stage = ST_S4;
-  if ((e = launch_contract(a, fmt, g.t, c->stream)) != hipSuccess) return e;
+  Args a{};
+  if (c->opt.method == BS32_METHOD_DP54) {
+    for (int st = ST_D2; st <= ST_D7; ++st) {
+      a = make_args(c, fmt, g, st);
+      if ((e = launch_contract(a, fmt, g.t, c->stream)) != hipSuccess) return e;
+    }
+  } else {
+    for (int st : {ST_S2, ST_S3, ST_S4}) {  // each stage with its own recipe row (Table MP-Distrib)
+      a = make_args(c, fmt, g, st);
+      if ((e = launch_contract(a, fmt, g.t, c->stream)) != hipSuccess) return e;
+    }
+  }
   e = launch_finalize(a, c->stream);
   c->par ^= 1;  // the finalize wrote the other control block
   return e;
@@ -603,6 +613,8 @@ bs32_status bs32_set_options(bs32_ctx* c, const bs32_options* o) {
   if (o->fixed_step && !(o->h0 > 0)) return fail(c, BS32_EINVAL, "fixed_step needs h0 > 0");
   if (o->controller != 0 && o->controller != 1) return fail(c, BS32_EINVAL, "unknown controller %d", o->controller);
   if (o->controller == 1 && !c->mlp_w) return fail(c, BS32_ESTATE, "learned controller needs bs32_set_controller");
+  if (o->method != BS32_METHOD_BS32 && o->method != BS32_METHOD_DP54)
+    return fail(c, BS32_EINVAL, "unknown method %d", o->method);
   c->opt = *o;
   free_graphs(c);
   return BS32_OK;
@@ -770,6 +782,11 @@ bs32_status bs32_solve(bs32_ctx* c, const double* y0, double t0, double t1, doub
     ~InSolve() { c->in_solve = false; }
   } in_solve(c);
   const bs32_options& o = c->opt;
+  if (o.method == BS32_METHOD_DP54) {
+    if (mode >= BS32_PREC_PAPER_SINGLE)
+      return fail(c, BS32_EUNSUPPORTED, "the paper's recipes are defined for the Bogacki-Shampine stages");
+    if (o.controller == 1) return fail(c, BS32_EUNSUPPORTED, "the learned proposer serves the Bogacki-Shampine pair");
+  }
   if (o.trace && c->trace_alloc < o.trace_cap) {
     dfree(c->trace_d);
     HIPCHK(c, hipMalloc((void**)&c->trace_d, sizeof(TraceRec) * (size_t)o.trace_cap));
@@ -818,6 +835,7 @@ bs32_status bs32_solve(bs32_ctx* c, const double* y0, double t0, double t1, doub
   h->trace_on = o.trace ? 1 : 0;
   h->trace_cap = o.trace ? o.trace_cap : 1;
   h->use_mlp = (o.controller == 1 && c->mlp_w) ? 1 : 0;
+  h->method = o.method;
   c->par = 0;
   HIPCHK(c, hipMemcpyAsync(c->ctl_d(), h, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemsetAsync((char*)c->scratch + 32, 0, sizeof(unsigned), c->stream));

@@ -12,12 +12,33 @@ constexpr double kA32 = 3.0 / 4.0;
 constexpr double kB1 = 2.0 / 9.0, kB2 = 1.0 / 3.0, kB3 = 4.0 / 9.0;
 constexpr double kBt1 = 7.0 / 24.0, kBt2 = 1.0 / 4.0, kBt3 = 1.0 / 3.0, kBt4 = 1.0 / 8.0;
 
+// ---- Dormand-Prince 5(4) with FSAL: the pair of the paper's reference solver
+// (Sec. 2.4, ode45) and a method its conclusion names the approach for; the
+// published coefficients.  Row s of kDpA builds the input of stage s + 1; the
+// last row equals the fifth-order weights, so stage 7 is evaluated at X^{n+1}.
+constexpr double kDpA[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 5.0, 0, 0, 0, 0, 0},
+    {3.0 / 40.0, 9.0 / 40.0, 0, 0, 0, 0},
+    {44.0 / 45.0, -56.0 / 15.0, 32.0 / 9.0, 0, 0, 0},
+    {19372.0 / 6561.0, -25360.0 / 2187.0, 64448.0 / 6561.0, -212.0 / 729.0, 0, 0},
+    {9017.0 / 3168.0, -355.0 / 33.0, 46732.0 / 5247.0, 49.0 / 176.0, -5103.0 / 18656.0, 0},
+    {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0, -2187.0 / 6784.0, 11.0 / 84.0},
+};
+constexpr double kDpB[7] = {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0, -2187.0 / 6784.0, 11.0 / 84.0, 0.0};
+constexpr double kDpBt[7] = {5179.0 / 57600.0, 0.0, 7571.0 / 16695.0, 393.0 / 640.0, -92097.0 / 339200.0,
+                             187.0 / 2100.0, 1.0 / 40.0};
+
 // internal solver status (public codes are bs32_status values >= 0)
 constexpr int kRunning = 100;
 constexpr int kStatusRange = 7;  // BS32_RANGE
 
 // stages of one contraction launch
-enum Stage : int { ST_INIT = 0, ST_H0 = 1, ST_S2 = 2, ST_S3 = 3, ST_S4 = 4, ST_RHS = 5 };
+// (ST_D2 .. ST_D7: the six contractions of a Dormand-Prince 5(4) attempt)
+enum Stage : int {
+  ST_INIT = 0, ST_H0 = 1, ST_S2 = 2, ST_S3 = 3, ST_S4 = 4, ST_RHS = 5,
+  ST_D2 = 6, ST_D3 = 7, ST_D4 = 8, ST_D5 = 9, ST_D6 = 10, ST_D7 = 11
+};
 
 // storage formats of the coupling matrix
 enum Fmt : int { F_F64 = 0, F_F32 = 1, F_BF16 = 2, F_F16 = 3, F_E4M3 = 4 };
@@ -50,7 +71,7 @@ struct Ctl {
   long long nhist;        // attempts recorded in the history
   long long n_mlp;        // steps chosen by the learned proposer
   int prop_cur;           // 1 if the current step size came from the learned proposer
-  int pad1;
+  int method;             // 0: Bogacki-Shampine 3(2), 1: Dormand-Prince 5(4)
 };
 
 struct TraceRec {
@@ -67,6 +88,7 @@ struct Args {
   double* Kf[2];          // first/last stage ping-pong (FSAL)
   double* K2;
   double* K3;
+  double* Kd[3];          // K4, K5, K6 of a Dormand-Prince attempt
   double* V64[2];         // FP64 vector operand ping-pong, [ld][m]
   void* Vq[2];            // split vector operand terms for reduced formats, [m*T][ld]
   double* ep0;            // per-row-block partial maxima

@@ -316,7 +316,13 @@ __device__ __forceinline__ void rhs_eval(const Args& a, const double* y, const d
 // Single keeps its solution and stage inputs in FP32
 __device__ __forceinline__ double sstore(const Args& a, double v) { return a.sstate ? (double)(float)v : v; }
 
-__device__ __forceinline__ int vin_of(int stage) { return stage == ST_S3 ? 1 : 0; }
+// operand buffer a contraction reads: stage 3 of BS3(2) and the odd Dormand-Prince
+// stages read buffer 1, the rest buffer 0 (each stage writes the next one's input
+// into the other buffer)
+__device__ __forceinline__ int vin_of(int stage) {
+  if (stage >= ST_D2) return (stage - ST_D2) & 1;
+  return stage == ST_S3 ? 1 : 0;
+}
 
 // ---------------------------------------------------------------------------
 // stage epilogue of one row.  Its inputs are loaded by load_row before the
@@ -331,6 +337,7 @@ struct RowIn {
 __device__ __forceinline__ void load_row(const Args& a, const Ctl* ctl, long long i, RowIn& r) {
   const long long np = a.np;
   const int st = a.stage;
+  if (st >= ST_D2) return;  // the Dormand-Prince epilogue loads its own inputs
   const double* X = a.X[ctl->xi];
   const double* K1 = a.Kf[ctl->ki];
   const double* Vin = a.V64[vin_of(st)];
@@ -439,6 +446,86 @@ __device__ void epilogue(const Args& a, const Ctl* ctl, long long i, const doubl
   }
 }
 
+// Dormand-Prince 5(4) stage s = 2..7 of one row: K_s from the contraction of the
+// stage input, then the next stage's input X + h sum_l a_{s+1,l} K_l (stage 6 writes
+// it as X^{n+1} too), or at stage 7 (FSAL, evaluated at X^{n+1}) the difference of
+// the two solutions h sum_l (b_l - bt_l) K_l and its weights.  The sums run over l in
+// increasing order, FP64.
+template <int VF>
+__device__ void epilogue_dp(const Args& a, const Ctl* ctl, long long i, const double* P, double* r0,
+                            double* r1) {
+  const int s = a.stage - ST_D2 + 2;
+  const int d = a.d;
+  const long long np = a.np;
+  const double ha = ctl->ha;
+  double* Kl[7] = {a.Kf[ctl->ki], a.K2, a.K3, a.Kd[0], a.Kd[1], a.Kd[2], a.Kf[1 - ctl->ki]};
+  const double* X = a.X[ctl->xi];
+  double* Xn = a.X[1 - ctl->xi];
+  const double* Vin = a.V64[vin_of(a.stage)];
+  double vs[2];
+  vs[0] = Vin[i * a.m];
+  vs[1] = a.m > 1 ? Vin[i * a.m + 1] : 0.0;
+  const double p = a.param[i];
+  const double rs = a.rsum ? a.rsum[i] : 0.0;
+  double x[4] = {0, 0, 0, 0}, y[4] = {0, 0, 0, 0}, k[4] = {0, 0, 0, 0}, K[7][4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (c >= d) break;
+    x[c] = X[c * np + i];
+#pragma unroll
+    for (int l = 0; l < 6; ++l)
+      if (l < s - 1) K[l][c] = Kl[l][c * np + i];
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (c >= d) break;
+    if (s == 7) {
+      y[c] = Xn[c * np + i];
+    } else {
+      double acc = 0.0;
+#pragma unroll
+      for (int l = 0; l < 6; ++l)
+        if (l < s - 1) acc += kDpA[s - 1][l] * K[l][c];
+      y[c] = x[c] + ha * acc;
+    }
+  }
+  rhs_eval(a, y, P, vs, p, rs, k);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (c >= d) break;
+    Kl[s - 1][c * np + i] = k[c];
+    K[s - 1][c] = k[c];
+  }
+  *r0 = 0.0;
+  *r1 = 0.0;
+  if (s < 7) {
+    double yn[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (c >= d) break;
+      double acc = 0.0;
+#pragma unroll
+      for (int l = 0; l < 6; ++l)
+        if (l < s) acc += kDpA[s][l] * K[l][c];
+      yn[c] = x[c] + ha * acc;
+      if (s == 6) Xn[c * np + i] = yn[c];
+    }
+    write_operand_t<VF>(a, vin_of(a.stage + 1), i, yn[0]);
+    return;
+  }
+  const double floor_w = ctl->atol / ctl->rtol;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (c >= d) break;
+    double acc = 0.0;
+#pragma unroll
+    for (int l = 0; l < 7; ++l) acc += (kDpB[l] - kDpBt[l]) * K[l][c];
+    const double W = fmax(fmax(fabs(x[c]), fabs(y[c])), floor_w);
+    *r0 = nanmax(*r0, fabs(ha * acc) / W);
+    *r1 = nanmax(*r1, fabs(K[0][c]) / fmax(fabs(x[c]), floor_w));
+  }
+}
+
 // the row this thread finishes (at most one: every tile has fewer rows than threads)
 __device__ __forceinline__ long long tail_row(const Args& a, int rb, int RB) {
   return threadIdx.x < RB ? (long long)rb * RB + threadIdx.x : -1;
@@ -452,8 +539,11 @@ __device__ void contract_tail(const Args& a, int rb, double (*sP)[M], int RB, co
   const int tid = threadIdx.x, nthr = blockDim.x;
   const long long i = tail_row(a, rb, RB);
   double r0 = 0.0, r1 = 0.0;
-  if (i >= 0 && i < a.n) epilogue<VF>(a, ctl, i, sP[tid], rin, &r0, &r1);
-  if (a.stage == ST_S2 || a.stage == ST_S3 || a.stage == ST_RHS) return;
+  if (i >= 0 && i < a.n) {
+    if (a.stage >= ST_D2) epilogue_dp<VF>(a, ctl, i, sP[tid], &r0, &r1);
+    else epilogue<VF>(a, ctl, i, sP[tid], rin, &r0, &r1);
+  }
+  if (a.stage == ST_S2 || a.stage == ST_S3 || a.stage == ST_RHS || (a.stage >= ST_D2 && a.stage < ST_D7)) return;
   r0 = wave_nanmax(r0);
   r1 = wave_nanmax(r1);
   const int lane = tid & 63, wave = tid >> 6, nw = (nthr + 63) >> 6;
@@ -1243,7 +1333,8 @@ __device__ bool finalize(const Args& a, Ctl* c, double m0, double m1, bool write
       const double h0 = c->h0probe;
       const double d2 = m0 / h0;
       const double dm = fmax(c->d1, d2);
-      const double h1 = (dm <= 1e-15) ? fmax(1e-6, h0 * 1e-3) : pow(0.01 / dm, 0.25);
+      // exponent 1/(p+1) of the method's order p: 3 (BS3(2)) or 5 (DP5(4))
+      const double h1 = (dm <= 1e-15) ? fmax(1e-6, h0 * 1e-3) : pow(0.01 / dm, c->method ? 1.0 / 6.0 : 0.25);
       c->h = fmin(fmin(100.0 * h0, h1), c->h_max);
       c->ha = fmin(c->h, c->t1 - c->t);
       break;
@@ -1306,6 +1397,45 @@ __device__ bool finalize(const Args& a, Ctl* c, double m0, double m1, bool write
         feat[8] = (float)log(fmax(m1, 1e-300));
       }
       return want;
+    }
+    case ST_D7: {  // a Dormand-Prince 5(4) attempt: estimate O(h^5), exponent 1/5
+      const double E = m0;
+      const double ha = c->ha;
+      c->n_fev += 6;
+      c->err = E;
+      bool accepted = true;
+      if (!c->fixed_step) {
+        if (!isfinite(E)) {
+          c->status = 6;  // BS32_NONFINITE
+          c->n_reject += 1;
+          if (c->trace_on) {
+            if (writer) a.trace[c->trace_n % c->trace_cap] = TraceRec{c->t, ha, E, m1, 0, 0};
+            c->trace_n += 1;
+          }
+          return false;
+        }
+        accepted = E < c->rtol;
+      }
+      if (c->trace_on) {
+        if (writer) a.trace[c->trace_n % c->trace_cap] = TraceRec{c->t, ha, E, m1, accepted ? 1 : 0, 0};
+        c->trace_n += 1;
+      }
+      const double fac = (E > 0.0) ? c->safety * pow(c->rtol / E, 0.2) : c->facmax;
+      if (accepted) {
+        c->n_accept += 1;
+        c->t = (c->t + ha >= c->t1 - c->snap) ? c->t1 : c->t + ha;
+        c->xi = 1 - c->xi;
+        c->ki = 1 - c->ki;
+        c->h = c->fixed_step ? c->h : ha * fmin(c->last_rejected ? 1.0 : c->facmax, fmax(c->facmin, fac));
+        c->last_rejected = 0;
+        if (ha < c->h_min_seen) c->h_min_seen = ha;
+      } else {
+        c->n_reject += 1;
+        c->h = ha * fmax(c->facmin, fac);
+        c->last_rejected = 1;
+      }
+      c->h_last = ha;
+      return false;
     }
     default: break;
   }
@@ -1397,7 +1527,7 @@ __device__ __forceinline__ void finalize_block(const Args& a, int blk) {
     s_next = (a.stage == ST_INIT && !(c->h0user > 0.0)) ? ST_H0 : ST_S2;
   }
   __syncthreads();
-  if (a.stage == ST_S4 && sc.status == kRunning) {
+  if ((a.stage == ST_S4 || a.stage == ST_D7) && sc.status == kRunning) {
     // learned proposal (whole workgroup), then the rest of the step-size update
     const float delta = s_want ? mlp_forward_wg(a.mlp, s_feat, s_h1, s_h2, s_red) : 0.0f;
     if (tid == 0) finalize_step(c, s_want != 0, delta);
@@ -1405,7 +1535,7 @@ __device__ __forceinline__ void finalize_block(const Args& a, int blk) {
   }
   if (writer && tid < kWords) ((unsigned long long*)a.ctl_out)[tid] = ((const unsigned long long*)&sc)[tid];
   // solution record: the initial value, then the state after every accepted step
-  if (a.rec && i < a.n && (a.stage == ST_INIT || (a.stage == ST_S4 && sc.n_accept != na0))) {
+  if (a.rec && i < a.n && (a.stage == ST_INIT || ((a.stage == ST_S4 || a.stage == ST_D7) && sc.n_accept != na0))) {
     const long long slot = (a.stage == ST_INIT) ? 0 : sc.n_accept;
     if (slot < a.rec_cap) {
       const double* Xc = a.X[sc.xi];
@@ -1416,7 +1546,8 @@ __device__ __forceinline__ void finalize_block(const Args& a, int blk) {
   if (sc.status != kRunning) return;
   if (i < a.n) {
     const double x = xc[sc.xi], k1 = kc[sc.ki];
-    const double y = (s_next == ST_H0) ? x + sc.h0probe * k1 : sstore(a, x + sc.ha * (kA21 * k1));
+    const double a21 = sc.method ? kDpA[1][0] : kA21;
+    const double y = (s_next == ST_H0) ? x + sc.h0probe * k1 : sstore(a, x + sc.ha * (a21 * k1));
     write_operand(a, 0, i, y);
   }
 }

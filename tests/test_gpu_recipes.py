@@ -135,3 +135,27 @@ def test_recipes_not_in_ensembles(bs):
     s.set_ensemble(ws)
     with pytest.raises(b.BS32Error):
         s.solve_batch(np.concatenate([w["y0"] for w in ws]), 0.0, 1.0, 1e-6, mode=6)
+
+
+@pytest.mark.parametrize("mode", [5, 6, 7])
+def test_recipe_rows_per_stage(bs, orc, mode):
+    """Each stage of an attempt uses its own row of Table MP-Distrib.  Without coupling
+    (K = 0) the Kuramoto right-hand side is omega, so the stages differ only in how F
+    rounds it: FP64 rows give omega, single rows (float)omega, and the error estimate
+    of the first attempt h |sum (b_l - bt_l) K_l| depends on which stages are single
+    (for Mixed1, k4 in FP64 against k4 in FP32 changes it by a factor 2.8)."""
+    b, s = bs
+    w = workloads.kuramoto(64, seed=66, K=0.0, t1=1.0)
+    s.set_workload(w)
+    s.set_options(trace=1, trace_cap=1024, h0=0.01)
+    try:
+        _, st = s.solve(w["y0"], 0.0, 1.0, 1e-6, mode=mode)
+        tr = s.trace()
+    finally:
+        s.set_options(trace=0, h0=0.0)
+    _, sto, tro = orc.bs32_solve(w["kind"], 64, w["y0"], 0.0, 1.0, 1e-6, A=w["A"], param=w["param"], gain=0.0,
+                                 mode=mode, trace_cap=1024, h0=0.01)
+    assert st["status"] == 0 and sto["status"] == 0
+    e_gpu, e_orc = tr["err"][0], tro["err"][0]
+    say(f"[recipe rows] mode {mode}: first estimate {e_gpu:.6e} vs oracle {e_orc:.6e}")
+    assert abs(e_gpu - e_orc) <= 1e-6 * e_orc + 1e-300
