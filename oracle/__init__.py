@@ -22,9 +22,9 @@ LIB_PATH = os.path.join(_HERE, "liborc_bs32.so")
 SRC_PATH = os.path.join(_HERE, "bs32_oracle.c")
 
 OSC2, LCO_PAPER, KURAMOTO, GOODWIN3, CLOCK4 = 1, 2, 3, 4, 5
-FMT_F64, FMT_F32, FMT_BF16, FMT_F16, FMT_E4M3 = 0, 1, 2, 3, 4
+FMT_F64, FMT_F32, FMT_BF16, FMT_F16, FMT_E4M3, FMT_BF16X2 = 0, 1, 2, 3, 4, 5
 (PREC_FP64, PREC_RHS_FP32, PREC_RHS_BF16, PREC_RHS_FP16, PREC_RHS_FP8,
- PREC_PAPER_SINGLE, PREC_PAPER_MIXED1, PREC_PAPER_MIXED2) = range(8)
+ PREC_PAPER_SINGLE, PREC_PAPER_MIXED1, PREC_PAPER_MIXED2, PREC_RHS_BF16X2) = range(9)
 OK, MAX_STEPS, MAX_REJECTS, H_TOO_SMALL, NONFINITE = 0, 1, 2, 3, 6
 DIM = {OSC2: 2, LCO_PAPER: 2, KURAMOTO: 1, GOODWIN3: 3, CLOCK4: 4}
 MLP_IN, MLP_HID, MLP_PARAMS = 9, 64, 4883

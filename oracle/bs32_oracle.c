@@ -27,7 +27,9 @@
  * eigendecomposition); uncoupled Kuramoto; the Kuramoto order-parameter
  * identity for uniform weights; the two-oscillator Adler equation; the Goodwin
  * fixed point; quantizer bit patterns; DP5(4) against an independent library
- * integrator.  The paper recipes (orc_rhs_recipe) are pinned only by their
+ * integrator; the BF16-pair storage (hi + rounded remainder, the conclusion's
+ * extension to other formats) by exact pairs, its 2^-17 bound and its reduction
+ * to BF16 on BF16 weights.  The paper recipes (orc_rhs_recipe) are pinned only by their
  * reductions (all-double equals orc_rhs; single results are float values) and
  * are otherwise parity unpinned: the paper prints no per-test numbers.
  */
@@ -266,6 +268,11 @@ static fmt_desc fmt_of(int fmt) {
 
 double orc_round_fmt(double x, int fmt) {
   if (fmt == ORC_FMT_F64) return x;
+  if (fmt == ORC_FMT_BF16X2) { /* the stored pair's value: hi + round(x - hi), exact in FP64 */
+    const double hi = orc_round_fmt(x, ORC_FMT_BF16);
+    if (!isfinite(hi)) return hi;
+    return hi + orc_round_fmt(x - hi, ORC_FMT_BF16);
+  }
   fmt_desc f = fmt_of(fmt);
   if (isnan(x) || x == 0.0) return x;
   double a = fabs(x);
@@ -346,7 +353,8 @@ void orc_split(double v, int fmt, int terms, int shift, double* out) {
 static void split_defaults(int fmt, int* sfmt, int* terms, int* shift) {
   switch (fmt) {
     case ORC_FMT_F32: *sfmt = ORC_FMT_F32; *terms = 2; *shift = 24; break;
-    case ORC_FMT_BF16: *sfmt = ORC_FMT_BF16; *terms = 2; *shift = 8; break;
+    case ORC_FMT_BF16:
+    case ORC_FMT_BF16X2: *sfmt = ORC_FMT_BF16; *terms = 2; *shift = 8; break;
     case ORC_FMT_F16: *sfmt = ORC_FMT_F16; *terms = 2; *shift = 11; break;
     case ORC_FMT_E4M3: *sfmt = ORC_FMT_E4M3; *terms = 3; *shift = 4; break;
     default: *sfmt = ORC_FMT_F64; *terms = 1; *shift = 0; break;
@@ -595,7 +603,8 @@ static int eval_stage(evaluator* e, int stage, double t, const double* Y, double
     case ORC_PREC_RHS_FP32:
     case ORC_PREC_RHS_BF16:
     case ORC_PREC_RHS_FP16:
-    case ORC_PREC_RHS_FP8: return lowp_rhs(&e->lp, Y, K);
+    case ORC_PREC_RHS_FP8:
+    case ORC_PREC_RHS_BF16X2: return lowp_rhs(&e->lp, Y, K);
     default: {
       const int r = e->mode - ORC_PREC_PAPER_SINGLE;
       const int* p = RECIPE[r][stage - 2];
@@ -610,6 +619,7 @@ static int mode_fmt(int mode) {
     case ORC_PREC_RHS_BF16: return ORC_FMT_BF16;
     case ORC_PREC_RHS_FP16: return ORC_FMT_F16;
     case ORC_PREC_RHS_FP8: return ORC_FMT_E4M3;
+    case ORC_PREC_RHS_BF16X2: return ORC_FMT_BF16X2;
     default: return ORC_FMT_F64;
   }
 }
@@ -742,7 +752,7 @@ static void fill_defaults(const orc_options* o, double t0, double t1, double* h_
 int orc_bs32_solve(const orc_system* s, const orc_options* o, int mode, const double* y0, double t0, double t1,
                    double* y_out, orc_stats* st, orc_trace_rec* trace, int64_t trace_cap, int64_t* trace_len) {
   const int d = orc_dim(s->kind);
-  if (d == 0 || s->n <= 0 || !(o->rtol > 0.0) || !(o->atol >= 0.0) || !(t1 >= t0) || mode < 0 || mode > 7)
+  if (d == 0 || s->n <= 0 || !(o->rtol > 0.0) || !(o->atol >= 0.0) || !(t1 >= t0) || mode < 0 || mode > 8)
     return ORC_EINVAL;
   if (o->fixed_step && !(o->h0 > 0.0)) return ORC_EINVAL;
   const int64_t m = (int64_t)d * s->n;
@@ -765,7 +775,7 @@ int orc_bs32_solve(const orc_system* s, const orc_options* o, int mode, const do
   ev.s = s;
   ev.mode = mode;
   ev.has_lp = 0;
-  if (mode >= ORC_PREC_RHS_FP32 && mode <= ORC_PREC_RHS_FP8) {
+  if ((mode >= ORC_PREC_RHS_FP32 && mode <= ORC_PREC_RHS_FP8) || mode == ORC_PREC_RHS_BF16X2) {
     if (lowp_init(&ev.lp, s, mode_fmt(mode), o->split_fmt, o->split_terms, o->split_shift) != ORC_OK)
       return ORC_EINVAL;
     ev.has_lp = 1;

@@ -36,6 +36,7 @@ extern "C" {
 #define ORC_FMT_BF16 2
 #define ORC_FMT_F16 3
 #define ORC_FMT_E4M3 4 /* OCP e4m3fn, saturating */
+#define ORC_FMT_BF16X2 5 /* a pair of BF16 values hi + lo, lo = the remainder x - hi rounded to BF16 */
 
 /* precision modes */
 #define ORC_PREC_FP64 0
@@ -46,6 +47,7 @@ extern "C" {
 #define ORC_PREC_PAPER_SINGLE 5
 #define ORC_PREC_PAPER_MIXED1 6
 #define ORC_PREC_PAPER_MIXED2 7
+#define ORC_PREC_RHS_BF16X2 8 /* coupling as BF16 pairs, operand in two BF16 terms */
 
 /* termination codes (paper Sec. 2.2, "Failure conditions") */
 #define ORC_OK 0

@@ -99,3 +99,52 @@ def test_matrix_scale_power_of_two(orc):
     s = orc.matrix_scale(A, 4)
     assert s == 2.0**-8 and np.max(A) / s <= 448
     assert orc.matrix_scale(A * 1000, 4) == 4.0
+
+
+def test_bf16_pair_represents_hi_plus_lo(orc):
+    # every value hi + lo with hi a BF16 value and lo a BF16 value within half an ulp of
+    # hi is stored exactly by the pair format
+    rng = np.random.default_rng(40)
+    for _ in range(2000):
+        hi = orc.round_fmt(rng.uniform(-4.0, 4.0), orc.FMT_BF16)
+        if hi == 0.0:
+            continue
+        ulp = 2.0 ** (np.floor(np.log2(abs(hi))) - 7)
+        lo = orc.round_fmt(rng.uniform(-0.5, 0.5) * ulp, orc.FMT_BF16)
+        assert orc.round_fmt(hi + lo, orc.FMT_BF16X2) == hi + lo
+
+
+def test_bf16_pair_error_bound_and_order(orc):
+    # |x - pair(x)| <= 2^-17 |x|: half an ulp of the 8-bit hi, then half an ulp of the
+    # 8-bit remainder; far finer than one BF16 value, coarser than FP32
+    rng = np.random.default_rng(41)
+    x = rng.uniform(-3.0, 3.0, 5000) * 2.0 ** rng.integers(-20, 20, 5000)
+    e2 = np.array([abs(v - orc.round_fmt(v, orc.FMT_BF16X2)) for v in x])
+    e1 = np.array([abs(v - orc.round_fmt(v, orc.FMT_BF16)) for v in x])
+    e32 = np.array([abs(v - orc.round_fmt(v, orc.FMT_F32)) for v in x])
+    assert np.all(e2 <= 2.0 ** -17 * np.abs(x))
+    assert np.median(e2 / np.abs(x)) < np.median(e1 / np.abs(x)) / 100
+    assert np.median(e32 / np.abs(x)) < np.median(e2 / np.abs(x))
+
+
+def test_bf16_pair_mode_reduces_to_bf16_on_bf16_weights(orc):
+    # weights that BF16 holds exactly have lo = 0: the pair mode is the BF16 mode
+    rng = np.random.default_rng(42)
+    n = 40
+    A = rng.integers(0, 256, (n, n)) / 256.0
+    om = rng.standard_normal(n)
+    th = rng.uniform(0, 2 * np.pi, n)
+    f8 = orc.rhs_lowp(orc.KURAMOTO, n, th, orc.FMT_BF16X2, A=A, param=om, gain=2.0)
+    f2 = orc.rhs_lowp(orc.KURAMOTO, n, th, orc.FMT_BF16, A=A, param=om, gain=2.0)
+    np.testing.assert_array_equal(f8, f2)
+    y8, s8, _ = orc.bs32_solve(orc.KURAMOTO, n, th, 0.0, 1.0, 1e-6, A=A, param=om, gain=2.0,
+                               mode=orc.PREC_RHS_BF16X2)
+    y2, s2, _ = orc.bs32_solve(orc.KURAMOTO, n, th, 0.0, 1.0, 1e-6, A=A, param=om, gain=2.0,
+                               mode=orc.PREC_RHS_BF16)
+    np.testing.assert_array_equal(y8, y2)
+    # on random weights the pair's storage error sits between FP32's and BF16's
+    A = rng.random((n, n))
+    ref = orc.rhs(orc.KURAMOTO, n, th, A=A, param=om, gain=2.0)
+    err = {f: np.max(np.abs(orc.rhs_lowp(orc.KURAMOTO, n, th, f, A=A, param=om, gain=2.0) - ref))
+           for f in (orc.FMT_F32, orc.FMT_BF16X2, orc.FMT_BF16)}
+    assert err[orc.FMT_F32] < err[orc.FMT_BF16X2] < err[orc.FMT_BF16] / 30
