@@ -40,7 +40,8 @@ Other measurement configurations, one JSON line each:
       coupling (N = 8192, A ~ U[0,1) zero diagonal) with their own K ~ U[0.5, 4),
       omega ~ N(0,1) and theta0, t in [0, 10], rtol = atol = 1e-6; every stage is
       one matrix product A [V_1 ... V_256] on the matrix cores (FP64, FP32, BF16,
-      FP16 storage), against plain FP64 single-system solves of the instances.
+      FP16 storage, and the BF16 pair: hi + lo BF16 planes), against plain FP64
+      single-system solves of the instances.
   c5  learned step-size proposer trained on solver traces of the c1-c3 laws,
       run on Kuramoto N = 32768 (t in [0, 50]) and coupled oscillators
       N = 32768 (t in [0, 10]), FP64 coupling, rtol = atol = 1e-7, against the
@@ -62,7 +63,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES = {0: 8, 1: 4, 2: 2, 3: 2, 4: 1}
-DTYPE = {0: "f64", 1: "f32", 2: "bf16", 3: "f16", 4: "fp8e4m3"}
+DTYPE = {0: "f64", 1: "f32", 2: "bf16", 3: "f16", 4: "fp8e4m3", 8: "bf16x2"}
 METRIC = "pair-interactions/s + time-to-t_end vs plain FP64 GPU at matched final error"
 KERNEL_SOURCES = ("bs32_kernels.hip", "bs32_internal.hpp", "bs32_mlp.hpp")
 
@@ -697,7 +698,9 @@ def bench_ensemble(args, torch, bs, modes, ref_rtol):
 # ---------------------------------------------------------------------------
 # f3: parameter sweep on one network (shared-coupling product)
 # ---------------------------------------------------------------------------
-MFMA_PEAK_TFLOPS = {0: 78.6, 1: 157.3, 2: 2500.0, 3: 2500.0}  # dense matrix-core peaks of MI355X
+MFMA_PEAK_TFLOPS = {0: 78.6, 1: 157.3, 2: 2500.0, 3: 2500.0, 8: 2500.0}  # dense matrix-core peaks of MI355X
+# executed products per algorithmic one: operand terms x planes of A
+EXEC_FACTOR = {0: 1, 1: 2, 2: 2, 3: 2, 8: 4}
 
 
 def bench_shared(args, torch, bs, modes, ref_rtol):
@@ -794,7 +797,7 @@ def bench_shared(args, torch, bs, modes, ref_rtol):
             "frac": round(rh["contraction_tflops"] / peak, 4), "traffic": None,
             "kernel": rh["kernel"] + f" over {B} instances",
             "flops_per_launch": 2.0 * n * n * B * 2, "avg_launch_ms": rh["contraction_ms"],
-            "executed_flops_per_launch": 2.0 * n * n * B * 2 * (1 if head == 0 else 2)}
+            "executed_flops_per_launch": 2.0 * n * n * B * 2 * EXEC_FACTOR[head]}
     line = base_line(args, rh["pairs_per_s"], rh["ms_per_step"],
                      ("f64" if head == 0 else DTYPE[head]) + "+f64-update",
                      {"workload": f"kuramoto-shared-network B={B} N={n} K=U[0.5,4) omega=N(0,1) t=[0,{t1:g}] "
@@ -967,7 +970,7 @@ def main():
     elif args.config == "f2":
         line = bench_accuracy(args, torch, bs)
     elif args.config == "f3":
-        line = bench_shared(args, torch, bs, modes if modes is not None else [0, 1, 2, 3], args.ref_rtol or 1e-9)
+        line = bench_shared(args, torch, bs, modes if modes is not None else [0, 1, 2, 3, 8], args.ref_rtol or 1e-9)
     elif args.config == "c4":
         line = bench_ensemble(args, torch, bs, modes if modes is not None else [0, 1, 2, 3], args.ref_rtol or 1e-9)
     else:

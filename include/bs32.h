@@ -95,7 +95,14 @@ typedef enum {
   BS32_PREC_PAPER_SINGLE = 5, /* k2, k3, k4 all single; solution and stage inputs stored FP32;
                                  h_min = 100 eps of FP32 */
   BS32_PREC_PAPER_MIXED1 = 6, /* k2, k3 all single; k4: F and Sigma double, G single */
-  BS32_PREC_PAPER_MIXED2 = 7  /* k2, k3, k4: F and Sigma double, G single */
+  BS32_PREC_PAPER_MIXED2 = 7, /* k2, k3, k4: F and Sigma double, G single */
+  /* each weight stored as a BF16 pair hi + lo (lo = the remainder A/s - hi rounded to
+     BF16: about 16 significant bits), the operand split into two BF16 terms, the
+     contraction (hi + lo) V accumulated in FP32 on the matrix cores within 128-element
+     chunks and in FP64 across them; the conclusion's extension of the approach to
+     other number formats.  Shared-coupling ensembles only (EUNSUPPORTED elsewhere);
+     bs32_get_packed_coupling returns the hi plane followed by the lo plane. */
+  BS32_PREC_RHS_BF16X2 = 8
 } bs32_precision_mode;
 
 typedef struct {

@@ -26,12 +26,12 @@ OSC2, LCO_PAPER, KURAMOTO, GOODWIN3, CLOCK4 = 1, 2, 3, 4, 5
 DIM = {OSC2: 2, LCO_PAPER: 2, KURAMOTO: 1, GOODWIN3: 3, CLOCK4: 4}
 # bs32_precision_mode
 (PREC_FP64, PREC_RHS_FP32, PREC_RHS_BF16, PREC_RHS_FP16, PREC_RHS_FP8_E4M3,
- PREC_PAPER_SINGLE, PREC_PAPER_MIXED1, PREC_PAPER_MIXED2) = range(8)
+ PREC_PAPER_SINGLE, PREC_PAPER_MIXED1, PREC_PAPER_MIXED2, PREC_RHS_BF16X2) = range(9)
 MLP_PARAMS = 4883  # BS32_MLP_PARAMS
 METHOD_BS32, METHOD_DP54 = 0, 1  # bs32_method
 MLP_IN = 9
 MODE_NAMES = {0: "fp64", 1: "rhs_fp32", 2: "rhs_bf16", 3: "rhs_fp16", 4: "rhs_fp8_e4m3", 5: "paper_single",
-              6: "paper_mixed1", 7: "paper_mixed2"}
+              6: "paper_mixed1", 7: "paper_mixed2", 8: "rhs_bf16x2"}
 
 
 class SystemDesc(C.Structure):
@@ -345,8 +345,11 @@ class Solver:
 
     def packed_coupling(self, mode):
         """(stored N x N matrix as raw format values, power-of-two scale) for a precision mode."""
-        dt = {0: np.float64, 1: np.float32, 2: np.uint16, 3: np.uint16, 4: np.uint8}[min(int(mode), 4)]
-        buf = np.empty((self.n, self.n), dtype=dt)
+        if int(mode) == PREC_RHS_BF16X2:   # hi plane, then lo plane
+            buf = np.empty((2, self.n, self.n), dtype=np.uint16)
+        else:
+            dt = {0: np.float64, 1: np.float32, 2: np.uint16, 3: np.uint16, 4: np.uint8}[min(int(mode), 4)]
+            buf = np.empty((self.n, self.n), dtype=dt)
         sc = C.c_double(0)
         self._check(lib().bs32_get_packed_coupling(self._ctx, int(mode), buf.ctypes.data, buf.nbytes, C.byref(sc)))
         return buf, sc.value

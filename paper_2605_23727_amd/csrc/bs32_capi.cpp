@@ -25,7 +25,7 @@ using namespace bs32;
 
 namespace {
 
-constexpr int kNumFmt = 5;
+constexpr int kNumFmt = 6;
 
 // per-format vector-operand split (reading of the reduced-precision contraction)
 struct VecSplit {
@@ -35,7 +35,8 @@ struct VecSplit {
 VecSplit vec_split(int fmt) {
   switch (fmt) {
     case F_F32: return {F_F32, 2, 24, 3.0e38};
-    case F_BF16: return {F_BF16, 2, 8, 3.0e38};
+    case F_BF16:
+    case F_BF16X2: return {F_BF16, 2, 8, 3.0e38};
     case F_F16: return {F_F16, 2, 11, 65504.0};
     case F_E4M3: return {F_E4M3, 3, 4, 448.0};
     default: return {F_F64, 1, 0, INFINITY};
@@ -49,6 +50,7 @@ int mode_fmt(int mode) {
     case BS32_PREC_RHS_BF16: return F_BF16;
     case BS32_PREC_RHS_FP16: return F_F16;
     case BS32_PREC_RHS_FP8_E4M3: return F_E4M3;
+    case BS32_PREC_RHS_BF16X2: return F_BF16X2;
     case BS32_PREC_PAPER_SINGLE:
     case BS32_PREC_PAPER_MIXED1:
     case BS32_PREC_PAPER_MIXED2: return F_F32;  // the recipes' single-precision pair terms
@@ -90,7 +92,7 @@ struct bs32_ctx {
   double* param = nullptr;
   void* Aq[kNumFmt] = {};       // packed coupling per storage format (FP64 always present)
   double* rsum[kNumFmt] = {};   // row sums of the stored matrix per format
-  double scale[kNumFmt] = {1, 1, 1, 1, 1};
+  double scale[kNumFmt] = {1, 1, 1, 1, 1, 1};
   bool tuned[kNumFmt] = {};
   Tile best[kNumFmt] = {};
 
@@ -434,7 +436,9 @@ int tile_index(const bs32_ctx* c, int fmt, const Tile& t) {
 // picks the tile: explicit option index into the candidate list, else the autotuned one
 bs32_status prepare(bs32_ctx* c, int mode, Geom* g, int* fmt) {
   if (!c->has_sys) return fail(c, BS32_ESTATE, "no system set");
-  if (mode < 0 || mode > 7) return fail(c, BS32_EINVAL, "unknown precision mode %d", mode);
+  if (mode < 0 || mode > BS32_PREC_RHS_BF16X2) return fail(c, BS32_EINVAL, "unknown precision mode %d", mode);
+  if (mode == BS32_PREC_RHS_BF16X2)
+    return fail(c, BS32_EUNSUPPORTED, "BF16-pair storage serves the shared-coupling product (bs32_set_shared_ensemble)");
   if (c->pairwise && mode >= BS32_PREC_RHS_FP32 && mode <= BS32_PREC_RHS_FP8_E4M3)
     return fail(c, BS32_EUNSUPPORTED, "pairwise couplings have no stored-matrix formats (modes 0, 5-7)");
   *fmt = mode_fmt(mode);
@@ -734,7 +738,7 @@ bs32_status bs32_time_contraction(bs32_ctx* c, int mode, int repeat, double* avg
 
 bs32_status bs32_kernel_name(bs32_ctx* c, int mode, int tile, char* buf, size_t cap) {
   if (!c || !buf || cap == 0) return fail(c, BS32_EINVAL, "null argument");
-  if (mode < 0 || mode > BS32_PREC_PAPER_MIXED2) return fail(c, BS32_EINVAL, "unknown precision mode %d", mode);
+  if (mode < 0 || mode > BS32_PREC_RHS_BF16X2) return fail(c, BS32_EINVAL, "unknown precision mode %d", mode);
   int m = 0;
   if (c->has_sys) m = c->m;
   else if (c->ens) m = ens_vcols(c);
@@ -752,7 +756,8 @@ bs32_status bs32_kernel_name(bs32_ctx* c, int mode, int tile, char* buf, size_t 
 bs32_status bs32_get_packed_coupling(bs32_ctx* c, int mode, void* dst, size_t bytes, double* scale) {
   if (!c || !dst || !scale) return fail(c, BS32_EINVAL, "null argument");
   if (!c->has_sys) return fail(c, BS32_ESTATE, "no system set");
-  if (mode < 0 || mode > BS32_PREC_RHS_FP8_E4M3) return fail(c, BS32_EINVAL, "mode %d has no packed matrix", mode);
+  if (mode < 0 || (mode > BS32_PREC_RHS_FP8_E4M3 && mode != BS32_PREC_RHS_BF16X2))
+    return fail(c, BS32_EINVAL, "mode %d has no packed matrix", mode);
   if (c->uniform) return fail(c, BS32_ESTATE, "a pairwise system with uniform weights stores no matrix");
   HIPCHK(c, hipSetDevice(c->device));
   const int fmt = mode_fmt(mode);
@@ -762,8 +767,16 @@ bs32_status bs32_get_packed_coupling(bs32_ctx* c, int mode, void* dst, size_t by
   if (s != BS32_OK) return s;
   s = ensure_packed(c, fmt);
   if (s != BS32_OK) return s;
-  HIPCHK(c, hipMemcpy2DAsync(dst, es * (size_t)c->n, c->Aq[fmt], es * (size_t)c->ld, es * (size_t)c->n,
-                             (size_t)c->n, hipMemcpyDeviceToHost, c->stream));
+  if (fmt == F_BF16X2) {  // the hi plane, then the remainder plane, each N x N BF16
+    const size_t plane = 2 * (size_t)c->np * (size_t)c->ld;
+    for (int q = 0; q < 2; ++q)
+      HIPCHK(c, hipMemcpy2DAsync((char*)dst + q * 2 * (size_t)(c->n * c->n), 2 * (size_t)c->n,
+                                 (const char*)c->Aq[fmt] + q * plane, 2 * (size_t)c->ld, 2 * (size_t)c->n, (size_t)c->n,
+                                 hipMemcpyDeviceToHost, c->stream));
+  } else {
+    HIPCHK(c, hipMemcpy2DAsync(dst, es * (size_t)c->n, c->Aq[fmt], es * (size_t)c->ld, es * (size_t)c->n,
+                               (size_t)c->n, hipMemcpyDeviceToHost, c->stream));
+  }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   *scale = c->scale[fmt];
   return BS32_OK;

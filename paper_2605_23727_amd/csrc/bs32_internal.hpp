@@ -41,7 +41,9 @@ enum Stage : int {
 };
 
 // storage formats of the coupling matrix
-enum Fmt : int { F_F64 = 0, F_F32 = 1, F_BF16 = 2, F_F16 = 3, F_E4M3 = 4 };
+// (F_BF16X2: each weight as a BF16 pair hi + lo, lo = the remainder rounded to BF16,
+// stored as two planes of np x ld values; the shared-coupling product only)
+enum Fmt : int { F_F64 = 0, F_F32 = 1, F_BF16 = 2, F_F16 = 3, F_E4M3 = 4, F_BF16X2 = 5 };
 
 // Device-resident control block of one solve: the step-size state lives on the
 // GPU so that attempts run back to back without host round trips.  Two buffers

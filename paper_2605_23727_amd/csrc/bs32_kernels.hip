@@ -16,6 +16,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "bs32_internal.hpp"
 #include "bs32_mlp.hpp"
@@ -44,7 +45,9 @@ int vcols_of(int kind, int pairwise) { return (kind == 3 && !pairwise) ? 2 : 1; 
 // constants of the clock / cell-cycle model, paper eq. (CC) (Sec. 2.1); k1 is per cell
 constexpr double kCcK0 = 2.0, kCcK2 = 0.144832, kCcK3 = 2.0, kCcA = 2.0, kCcB = 0.7, kCcC = 0.8,
                  kCcEps = 0.228249;
-size_t fmt_bytes(int fmt) { return fmt == F_F64 ? 8 : fmt == F_F32 ? 4 : (fmt == F_BF16 || fmt == F_F16) ? 2 : 1; }
+size_t fmt_bytes(int fmt) {
+  return fmt == F_F64 ? 8 : (fmt == F_F32 || fmt == F_BF16X2) ? 4 : (fmt == F_BF16 || fmt == F_F16) ? 2 : 1;
+}
 
 // ---------------------------------------------------------------------------
 // small helpers
@@ -146,6 +149,13 @@ __device__ inline double decode_bits(uint32_t b, FmtDesc f) {
   return s ? -v : v;
 }
 
+// one pointer of a two-pointer pair in the argument block: a select, never an
+// index computed at run time (which would copy the whole by-value block to scratch)
+template <typename P>
+__device__ __forceinline__ P pick2(P const (&p)[2], int q) {
+  return q ? p[1] : p[0];
+}
+
 // ---------------------------------------------------------------------------
 // vector operand of one agent and its split into reduced-format terms
 // ---------------------------------------------------------------------------
@@ -168,7 +178,7 @@ struct VSplit {
 // r_{t+1} = r_t - 2^(-t S) Q(r_t 2^(t S)).  (Scaling by a power of two is exact,
 // so the products below equal ldexp.)
 template <int VF>
-__device__ void write_vq_t(const Args& a, void* Vq, long long i, const double* v) {
+__device__ __forceinline__ void write_vq_t(const Args& a, void* Vq, long long i, const double* v) {
   if constexpr (VF == F_F64) {
     return;
   } else {
@@ -205,8 +215,8 @@ template <int VF>
 __device__ __forceinline__ void write_operand_t(const Args& a, int buf, long long i, double y) {
   double v[2];
   vec_of(a, y, v);
-  for (int c = 0; c < a.m; ++c) a.V64[buf][i * a.m + c] = v[c];
-  write_vq_t<VF>(a, a.Vq[buf], i, v);
+  for (int c = 0; c < a.m; ++c) pick2(a.V64, buf)[i * a.m + c] = v[c];
+  write_vq_t<VF>(a, pick2(a.Vq, buf), i, v);
 }
 
 // the same with the format known only at run time (prep and finalize serve every format)
@@ -223,6 +233,9 @@ __device__ __forceinline__ void write_operand(const Args& a, int buf, long long 
 // F_i(Y_i) + coupling of agent i from the contraction P_i (Sec. 2.1 benchmarks with
 // weights A_ij/N).  vself: the agent's own vector operand (sin, cos of theta_i);
 // p: its parameter (omega or b); rs: its row sum of the stored weights.
+// LEAN: the matrix-vector systems only (ensembles serve no pairwise coupling), so
+// that the code of a kernel's per-item tail stays small
+template <bool LEAN = false>
 __device__ __forceinline__ void rhs_agent(const Args& a, const double* y, const double* P, const double* vself,
                                           double p, double rs, double* k) {
   switch (a.kind) {
@@ -235,16 +248,18 @@ __device__ __forceinline__ void rhs_agent(const Args& a, const double* y, const 
       k[1] = -y[0];
       break;
     case 3:  // paper eq. (Kuramoto): sum_j A_ij sin(th_j - th_i) = cos th_i (A sin th)_i - sin th_i (A cos th)_i
-      if (a.pairwise) k[0] = p + a.gain * a.invN * P[0];  // P = sum_j A_ij sin(th_j - th_i) pair by pair
+      if (!LEAN && a.pairwise) k[0] = p + a.gain * a.invN * P[0];  // P = sum_j A_ij sin(th_j - th_i) pair by pair
       else k[0] = p + a.gain * a.invN * (vself[1] * P[0] - vself[0] * P[1]);
       break;
     case 5: {  // paper eq. (CC): P = sum_j A_ij arctan(X_j1 - X_i1), the pair prefactor depends on X_i2
-      const double th = p / (kCcK0 - p);
-      const double q = kCcK0 * th / (th + y[1] * y[1] * y[1] * y[1]);
-      k[0] = q * (kCcA * y[0] * y[0] + 1.0) - p * y[0] + (q * kCcA) * a.gain * a.invN * P[0];
-      k[1] = kCcK2 * (y[0] - y[1]);
-      k[2] = y[2] * (1.0 - y[2] * y[2] / 3.0) - y[3] + a.stim * (1.0 - kCcK3 * kCcK3 / (kCcK3 * kCcK3 + y[0] * y[0]));
-      k[3] = kCcEps * (y[2] + kCcB - kCcC * y[3]);
+      if constexpr (!LEAN) {
+        const double th = p / (kCcK0 - p);
+        const double q = kCcK0 * th / (th + y[1] * y[1] * y[1] * y[1]);
+        k[0] = q * (kCcA * y[0] * y[0] + 1.0) - p * y[0] + (q * kCcA) * a.gain * a.invN * P[0];
+        k[1] = kCcK2 * (y[0] - y[1]);
+        k[2] = y[2] * (1.0 - y[2] * y[2] / 3.0) - y[3] + a.stim * (1.0 - kCcK3 * kCcK3 / (kCcK3 * kCcK3 + y[0] * y[0]));
+        k[3] = kCcEps * (y[2] + kCcB - kCcC * y[3]);
+      }
       break;
     }
     default: {  // Goodwin clock: x' = 1/(1+z^10) - b x + (kappa/N) sum_j C_ij (x_j - x_i)
@@ -307,10 +322,12 @@ __device__ __forceinline__ void rhs_agent_f32(const Args& a, const double* y, co
   }
 }
 
+// (LEAN: no recipes either; ensembles run the storage-format modes only)
+template <bool LEAN = false>
 __device__ __forceinline__ void rhs_eval(const Args& a, const double* y, const double* P, const double* vself,
                                          double p, double rs, double* k) {
-  if (a.fsingle) rhs_agent_f32(a, y, P, vself, p, rs, k);
-  else rhs_agent(a, y, P, vself, p, rs, k);
+  if (!LEAN && a.fsingle) rhs_agent_f32(a, y, P, vself, p, rs, k);
+  else rhs_agent<LEAN>(a, y, P, vself, p, rs, k);
 }
 
 // Single keeps its solution and stage inputs in FP32
@@ -338,9 +355,9 @@ __device__ __forceinline__ void load_row(const Args& a, const Ctl* ctl, long lon
   const long long np = a.np;
   const int st = a.stage;
   if (st >= ST_D2) return;  // the Dormand-Prince epilogue loads its own inputs
-  const double* X = a.X[ctl->xi];
-  const double* K1 = a.Kf[ctl->ki];
-  const double* Vin = a.V64[vin_of(st)];
+  const double* X = pick2(a.X, ctl->xi);
+  const double* K1 = pick2(a.Kf, ctl->ki);
+  const double* Vin = pick2(a.V64, vin_of(st));
   r.p = a.param[i];
   r.rs = a.rsum ? a.rsum[i] : 0.0;  // pairwise systems with uniform weights keep no row sums
   r.vs[0] = Vin[i * a.m];
@@ -354,13 +371,13 @@ __device__ __forceinline__ void load_row(const Args& a, const Ctl* ctl, long lon
     if (st == ST_S3 || st == ST_S4) r.k2[c] = a.K2[c * np + i];
     if (st == ST_S4) {
       r.k3[c] = a.K3[c * np + i];
-      r.xn[c] = a.X[1 - ctl->xi][c * np + i];
+      r.xn[c] = pick2(a.X, 1 - ctl->xi)[c * np + i];
     }
   }
 }
 
-template <int VF>
-__device__ void epilogue(const Args& a, const Ctl* ctl, long long i, const double* P, const RowIn& r, double* r0,
+template <int VF, bool LEAN = false>
+__device__ __forceinline__ void epilogue(const Args& a, const Ctl* ctl, long long i, const double* P, const RowIn& r, double* r0,
                          double* r1) {
   const int d = a.d;
   const long long np = a.np;
@@ -373,8 +390,8 @@ __device__ void epilogue(const Args& a, const Ctl* ctl, long long i, const doubl
     case ST_RHS: {
 #pragma unroll
       for (int c = 0; c < 4; ++c) y[c] = r.x[c];
-      rhs_eval(a, y, P, r.vs, r.p, r.rs, k);
-      double* K = a.Kf[ctl->ki];
+      rhs_eval<LEAN>(a, y, P, r.vs, r.p, r.rs, k);
+      double* K = pick2(a.Kf, ctl->ki);
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         if (c >= d) break;
@@ -388,7 +405,7 @@ __device__ void epilogue(const Args& a, const Ctl* ctl, long long i, const doubl
     case ST_H0: {
 #pragma unroll
       for (int c = 0; c < 4; ++c) y[c] = r.x[c] + ctl->h0probe * r.k1[c];
-      rhs_eval(a, y, P, r.vs, r.p, r.rs, k);
+      rhs_eval<LEAN>(a, y, P, r.vs, r.p, r.rs, k);
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         if (c >= d) break;
@@ -400,7 +417,7 @@ __device__ void epilogue(const Args& a, const Ctl* ctl, long long i, const doubl
     case ST_S2: {
 #pragma unroll
       for (int c = 0; c < 4; ++c) y[c] = sstore(a, r.x[c] + ha * (kA21 * r.k1[c]));
-      rhs_eval(a, y, P, r.vs, r.p, r.rs, k);
+      rhs_eval<LEAN>(a, y, P, r.vs, r.p, r.rs, k);
 #pragma unroll
       for (int c = 0; c < 4; ++c)
         if (c < d) a.K2[c * np + i] = k[c];
@@ -408,10 +425,10 @@ __device__ void epilogue(const Args& a, const Ctl* ctl, long long i, const doubl
       break;
     }
     case ST_S3: {
-      double* Xn = a.X[1 - ctl->xi];
+      double* Xn = pick2(a.X, 1 - ctl->xi);
 #pragma unroll
       for (int c = 0; c < 4; ++c) y[c] = sstore(a, r.x[c] + ha * (kA32 * r.k2[c]));
-      rhs_eval(a, y, P, r.vs, r.p, r.rs, k);
+      rhs_eval<LEAN>(a, y, P, r.vs, r.p, r.rs, k);
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         if (c >= d) break;
@@ -424,10 +441,10 @@ __device__ void epilogue(const Args& a, const Ctl* ctl, long long i, const doubl
       break;
     }
     case ST_S4: {
-      double* K4 = a.Kf[1 - ctl->ki];
+      double* K4 = pick2(a.Kf, 1 - ctl->ki);
 #pragma unroll
       for (int c = 0; c < 4; ++c) y[c] = r.xn[c];
-      rhs_eval(a, y, P, r.vs, r.p, r.rs, k);
+      rhs_eval<LEAN>(a, y, P, r.vs, r.p, r.rs, k);
       const double floor_w = ctl->atol / ctl->rtol;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
@@ -451,17 +468,19 @@ __device__ void epilogue(const Args& a, const Ctl* ctl, long long i, const doubl
 // it as X^{n+1} too), or at stage 7 (FSAL, evaluated at X^{n+1}) the difference of
 // the two solutions h sum_l (b_l - bt_l) K_l and its weights.  The sums run over l in
 // increasing order, FP64.
-template <int VF>
-__device__ void epilogue_dp(const Args& a, const Ctl* ctl, long long i, const double* P, double* r0,
-                            double* r1) {
-  const int s = a.stage - ST_D2 + 2;
+template <int VF, int S>
+__device__ __forceinline__ void epilogue_dp_s(const Args& a, const Ctl* ctl, long long i, const double* P,
+                                              double* r0, double* r1) {
+  // every index below is a compile-time constant, so the stages live in registers
   const int d = a.d;
   const long long np = a.np;
   const double ha = ctl->ha;
-  double* Kl[7] = {a.Kf[ctl->ki], a.K2, a.K3, a.Kd[0], a.Kd[1], a.Kd[2], a.Kf[1 - ctl->ki]};
-  const double* X = a.X[ctl->xi];
-  double* Xn = a.X[1 - ctl->xi];
-  const double* Vin = a.V64[vin_of(a.stage)];
+  const double* X = pick2(a.X, ctl->xi);
+  double* Xn = pick2(a.X, 1 - ctl->xi);
+  auto kbuf = [&](int l) -> double* {  // K_{l+1}
+    return l == 0 ? pick2(a.Kf, ctl->ki) : l == 1 ? a.K2 : l == 2 ? a.K3 : l == 6 ? pick2(a.Kf, 1 - ctl->ki) : l == 3 ? a.Kd[0] : l == 4 ? a.Kd[1] : a.Kd[2];
+  };
+  const double* Vin = pick2(a.V64, vin_of(ST_D2 + S - 2));
   double vs[2];
   vs[0] = Vin[i * a.m];
   vs[1] = a.m > 1 ? Vin[i * a.m + 1] : 0.0;
@@ -473,56 +492,66 @@ __device__ void epilogue_dp(const Args& a, const Ctl* ctl, long long i, const do
     if (c >= d) break;
     x[c] = X[c * np + i];
 #pragma unroll
-    for (int l = 0; l < 6; ++l)
-      if (l < s - 1) K[l][c] = Kl[l][c * np + i];
+    for (int l = 0; l < S - 1; ++l) K[l][c] = kbuf(l)[c * np + i];
   }
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     if (c >= d) break;
-    if (s == 7) {
+    if constexpr (S == 7) {
       y[c] = Xn[c * np + i];
     } else {
       double acc = 0.0;
 #pragma unroll
-      for (int l = 0; l < 6; ++l)
-        if (l < s - 1) acc += kDpA[s - 1][l] * K[l][c];
+      for (int l = 0; l < S - 1; ++l) acc += kDpA[S - 1][l] * K[l][c];
       y[c] = x[c] + ha * acc;
     }
   }
   rhs_eval(a, y, P, vs, p, rs, k);
+  double* Ks = kbuf(S - 1);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     if (c >= d) break;
-    Kl[s - 1][c * np + i] = k[c];
-    K[s - 1][c] = k[c];
+    Ks[c * np + i] = k[c];
+    K[S - 1][c] = k[c];
   }
   *r0 = 0.0;
   *r1 = 0.0;
-  if (s < 7) {
+  if constexpr (S < 7) {
     double yn[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       if (c >= d) break;
       double acc = 0.0;
 #pragma unroll
-      for (int l = 0; l < 6; ++l)
-        if (l < s) acc += kDpA[s][l] * K[l][c];
+      for (int l = 0; l < S; ++l) acc += kDpA[S][l] * K[l][c];
       yn[c] = x[c] + ha * acc;
-      if (s == 6) Xn[c * np + i] = yn[c];
+      if constexpr (S == 6) Xn[c * np + i] = yn[c];
     }
-    write_operand_t<VF>(a, vin_of(a.stage + 1), i, yn[0]);
-    return;
+    write_operand_t<VF>(a, vin_of(ST_D2 + S - 1), i, yn[0]);
+  } else {
+    const double floor_w = ctl->atol / ctl->rtol;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (c >= d) break;
+      double acc = 0.0;
+#pragma unroll
+      for (int l = 0; l < 7; ++l) acc += (kDpB[l] - kDpBt[l]) * K[l][c];
+      const double W = fmax(fmax(fabs(x[c]), fabs(y[c])), floor_w);
+      *r0 = nanmax(*r0, fabs(ha * acc) / W);
+      *r1 = nanmax(*r1, fabs(K[0][c]) / fmax(fabs(x[c]), floor_w));
+    }
   }
-  const double floor_w = ctl->atol / ctl->rtol;
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    if (c >= d) break;
-    double acc = 0.0;
-#pragma unroll
-    for (int l = 0; l < 7; ++l) acc += (kDpB[l] - kDpBt[l]) * K[l][c];
-    const double W = fmax(fmax(fabs(x[c]), fabs(y[c])), floor_w);
-    *r0 = nanmax(*r0, fabs(ha * acc) / W);
-    *r1 = nanmax(*r1, fabs(K[0][c]) / fmax(fabs(x[c]), floor_w));
+}
+
+template <int VF>
+__device__ __forceinline__ void epilogue_dp(const Args& a, const Ctl* ctl, long long i, const double* P, double* r0, double* r1) {
+  switch (a.stage) {
+    case ST_D2: epilogue_dp_s<VF, 2>(a, ctl, i, P, r0, r1); break;
+    case ST_D3: epilogue_dp_s<VF, 3>(a, ctl, i, P, r0, r1); break;
+    case ST_D4: epilogue_dp_s<VF, 4>(a, ctl, i, P, r0, r1); break;
+    case ST_D5: epilogue_dp_s<VF, 5>(a, ctl, i, P, r0, r1); break;
+    case ST_D6: epilogue_dp_s<VF, 6>(a, ctl, i, P, r0, r1); break;
+    default: epilogue_dp_s<VF, 7>(a, ctl, i, P, r0, r1); break;
   }
 }
 
@@ -531,17 +560,23 @@ __device__ __forceinline__ long long tail_row(const Args& a, int rb, int RB) {
   return threadIdx.x < RB ? (long long)rb * RB + threadIdx.x : -1;
 }
 
-// common tail of every contraction kernel: row epilogues and the block maxima
-template <int M, int VF>
-__device__ void contract_tail(const Args& a, int rb, double (*sP)[M], int RB, const RowIn& rin) {
+// common tail of every contraction kernel: row epilogues and the block maxima (DP: the
+// kernel also serves Dormand-Prince attempts; the grouped ensemble kernels do not, and
+// leave that code out)
+template <int M, int VF, bool DP = true>
+__device__ __forceinline__ void contract_tail(const Args& a, int rb, double (*sP)[M], int RB, const RowIn& rin) {
   __shared__ double sRed0[16], sRed1[16];
   const Ctl* ctl = a.ctl;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const long long i = tail_row(a, rb, RB);
   double r0 = 0.0, r1 = 0.0;
   if (i >= 0 && i < a.n) {
-    if (a.stage >= ST_D2) epilogue_dp<VF>(a, ctl, i, sP[tid], &r0, &r1);
-    else epilogue<VF>(a, ctl, i, sP[tid], rin, &r0, &r1);
+    if constexpr (DP) {
+      if (a.stage >= ST_D2) epilogue_dp<VF>(a, ctl, i, sP[tid], &r0, &r1);
+      else epilogue<VF>(a, ctl, i, sP[tid], rin, &r0, &r1);
+    } else {  // the grouped ensemble kernels
+      epilogue<VF, true>(a, ctl, i, sP[tid], rin, &r0, &r1);
+    }
   }
   if (a.stage == ST_S2 || a.stage == ST_S3 || a.stage == ST_RHS || (a.stage >= ST_D2 && a.stage < ST_D7)) return;
   r0 = wave_nanmax(r0);
@@ -574,7 +609,7 @@ __device__ __forceinline__ void prefetch_row(const Args& a, int rb, int RB, RowI
 // [wk KW, (wk+1) KW); lanes stride the row with 16-byte loads (2 doubles) and keep
 // U chunks of 128 columns in flight.  The WK slice sums are added in slice order.
 // ---------------------------------------------------------------------------
-template <int M, int R, int WR, int WK, int U, bool NT>
+template <int M, int R, int WR, int WK, int U, bool NT, bool DP = true>
 __device__ __forceinline__ void contract_f64(const Args& a, int rb) {
   constexpr int RB = R * WR;
   __shared__ double sPart[WK][RB][M];
@@ -586,7 +621,7 @@ __device__ __forceinline__ void contract_f64(const Args& a, int rb) {
   const int wr = w % WR, wk = w / WR;
   const long long row0 = (long long)rb * RB + wr * R;
   const double* __restrict__ Ab = (const double*)a.A + row0 * a.ld;
-  const double* __restrict__ V = a.V64[vin_of(a.stage)];
+  const double* __restrict__ V = pick2(a.V64, vin_of(a.stage));
   const long long jb = (long long)wk * a.KW;
   const long long je = min(jb + (long long)a.KW, a.ld);
   double acc[R][M];
@@ -654,7 +689,7 @@ __device__ __forceinline__ void contract_f64(const Args& a, int rb) {
     sP[e / M][e % M] = s;
   }
   __syncthreads();
-  contract_tail<M, F_F64>(a, rb, sP, RB, rin);
+  contract_tail<M, F_F64, DP>(a, rb, sP, RB, rin);
 }
 
 // ---------------------------------------------------------------------------
@@ -662,7 +697,7 @@ __device__ __forceinline__ void contract_f64(const Args& a, int rb) {
 // T FP32 terms; each lane forms 4-element FP32 dot products per term and adds
 // them to FP64 accumulators (FP32 within a chunk, FP64 across chunks).
 // ---------------------------------------------------------------------------
-template <int M, int T, int R, int WR, int WK, int U, bool NT>
+template <int M, int T, int R, int WR, int WK, int U, bool NT, bool DP = true>
 __device__ __forceinline__ void contract_f32(const Args& a, int rb) {
   constexpr int RB = R * WR;
   constexpr int NC = M * T;
@@ -675,7 +710,7 @@ __device__ __forceinline__ void contract_f32(const Args& a, int rb) {
   const int wr = w % WR, wk = w / WR;
   const long long row0 = (long long)rb * RB + wr * R;
   const float* __restrict__ Ab = (const float*)a.A + row0 * a.ld;
-  const float* __restrict__ Vq = (const float*)a.Vq[vin_of(a.stage)];
+  const float* __restrict__ Vq = (const float*)pick2(a.Vq, vin_of(a.stage));
   const long long jb = (long long)wk * a.KW;
   const long long je = min(jb + (long long)a.KW, a.ld);
   double acc[R][NC];
@@ -745,7 +780,7 @@ __device__ __forceinline__ void contract_f32(const Args& a, int rb) {
     sP[row][cc] = a.scale * p;
   }
   __syncthreads();
-  contract_tail<M, F_F32>(a, rb, sP, RB, rin);
+  contract_tail<M, F_F32, DP>(a, rb, sP, RB, rin);
 }
 
 // ---------------------------------------------------------------------------
@@ -785,7 +820,7 @@ __device__ __forceinline__ f32x4 mma(u32x4 av, u32x4 bv, f32x4 c) {
   }
 }
 
-template <int FMT, int M, int T, int RT, int WR, int WK, int U, bool NT>
+template <int FMT, int M, int T, int RT, int WR, int WK, int U, bool NT, bool DP = true>
 __device__ __forceinline__ void contract_mfma(const Args& a, int rb) {
   constexpr int NC = M * T;
   static_assert(NC <= 16, "vector terms exceed the MFMA tile width");
@@ -809,7 +844,7 @@ __device__ __forceinline__ void contract_mfma(const Args& a, int rb) {
 #pragma unroll
   for (int t = 0; t < RT; ++t) ap[t] = Ab + ((row_base + 16 * t + r16) * a.ld + kb) * ES + g * 16;
   const bool bcol = r16 < NC;
-  const char* bp = (const char*)a.Vq[vin_of(a.stage)] + ((long long)(bcol ? r16 : 0) * a.ld + kb) * ES + g * 16;
+  const char* bp = (const char*)pick2(a.Vq, vin_of(a.stage)) + ((long long)(bcol ? r16 : 0) * a.ld + kb) * ES + g * 16;
   f32x4 c[RT];
   double dacc[RT][4];
 #pragma unroll
@@ -896,7 +931,7 @@ __device__ __forceinline__ void contract_mfma(const Args& a, int rb) {
     sP[row][cc] = a.scale * p;
   }
   __syncthreads();
-  contract_tail<M, FMT>(a, rb, sP, RB, rin);
+  contract_tail<M, FMT, DP>(a, rb, sP, RB, rin);
 }
 
 // ---------------------------------------------------------------------------
@@ -929,7 +964,7 @@ __device__ __forceinline__ void contract_pair(const Args& a, int rb) {
   prefetch_row(a, rb, RB, rin);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const long long row0 = (long long)rb * RB + (long long)w * R;
-  const double* __restrict__ V = a.V64[vin_of(a.stage)];
+  const double* __restrict__ V = pick2(a.V64, vin_of(a.stage));
   double xi[R], accd[R];
   float accf[R];
 #pragma unroll
@@ -979,8 +1014,8 @@ __device__ __forceinline__ void prep_block(const Args& a, int blk) {
   if (ctl->status != kRunning) return;
   const long long i = (long long)blk * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  const double* X = a.X[ctl->xi];
-  const double* K1 = a.Kf[ctl->ki];
+  const double* X = pick2(a.X, ctl->xi);
+  const double* K1 = pick2(a.Kf, ctl->ki);
   double y = X[i];
   if (a.stage == ST_H0) y = X[i] + ctl->h0probe * K1[i];
   else if (a.stage == ST_S2) y = sstore(a, X[i] + ctl->ha * (kA21 * K1[i]));
@@ -1009,7 +1044,7 @@ __global__ __launch_bounds__(WR* WK * 64) void k_contract_f64(Args a) {
 }
 template <int M, int R, int WR, int WK, int U, bool NT>
 __global__ __launch_bounds__(WR* WK * 64) void k_group_f64(Group g) {
-  BS32_GROUP_LOOP((contract_f64<M, R, WR, WK, U, NT>))
+  BS32_GROUP_LOOP((contract_f64<M, R, WR, WK, U, NT, false>))
 }
 template <int M, int T, int R, int WR, int WK, int U, bool NT>
 __global__ __launch_bounds__(WR* WK * 64) void k_contract_f32(Args a) {
@@ -1017,7 +1052,7 @@ __global__ __launch_bounds__(WR* WK * 64) void k_contract_f32(Args a) {
 }
 template <int M, int T, int R, int WR, int WK, int U, bool NT>
 __global__ __launch_bounds__(WR* WK * 64) void k_group_f32(Group g) {
-  BS32_GROUP_LOOP((contract_f32<M, T, R, WR, WK, U, NT>))
+  BS32_GROUP_LOOP((contract_f32<M, T, R, WR, WK, U, NT, false>))
 }
 template <int FMT, int M, int T, int RT, int WR, int WK, int U, bool NT>
 __global__ __launch_bounds__(WR* WK * 64) void k_contract_mfma(Args a) {
@@ -1025,7 +1060,7 @@ __global__ __launch_bounds__(WR* WK * 64) void k_contract_mfma(Args a) {
 }
 template <int FMT, int M, int T, int RT, int WR, int WK, int U, bool NT>
 __global__ __launch_bounds__(WR* WK * 64) void k_group_mfma(Group g) {
-  BS32_GROUP_LOOP((contract_mfma<FMT, M, T, RT, WR, WK, U, NT>))
+  BS32_GROUP_LOOP((contract_mfma<FMT, M, T, RT, WR, WK, U, NT, false>))
 }
 template <bool ATAN, bool G32, bool DENSE, int R, int WV, int UJ>
 __global__ __launch_bounds__(WV * 64) void k_contract_pair(Args a) {
@@ -1052,6 +1087,12 @@ __global__ __launch_bounds__(256) void k_group_prep(Group g) { BS32_GROUP_LOOP(p
 // ---------------------------------------------------------------------------
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
+// operand format of a storage format (the BF16 pair multiplies BF16 operand terms)
+template <int FMT>
+constexpr int sh_opfmt() {
+  return FMT == F_BF16X2 ? F_BF16 : FMT;
+}
+
 template <int FMT>
 struct ShAcc {
   using T = f32x4;
@@ -1069,31 +1110,40 @@ __device__ __forceinline__ typename ShAcc<FMT>::T sh_mma(u32x4 av, u32x4 bv, typ
     c = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[0], fb[0], c, 0, 0, 0);
     return __builtin_amdgcn_mfma_f64_16x16x4f64(fa[1], fb[1], c, 0, 0, 0);
   } else {
-    return mma<FMT>(av, bv, c);
+    return mma<sh_opfmt<FMT>()>(av, bv, c);
   }
 }
 
 constexpr int kShChunk = 256;          // bytes of k per operand column and chunk
 constexpr int kShPitch = kShChunk + 16;  // LDS pitch of one operand column (spreads the banks)
 
+// 16-bit storage accumulates in FP32 across the whole k range (its products carry
+// 8- or 11-bit weights, far coarser than an FP32 sum of N terms) and keeps the P tile
+// in FP32; FP32 storage adds each chunk's FP32 partial sums in FP64
+template <int FMT>
+constexpr bool sh_f32acc() {
+  return FMT == F_BF16 || FMT == F_F16;
+}
+
 template <int FMT, int RT, int CT>
 constexpr int sh_lds_bytes() {
   constexpr int BM = 64 * RT, BN = 16 * CT;
-  constexpr int tiles = 2 * BN * kShPitch, part = BM * (BN + 1) * 8;
+  constexpr int tiles = 2 * BN * kShPitch, part = BM * (BN + 1) * (sh_f32acc<FMT>() ? 4 : 8);
   return tiles > part ? tiles : part;
 }
 
 int shared_cols(int fmt, int m) {
   if (fmt == F_F64) return m;
-  if (fmt == F_F32 || fmt == F_BF16 || fmt == F_F16) return 2 * m;  // two split terms
+  if (fmt == F_F32 || fmt == F_BF16 || fmt == F_F16 || fmt == F_BF16X2) return 2 * m;  // two split terms
   return 0;  // e4m3's three terms do not tile the product's columns
 }
 
 template <int FMT, int M, int RT, int CT>
 __global__ __launch_bounds__(256) void k_shared_contract(Shared sh) {
-  constexpr int ES = FMT == F_F64 ? 8 : FMT == F_F32 ? 4 : 2;
+  constexpr int ES = FMT == F_F64 ? 8 : FMT == F_F32 ? 4 : 2;  // bytes per element of A (per plane) and operand
   constexpr int T = FMT == F_F64 ? 1 : 2;
   constexpr int C = M * T;
+  constexpr int PL = FMT == F_BF16X2 ? 2 : 1;  // planes of A: the BF16 pair adds its remainder plane
   constexpr int BM = 64 * RT, BN = 16 * CT, IB = BN / C;
   constexpr int NSTEP = kShChunk / 64;  // 64-byte lane-group steps per chunk
   constexpr int UNITS = BN * kShChunk / 16 / 256;  // 16-byte operand loads per thread and chunk
@@ -1162,30 +1212,39 @@ __global__ __launch_bounds__(256) void k_shared_contract(Shared sh) {
       }
     }
   };
-  auto load_a = [&](u32x4 (&av)[NSTEP][RT], long long ch) {
+  const long long plane_bytes = sh.np * ld * ES;
+  auto load_a = [&](u32x4 (&av)[NSTEP][RT * PL], long long ch) {
 #pragma unroll
     for (int s = 0; s < NSTEP; ++s)
 #pragma unroll
-      for (int t = 0; t < RT; ++t) av[s][t] = *(const u32x4*)(ap[t] + ch * kShChunk + s * 64);
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int q = 0; q < PL; ++q) av[s][t * PL + q] = *(const u32x4*)(ap[t] + q * plane_bytes + ch * kShChunk + s * 64);
   };
 
+  constexpr bool F32ACC = sh_f32acc<FMT>();
+  constexpr bool FLUSH = !F32ACC && FMT != F_F64;
   Acc c[RT][CT];
-  double dacc[RT][CT][4];
+  double dacc[FLUSH ? RT : 1][FLUSH ? CT : 1][4];
 #pragma unroll
   for (int t = 0; t < RT; ++t)
 #pragma unroll
-    for (int u = 0; u < CT; ++u) {
-      c[t][u] = Acc{0, 0, 0, 0};
-      for (int i = 0; i < 4; ++i) dacc[t][u][i] = 0.0;
-    }
+    for (int u = 0; u < CT; ++u) c[t][u] = Acc{0, 0, 0, 0};
+  if constexpr (FLUSH) {
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int u = 0; u < CT; ++u)
+        for (int i = 0; i < 4; ++i) dacc[t][u][i] = 0.0;
+  }
 
   u32x4 bu[UNITS];
-  u32x4 a0[NSTEP][RT], a1[NSTEP][RT];
+  u32x4 a0[NSTEP][RT * PL], a1[NSTEP][RT * PL];
   load_units(bu, 0);
   load_a(a0, 0);
   store_units(bu, 0);
   __syncthreads();
-  auto compute = [&](const u32x4 (&av)[NSTEP][RT], int buf) {
+  auto compute = [&](const u32x4 (&av)[NSTEP][RT * PL], int buf) {
     const char* base = smem + buf * BN * kShPitch;
 #pragma unroll
     for (int s = 0; s < NSTEP; ++s) {
@@ -1193,10 +1252,12 @@ __global__ __launch_bounds__(256) void k_shared_contract(Shared sh) {
       for (int u = 0; u < CT; ++u) {
         const u32x4 bv = *(const u32x4*)(base + (16 * u + r16) * kShPitch + s * 64 + g * 16);
 #pragma unroll
-        for (int t = 0; t < RT; ++t) c[t][u] = sh_mma<FMT>(av[s][t], bv, c[t][u]);
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int q = 0; q < PL; ++q) c[t][u] = sh_mma<FMT>(av[s][t * PL + q], bv, c[t][u]);  // (hi + lo) b
       }
     }
-    if constexpr (FMT != F_F64) {  // FP64 across chunks
+    if constexpr (FLUSH) {  // FP64 across chunks
 #pragma unroll
       for (int t = 0; t < RT; ++t)
 #pragma unroll
@@ -1229,9 +1290,11 @@ __global__ __launch_bounds__(256) void k_shared_contract(Shared sh) {
   }
   __syncthreads();  // every wave is done with the operand tiles: the LDS now takes P
 
-  // P tile [BM][BN] in FP64.  Lane (r16, g) holds column r16 of each 16x16 tile: rows
-  // 4g + i for the FP32-output instructions, rows g + 4i for the FP64 one (measured)
-  double* sP = (double*)smem;
+  // P tile [BM][BN] (FP32 for 16-bit storage, else FP64).  Lane (r16, g) holds column
+  // r16 of each 16x16 tile: rows 4g + i for the FP32-output instructions, rows g + 4i
+  // for the FP64 one (measured)
+  using PT = typename std::conditional<F32ACC, float, double>::type;
+  PT* sP = (PT*)smem;
   constexpr int PP = BN + 1;
 #pragma unroll
   for (int t = 0; t < RT; ++t)
@@ -1240,7 +1303,8 @@ __global__ __launch_bounds__(256) void k_shared_contract(Shared sh) {
       for (int i = 0; i < 4; ++i) {
         const int rr = (FMT == F_F64) ? g + 4 * i : 4 * g + i;
         const int row = w * 16 * RT + 16 * t + rr, col = 16 * u + r16;
-        sP[row * PP + col] = (FMT == F_F64) ? (double)c[t][u][i] : dacc[t][u][i];
+        if constexpr (FLUSH) sP[row * PP + col] = dacc[t][u][i];
+        else sP[row * PP + col] = (PT)c[t][u][i];
       }
   __syncthreads();
 
@@ -1263,10 +1327,10 @@ __global__ __launch_bounds__(256) void k_shared_contract(Shared sh) {
         for (int mm = 0; mm < M; ++mm) {
           double p = 0.0;
 #pragma unroll
-          for (int tt = 0; tt < T; ++tt) p += ldexp(sP[row * PP + ib * C + mm * T + tt], -tt * sh.vshift);
+          for (int tt = 0; tt < T; ++tt) p += ldexp((double)sP[row * PP + ib * C + mm * T + tt], -tt * sh.vshift);
           P[mm] = sh.scale * p;
         }
-        epilogue<FMT>(a, ctl, i, P, rin, &r0, &r1);
+        epilogue<sh_opfmt<FMT>(), true>(a, ctl, i, P, rin, &r0, &r1);
       }
     }
     if (!reduce) continue;
@@ -1538,7 +1602,7 @@ __device__ __forceinline__ void finalize_block(const Args& a, int blk) {
   if (a.rec && i < a.n && (a.stage == ST_INIT || ((a.stage == ST_S4 || a.stage == ST_D7) && sc.n_accept != na0))) {
     const long long slot = (a.stage == ST_INIT) ? 0 : sc.n_accept;
     if (slot < a.rec_cap) {
-      const double* Xc = a.X[sc.xi];
+      const double* Xc = pick2(a.X, sc.xi);
       double* dst = a.rec + (slot * a.n + i) * a.d;
       for (int c = 0; c < a.d; ++c) dst[c] = Xc[c * a.np + i];
     }
@@ -1606,13 +1670,20 @@ __global__ void k_pack_fmt(const double* __restrict__ A, void* __restrict__ dst,
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count;
        e += (long long)gridDim.x * blockDim.x) {
     const double x = A[e] * inv_scale;  // power-of-two scale: exact
-    if (fmt == F_F32) ((float*)dst)[e] = (float)x;
+    if (fmt == F_BF16X2) {  // hi plane, then the remainder's plane
+      const uint32_t hi = encode_rne(x, fmt_desc(F_BF16));
+      ((uint16_t*)dst)[e] = (uint16_t)hi;
+      ((uint16_t*)dst)[count + e] = (uint16_t)encode_rne(x - decode_bits(hi, fmt_desc(F_BF16)), fmt_desc(F_BF16));
+    } else if (fmt == F_F32) ((float*)dst)[e] = (float)x;
     else if (fmt == F_E4M3) ((uint8_t*)dst)[e] = (uint8_t)encode_rne(x, fmt_desc(fmt));
     else ((uint16_t*)dst)[e] = (uint16_t)encode_rne(x, fmt_desc(fmt));
   }
 }
-__device__ __forceinline__ double stored_value(const void* A, int fmt, long long e) {
+__device__ __forceinline__ double stored_value(const void* A, int fmt, long long e, long long plane) {
   switch (fmt) {
+    case F_BF16X2:
+      return decode_bits(((const uint16_t*)A)[e], fmt_desc(F_BF16)) +
+             decode_bits(((const uint16_t*)A)[plane + e], fmt_desc(F_BF16));
     case F_F64: return ((const double*)A)[e];
     case F_F32: return (double)((const float*)A)[e];
     case F_E4M3: return decode_bits(((const uint8_t*)A)[e], fmt_desc(fmt));
@@ -1621,11 +1692,11 @@ __device__ __forceinline__ double stored_value(const void* A, int fmt, long long
 }
 // row sums of the stored matrix in FP64 (fixed order; one workgroup per row)
 __global__ void k_rowsum(const void* __restrict__ A, int fmt, double scale, double* __restrict__ rsum, long long n,
-                         long long ld) {
+                         long long ld, long long plane) {
   __shared__ double red[4];
   const long long r = blockIdx.x;
   double s = 0.0;
-  for (long long j = threadIdx.x; j < n; j += blockDim.x) s += scale * stored_value(A, fmt, r * ld + j);
+  for (long long j = threadIdx.x; j < n; j += blockDim.x) s += scale * stored_value(A, fmt, r * ld + j, plane);
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
@@ -1673,7 +1744,8 @@ hipError_t launch_pack_fmt(const double* A64, void* dst, int fmt, double inv_sca
 }
 hipError_t launch_rowsum(const void* A, int fmt, double scale, double* rsum, long long n, long long ld,
                          hipStream_t s) {
-  k_rowsum<<<(unsigned)n, 256, 0, s>>>(A, fmt, scale, rsum, n, ld);
+  const long long plane = (n + 255) / 256 * 256 * ld;  // np x ld values per plane (BF16 pairs)
+  k_rowsum<<<(unsigned)n, 256, 0, s>>>(A, fmt, scale, rsum, n, ld, plane);
   return hipGetLastError();
 }
 hipError_t launch_prep(const Args& a, hipStream_t s) {
@@ -1716,8 +1788,9 @@ int tile_kalign(int fmt, const Tile& t) {
 // pairwise kernels: (R rows per wave, WV waves, UJ column chunks per step)
 #define BS32_PAIR_TILES(X) X(2, 4, 1) X(4, 4, 1) X(8, 4, 1) X(4, 4, 2)
 
-// shared-coupling products: (RT 16-row tiles per wave, CT 16-column tiles), four waves
-#define BS32_SHARED_TILES(X) X(2, 4) X(1, 8) X(1, 4) X(2, 2)
+// shared-coupling products: (RT 16-row tiles per wave, CT 16-column tiles), four waves;
+// RT = 4 only for 16-bit storage (its FP32 P tile fits the LDS)
+#define BS32_SHARED_TILES(X) X(2, 4) X(1, 8) X(1, 4) X(2, 2) X(4, 4) X(4, 2)
 
 #define BS32_TILE_VALU(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 0},
 #define BS32_TILE_MMA(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 1},
@@ -1762,9 +1835,13 @@ static hipError_t launch_shared_t(const Shared* sh, const Tile& t, hipStream_t s
   const unsigned grid = 8u * (unsigned)((total + 7) / 8);
 #define X(RT_, CT_)                                                                       \
   if (t.R == RT_ && t.U == CT_) {                                                         \
-    if (!sh) return hipSuccess;                                                           \
-    if (total > 0) k_shared_contract<FMT, M, RT_, CT_><<<grid, 256, 0, s>>>(*sh);        \
-    return hipGetLastError();                                                             \
+    if constexpr (RT_ == 4 && !sh_f32acc<FMT>()) {                                        \
+      return hipErrorInvalidValue;                                                        \
+    } else {                                                                              \
+      if (!sh) return hipSuccess;                                                         \
+      if (total > 0) k_shared_contract<FMT, M, RT_, CT_><<<grid, 256, 0, s>>>(*sh);      \
+      return hipGetLastError();                                                           \
+    }                                                                                     \
   }
   BS32_SHARED_TILES(X)
 #undef X
@@ -1779,6 +1856,8 @@ static hipError_t dispatch_shared(const Shared* sh, int m, int fmt, const Tile& 
     case F_F32: return m == 2 ? launch_shared_t<F_F32, 2>(sh, t, s) : launch_shared_t<F_F32, 1>(sh, t, s);
     case F_BF16: return m == 2 ? launch_shared_t<F_BF16, 2>(sh, t, s) : launch_shared_t<F_BF16, 1>(sh, t, s);
     case F_F16: return m == 2 ? launch_shared_t<F_F16, 2>(sh, t, s) : launch_shared_t<F_F16, 1>(sh, t, s);
+    case F_BF16X2:
+      return m == 2 ? launch_shared_t<F_BF16X2, 2>(sh, t, s) : launch_shared_t<F_BF16X2, 1>(sh, t, s);
     default: return hipErrorInvalidValue;
   }
 }

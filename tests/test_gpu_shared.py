@@ -93,8 +93,8 @@ def test_shared_fp64_matches_oracle(bs, orc, kind, n, B):
     _check_against_oracle(b, s, orc, kind, base, params, gains, y0, t1, 1e-7, 0, 1e-10, (1, 0.01))
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2, 3])
-@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 8])
 def test_shared_every_tile(bs, orc, tile, mode):
     """Every instantiated product tile in every storage format, on a ragged N and a
     batch that does not fill the last column block."""
@@ -106,6 +106,10 @@ def test_shared_every_tile(bs, orc, tile, mode):
     s.set_options(tile=tile)
     try:
         s.set_shared_ensemble(base["kind"], 333, 37, A=base["A"], params=params, gains=gains)
+        if tile >= 4 and mode not in (2, 3):   # the 256-row tiles serve BF16 and FP16 only
+            with pytest.raises(b.BS32Error):
+                s.kernel_name(mode, tile)
+            return
         assert s.kernel_name(mode, tile).startswith("k_shared_contract<")
         y, st, _ = s.solve_batch(y0.reshape(-1), 0.0, t1, 1e-6, mode=mode)
         assert np.all(st == 0)
@@ -119,7 +123,7 @@ def test_shared_every_tile(bs, orc, tile, mode):
         s.set_options(tile=-1)
 
 
-@pytest.mark.parametrize("mode", [1, 2, 3])
+@pytest.mark.parametrize("mode", [1, 2, 3, 8])
 def test_shared_reduced_tracks_oracle(bs, orc, mode):
     b, s = bs
     base, params, gains, y0 = _sweep("kuramoto", 520, 6, 91)
@@ -157,3 +161,30 @@ def test_shared_rejections(bs):
     s.set_shared_ensemble(base["kind"], 64, 3, A=base["A"], params=params, gains=gains)
     y, st, _ = s.solve_batch(y0.reshape(-1), 0.0, 1.0, 1e-6)
     assert np.all(st == 0)
+
+
+def test_bf16_pair_planes_bit_exact(bs, orc):
+    """The BF16-pair planes of the stored coupling equal the oracle's quantizer bit for
+    bit: hi = RNE_bf16(A/s), lo = RNE_bf16(A/s - hi), s the power-of-two scale."""
+    b, s = bs
+    w = workloads.kuramoto(300, seed=97)
+    s.set_workload(w)
+    planes, sc = s.packed_coupling(b.PREC_RHS_BF16X2)
+    assert sc == orc.matrix_scale(w["A"], orc.FMT_BF16X2)
+    x = w["A"] / sc
+    hi = orc.encode_fmt(x, orc.FMT_BF16).astype(np.uint16)
+    lo = orc.encode_fmt(x - orc.decode_fmt(hi, orc.FMT_BF16), orc.FMT_BF16).astype(np.uint16)
+    np.testing.assert_array_equal(planes[0], hi)
+    np.testing.assert_array_equal(planes[1], lo)
+
+
+def test_bf16_pair_only_for_shared_products(bs):
+    b, s = bs
+    w = workloads.kuramoto(64, seed=98, t1=1.0)
+    s.set_workload(w)
+    with pytest.raises(b.BS32Error):
+        s.solve(w["y0"], 0.0, 1.0, 1e-6, mode=b.PREC_RHS_BF16X2)
+    s.set_ensemble([w, workloads.kuramoto(32, seed=99, t1=1.0)])
+    with pytest.raises(b.BS32Error):
+        s.solve_batch(np.concatenate([w["y0"], workloads.kuramoto(32, seed=99)["y0"]]), 0.0, 1.0, 1e-6,
+                      mode=b.PREC_RHS_BF16X2)
