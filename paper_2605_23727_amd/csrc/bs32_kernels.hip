@@ -791,6 +791,15 @@ __device__ __forceinline__ void contract_f32(const Args& a, int rb) {
 // with the same k-permutation on both operands).  FP32 accumulation inside the
 // matrix core for KC k-groups, then FP64 accumulation; waves split k and their
 // sums are added in slice order.
+// Staging: the operand layout above reads 64 bytes of each of 16 rows per load
+// instruction, half a cache line per row, which streams HBM markedly slower than
+// whole lines.  A batch of U 64-byte steps is therefore loaded as 16/U rows x U*64
+// contiguous bytes per instruction, written to the wave's own slab of LDS and read
+// back in the operand layout: the same elements meet the same products in the same
+// order, only the path from HBM changes.  The slab is private to the wave, and LDS
+// operations of one wave complete in order, so no barrier is needed.  The grouped
+// ensemble kernels of eight-wave tiles with 8-step batches or two row tiles keep
+// the direct path: their per-item loop leaves no registers for the staging.
 // ---------------------------------------------------------------------------
 template <int FMT>
 __device__ __forceinline__ f32x4 mma(u32x4 av, u32x4 bv, f32x4 c) {
@@ -828,11 +837,15 @@ __device__ __forceinline__ void contract_mfma(const Args& a, int rb) {
   constexpr int ES = (FMT == F_E4M3) ? 1 : (FMT == F_F32) ? 4 : 2;  // bytes per element
   constexpr int KB = 64 / ES;  // k elements per 16-byte lane load x 4 lane groups
   constexpr int KC = 8;                        // k-groups kept in FP32 before an FP64 flush
+  static_assert(U == 2 || U == 4 || U == 8, "staged batches of 2, 4 or 8 steps");
+  constexpr int RPI = 16 / U;                  // rows per staged load instruction
+  constexpr int LPR = 64 / RPI;                // lanes per row: U*64 contiguous bytes
+  constexpr int SROW = U * 64 + 16;            // slab row stride (padded against bank conflicts)
+  constexpr int NQ = RT * U;                   // load instructions per batch
+  constexpr bool STAGE = DP || !(WR * WK >= 8 && (U == 8 || RT == 2));
   __shared__ double sPart[WK][RB][NC];
   __shared__ double sP[RB][M];
-  if (a.ctl->status != kRunning) return;
-  RowIn rin;
-  prefetch_row(a, rb, RB, rin);
+  __shared__ __attribute__((aligned(16))) unsigned char sA[STAGE ? WR * WK : 1][STAGE ? RT * 16 * SROW : 16];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w % WR, wk = w / WR;
   const int r16 = lane & 15, g = lane >> 4;
@@ -840,11 +853,13 @@ __device__ __forceinline__ void contract_mfma(const Args& a, int rb) {
   const long long kb = (long long)wk * a.KW;
   const long long ke = min(kb + (long long)a.KW, a.ld);
   const char* Ab = (const char*)a.A;
-  const char* ap[RT];
-#pragma unroll
-  for (int t = 0; t < RT; ++t) ap[t] = Ab + ((row_base + 16 * t + r16) * a.ld + kb) * ES + g * 16;
   const bool bcol = r16 < NC;
   const char* bp = (const char*)pick2(a.Vq, vin_of(a.stage)) + ((long long)(bcol ? r16 : 0) * a.ld + kb) * ES + g * 16;
+  // staged path: instruction q reads rows q*RPI + srow of the wave's 16*RT, bytes scol..scol+15
+  unsigned char* const slab = sA[w];
+  const int srow = lane / LPR, scol = (lane % LPR) * 16;
+  const char* const sp = Ab + ((row_base + srow) * a.ld + kb) * ES + scol;
+  const long long qstride = (long long)RPI * a.ld * ES;
   f32x4 c[RT];
   double dacc[RT][4];
 #pragma unroll
@@ -861,20 +876,39 @@ __device__ __forceinline__ void contract_mfma(const Args& a, int rb) {
   // buffers, ping-pong).  Same products, same order as a plain loop.
   constexpr long long BATCH = 64LL * U;
   const long long full = span / BATCH * BATCH;
-  u32x4 a0[U][RT], b0[U], a1[U][RT], b1[U];
-  auto load = [&](u32x4 (&xa)[U][RT], u32x4 (&xb)[U], long long o) {
+  u32x4 a0[NQ], b0[U], a1[NQ], b1[U];
+  auto load = [&](u32x4 (&xa)[NQ], u32x4 (&xb)[U], long long o) {
+    if constexpr (STAGE) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
+      for (int q = 0; q < NQ; ++q) xa[q] = ldA<NT>((const u32x4*)(sp + q * qstride + o));
+    } else {  // operand layout straight from HBM: element u*RT + t is step u of row tile t
 #pragma unroll
-      for (int t = 0; t < RT; ++t) xa[u][t] = ldA<NT>((const u32x4*)(ap[t] + o + 64 * u));
-      xb[u] = bcol ? *(const u32x4*)(bp + o + 64 * u) : zero;
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+          xa[u * RT + t] =
+              ldA<NT>((const u32x4*)(Ab + ((row_base + 16 * t + r16) * a.ld + kb) * ES + g * 16 + o + 64 * u));
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u) xb[u] = bcol ? *(const u32x4*)(bp + o + 64 * u) : zero;
   };
-  auto step = [&](const u32x4 (&xa)[U][RT], const u32x4 (&xb)[U]) {
+  auto step = [&](const u32x4 (&xa)[NQ], const u32x4 (&xb)[U]) {
+    if constexpr (STAGE) {
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+      for (int q = 0; q < NQ; ++q) *(u32x4*)(slab + (q * RPI + srow) * SROW + scol) = xa[q];
 #pragma unroll
-      for (int t = 0; t < RT; ++t) c[t] = mma<FMT>(xa[u][t], xb[u], c[t]);
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          const u32x4 av = *(const u32x4*)(slab + (16 * t + r16) * SROW + 64 * u + 16 * g);
+          c[t] = mma<FMT>(av, xb[u], c[t]);
+        }
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int t = 0; t < RT; ++t) c[t] = mma<FMT>(xa[u * RT + t], xb[u], c[t]);
+    }
     kc += U;
     if (kc >= KC && !a.sum32) {  // FP64 flush (the recipes' single sum keeps FP32 throughout)
 #pragma unroll
@@ -886,6 +920,10 @@ __device__ __forceinline__ void contract_mfma(const Args& a, int rb) {
     }
   };
   if (full > 0) load(a0, b0, 0);
+  // the first batch is in flight while the control state arrives
+  if (a.ctl->status != kRunning) return;
+  RowIn rin;
+  prefetch_row(a, rb, RB, rin);
   while (off < full) {
     if (off + BATCH < full) load(a1, b1, off + BATCH);
     step(a0, b0);
@@ -895,10 +933,12 @@ __device__ __forceinline__ void contract_mfma(const Args& a, int rb) {
     step(a1, b1);
     off += BATCH;
   }
+  // steps left over after the last whole batch: operand layout straight from HBM
   for (; off < span; off += 64) {
     u32x4 av[RT];
 #pragma unroll
-    for (int t = 0; t < RT; ++t) av[t] = ldA<NT>((const u32x4*)(ap[t] + off));
+    for (int t = 0; t < RT; ++t)
+      av[t] = ldA<NT>((const u32x4*)(Ab + ((row_base + 16 * t + r16) * a.ld + kb) * ES + g * 16 + off));
     const u32x4 bv = bcol ? *(const u32x4*)(bp + off) : zero;
 #pragma unroll
     for (int t = 0; t < RT; ++t) c[t] = mma<FMT>(av[t], bv, c[t]);
@@ -1364,7 +1404,7 @@ __global__ __launch_bounds__(256) void k_shared_contract(Shared sh) {
 
 // elementary controller (reading of the unspecified step-size correction; the
 // estimate is O(h^3), so the exponent is 1/3)
-__device__ double control(const Ctl* c, double h, double E, bool accepted) {
+__device__ __forceinline__ double control(const Ctl* c, double h, double E, bool accepted) {
   const double fac = (E > 0.0) ? c->safety * cbrt(c->rtol / E) : c->facmax;
   if (accepted) {
     const double hi = c->last_rejected ? 1.0 : c->facmax;
@@ -1377,7 +1417,7 @@ __device__ double control(const Ctl* c, double h, double E, bool accepted) {
 
 // grid maxima of the evaluation that just finished -> new control state
 // returns true when the learned proposer should choose the next step (features in feat)
-__device__ bool finalize(const Args& a, Ctl* c, double m0, double m1, bool writer, float* feat) {
+__device__ __forceinline__ bool finalize(const Args& a, Ctl* c, double m0, double m1, bool writer, float* feat) {
   switch (a.stage) {
     case ST_INIT: {
       c->n_fev += 1;
@@ -1508,7 +1548,7 @@ __device__ bool finalize(const Args& a, Ctl* c, double m0, double m1, bool write
 
 // second half of the step-size update, after the optional learned proposal:
 // choose h, clip to h_max, failure conditions of Sec. 2.2, next attempt's step
-__device__ void finalize_step(Ctl* c, bool want, float delta) {
+__device__ __forceinline__ void finalize_step(Ctl* c, bool want, float delta) {
   double hn = c->h;
   int prop = 0;
   if (want && isfinite(delta)) {
@@ -1568,7 +1608,6 @@ __device__ __forceinline__ void finalize_block(const Args& a, int blk) {
     if (writer && tid < kWords) ((unsigned long long*)a.ctl_out)[tid] = ((const unsigned long long*)&sc)[tid];
     return;
   }
-  Ctl* c = &sc;
   m0 = wave_nanmax(m0);
   m1 = wave_nanmax(m1);
   if (lane == 0) {
@@ -1586,15 +1625,23 @@ __device__ __forceinline__ void finalize_block(const Args& a, int blk) {
       m1 = nanmax(m1, sR1[w]);
     }
     s_want = 0;
-    if (rflag) c->status = kStatusRange;
-    else s_want = finalize(a, c, m0, m1, writer, s_feat) ? 1 : 0;
-    s_next = (a.stage == ST_INIT && !(c->h0user > 0.0)) ? ST_H0 : ST_S2;
+    // the decision is a chain of dependent updates of the control state: run it on a
+    // copy in registers, not field by field in LDS
+    Ctl cl = sc;
+    if (rflag) cl.status = kStatusRange;
+    else s_want = finalize(a, &cl, m0, m1, writer, s_feat) ? 1 : 0;
+    s_next = (a.stage == ST_INIT && !(cl.h0user > 0.0)) ? ST_H0 : ST_S2;
+    sc = cl;
   }
   __syncthreads();
   if ((a.stage == ST_S4 || a.stage == ST_D7) && sc.status == kRunning) {
     // learned proposal (whole workgroup), then the rest of the step-size update
     const float delta = s_want ? mlp_forward_wg(a.mlp, s_feat, s_h1, s_h2, s_red) : 0.0f;
-    if (tid == 0) finalize_step(c, s_want != 0, delta);
+    if (tid == 0) {
+      Ctl cl = sc;
+      finalize_step(&cl, s_want != 0, delta);
+      sc = cl;
+    }
     __syncthreads();
   }
   if (writer && tid < kWords) ((unsigned long long*)a.ctl_out)[tid] = ((const unsigned long long*)&sc)[tid];
@@ -1781,9 +1828,9 @@ int tile_kalign(int fmt, const Tile& t) {
 #define BS32_F32_TILES(X)                                                                                   \
   X(1, 4, 1, 2, 0) X(1, 1, 4, 2, 0) X(2, 1, 4, 2, 0) X(1, 1, 8, 2, 0) X(1, 1, 4, 4, 0) X(2, 1, 4, 4, 0)     \
   X(1, 1, 8, 4, 0) X(2, 1, 4, 2, 1) X(1, 1, 8, 4, 1) X(1, 1, 16, 2, 0)
-#define BS32_MMA_TILES(X)                                                                                   \
-  X(1, 1, 8, 2, 0) X(1, 1, 8, 4, 0) X(1, 1, 8, 8, 0) X(1, 1, 16, 4, 0) X(1, 1, 16, 8, 0) X(2, 1, 8, 4, 0)  \
-  X(1, 1, 4, 8, 0) X(2, 1, 4, 4, 0) X(1, 1, 8, 4, 1) X(1, 1, 16, 4, 1) X(2, 1, 8, 4, 1) X(1, 2, 8, 4, 0)
+#define BS32_MMA_TILES(X)                                                                    \
+  X(1, 1, 8, 2, 0) X(1, 1, 8, 4, 0) X(1, 1, 8, 8, 0) X(2, 1, 8, 4, 0) X(1, 1, 4, 8, 0) X(2, 1, 4, 4, 0) \
+  X(1, 1, 8, 4, 1) X(2, 1, 8, 4, 1) X(1, 1, 4, 4, 0) X(1, 1, 4, 8, 1) X(1, 1, 8, 8, 1)
 
 // pairwise kernels: (R rows per wave, WV waves, UJ column chunks per step)
 #define BS32_PAIR_TILES(X) X(2, 4, 1) X(4, 4, 1) X(8, 4, 1) X(4, 4, 2)
