@@ -11,7 +11,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbs32.so")
-SOURCES = ["bs32_kernels.hip", "bs32_mlp.hip", "bs32_lco.hip", "bs32_capi.cpp"]
+SOURCES = ["bs32_kernels.hip", "bs32_mlp.hip", "bs32_lco.hip", "bs32_blas.cpp", "bs32_capi.cpp"]
+# hipBLASLt: the plain library product of 16-bit shared-coupling ensembles
+LIBS = ["-L/opt/rocm/lib", "-lhipblaslt"]
 
 FLAGS = [
     "--offload-arch=gfx950",
@@ -41,7 +43,7 @@ def build(verbose: bool = False) -> str:
             print(msg)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, *LIBS, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)

@@ -81,6 +81,14 @@ struct TraceRec {
   int accepted, proposer;
 };
 
+// operand buffer a contraction reads: stage 3 of BS3(2) and the odd Dormand-Prince
+// stages read buffer 1, the rest buffer 0 (each stage writes the next one's input
+// into the other buffer)
+__host__ __device__ inline int vin_of(int stage) {
+  if (stage >= ST_D2) return (stage - ST_D2) & 1;
+  return stage == ST_S3 ? 1 : 0;
+}
+
 // Arguments of the contraction / prep / finalize kernels (passed by value).
 struct Args {
   const void* A;          // packed coupling, rows_pad x ld, storage format
@@ -147,6 +155,9 @@ struct Shared {
   int nrb, ncb;           // row and column blocks of the product
   double scale;           // power-of-two scale of the stored coupling
   int vshift;             // exponent shift between the operand's split terms
+  const float* Pg[2];     // library product tile source (tile NT = 1): P of A (and of the BF16
+                          // pair's remainder plane), [np][ldp] FP32; null for the fused kernels
+  long long ldp;          // row stride of Pg (operand columns of all pooled instances)
 };
 
 // Contraction tile: WR row groups x WK k-slices of waves per workgroup; each wave
@@ -154,7 +165,7 @@ struct Shared {
 // keeps U loads per row in flight.  Pairwise kernels: WR waves of R rows, U
 // column chunks of 64 per step.
 struct Tile {
-  int R, WR, WK, U, NT;  // NT: non-temporal loads of A
+  int R, WR, WK, U, NT;  // NT: non-temporal loads of A (shared products: 1 = library product + epilogue)
   int MM;                // 0: vector-ALU kernel, 1: matrix-core kernel (16-row tiles), 2: pairwise kernel,
                          // 3: shared-coupling product (R: 16-row tiles per wave of 4, U: 16-column tiles)
 };
@@ -181,6 +192,13 @@ hipError_t launch_group_contract(const Group& g, int m, int fmt, const Tile& t, 
 hipError_t launch_group_prep(const Group& g, unsigned grid, hipStream_t s);
 hipError_t launch_group_finalize(const Group& g, unsigned grid, hipStream_t s);
 hipError_t launch_shared_contract(const Shared& sh, int m, int fmt, const Tile& t, hipStream_t s);
+
+// plain library product for 16-bit shared products (bs32_blas.cpp)
+struct BlasProduct;
+BlasProduct* blas_create(char* err, size_t cap);
+void blas_destroy(BlasProduct* b);
+int blas_product(BlasProduct* b, int fmt, const void* A, const void* B, long long rows, long long m, long long ld,
+                 float* P, hipStream_t stream, char* err, size_t cap);
 
 // learned proposer training (bs32_mlp.hip)
 hipError_t launch_mlp_grad(const float* W, const float* X, const float* Y, const int* idx, int nb, float inv_n,

@@ -333,14 +333,6 @@ __device__ __forceinline__ void rhs_eval(const Args& a, const double* y, const d
 // Single keeps its solution and stage inputs in FP32
 __device__ __forceinline__ double sstore(const Args& a, double v) { return a.sstate ? (double)(float)v : v; }
 
-// operand buffer a contraction reads: stage 3 of BS3(2) and the odd Dormand-Prince
-// stages read buffer 1, the rest buffer 0 (each stage writes the next one's input
-// into the other buffer)
-__device__ __forceinline__ int vin_of(int stage) {
-  if (stage >= ST_D2) return (stage - ST_D2) & 1;
-  return stage == ST_S3 ? 1 : 0;
-}
-
 // ---------------------------------------------------------------------------
 // stage epilogue of one row.  Its inputs are loaded by load_row before the
 // contraction loop, so that their latency hides behind the stream of A; the
@@ -1124,6 +1116,9 @@ __global__ __launch_bounds__(256) void k_group_prep(Group g) { BS32_GROUP_LOOP(p
 // storage: FP64 matrix cores throughout.  Workgroups are ordered so that the
 // eight XCDs each take a contiguous range of row blocks (the column blocks of a
 // row block share its A rows in that XCD's L2).
+// FROMP: the product itself came from the library (16-bit storage, FP32
+// accumulation over the whole k and FP32 output, one product per plane of A); the
+// kernel reads its P tile from there and runs the same row epilogues.
 // ---------------------------------------------------------------------------
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
@@ -1165,10 +1160,10 @@ constexpr bool sh_f32acc() {
   return FMT == F_BF16 || FMT == F_F16;
 }
 
-template <int FMT, int RT, int CT>
+template <int FMT, int RT, int CT, bool FROMP>
 constexpr int sh_lds_bytes() {
   constexpr int BM = 64 * RT, BN = 16 * CT;
-  constexpr int tiles = 2 * BN * kShPitch, part = BM * (BN + 1) * (sh_f32acc<FMT>() ? 4 : 8);
+  constexpr int tiles = FROMP ? 0 : 2 * BN * kShPitch, part = BM * (BN + 1) * (sh_f32acc<FMT>() ? 4 : 8);
   return tiles > part ? tiles : part;
 }
 
@@ -1178,7 +1173,7 @@ int shared_cols(int fmt, int m) {
   return 0;  // e4m3's three terms do not tile the product's columns
 }
 
-template <int FMT, int M, int RT, int CT>
+template <int FMT, int M, int RT, int CT, bool FROMP = false>
 __global__ __launch_bounds__(256) void k_shared_contract(Shared sh) {
   constexpr int ES = FMT == F_F64 ? 8 : FMT == F_F32 ? 4 : 2;  // bytes per element of A (per plane) and operand
   constexpr int T = FMT == F_F64 ? 1 : 2;
@@ -1189,7 +1184,7 @@ __global__ __launch_bounds__(256) void k_shared_contract(Shared sh) {
   constexpr int UNITS = BN * kShChunk / 16 / 256;  // 16-byte operand loads per thread and chunk
   static_assert(BN % C == 0, "whole instances per column block");
   using Acc = typename ShAcc<FMT>::T;
-  __shared__ __align__(16) char smem[sh_lds_bytes<FMT, RT, CT>()];
+  __shared__ __align__(16) char smem[sh_lds_bytes<FMT, RT, CT, FROMP>()];
   __shared__ double sRed0[4], sRed1[4];
 
   // XCD-aware tile order: blockIdx.x % 8 selects the XCD
@@ -1212,147 +1207,162 @@ __global__ __launch_bounds__(256) void k_shared_contract(Shared sh) {
     if (!__syncthreads_or(live)) return;
   }
 
-  const long long ld = sh.ld;
-  const long long row_base = (long long)rb * BM + w * 16 * RT;
-  const char* ap[RT];
+  constexpr bool F32ACC = sh_f32acc<FMT>();
+  // P tile [BM][BN] (FP32 for 16-bit storage, else FP64)
+  using PT = typename std::conditional<F32ACC, float, double>::type;
+  PT* sP = (PT*)smem;
+  constexpr int PP = BN + 1;
+  if constexpr (FROMP) {
+    // the library's P of this tile: rows rb*BM.., columns cb*BN.. (the BF16 pair adds its
+    // remainder plane's product in FP64)
+    const float* P0 = sh.Pg[0] + ((long long)rb * BM) * sh.ldp + (long long)cb * BN;
+    const float* P1 = (PL == 2) ? sh.Pg[1] + ((long long)rb * BM) * sh.ldp + (long long)cb * BN : nullptr;
+    for (int e = tid; e < BM * BN; e += 256) {
+      const int row = e / BN, col = e % BN;
+      const long long o = (long long)row * sh.ldp + col;
+      if constexpr (PL == 2) sP[row * PP + col] = (PT)((double)P0[o] + (double)P1[o]);
+      else sP[row * PP + col] = (PT)P0[o];
+    }
+  } else {
+    const long long ld = sh.ld;
+    const long long row_base = (long long)rb * BM + w * 16 * RT;
+    const char* ap[RT];
 #pragma unroll
-  for (int t = 0; t < RT; ++t) ap[t] = (const char*)sh.A + ((row_base + 16 * t + r16) * ld) * ES + g * 16;
-  const char* Bg = (const char*)sh.Bop[vin_of(stage)];
-  const long long nchunk = ld * ES / kShChunk;
+    for (int t = 0; t < RT; ++t) ap[t] = (const char*)sh.A + ((row_base + 16 * t + r16) * ld) * ES + g * 16;
+    const char* Bg = (const char*)sh.Bop[vin_of(stage)];
+    const long long nchunk = ld * ES / kShChunk;
 
-  // operand unit q of this thread in a chunk: global source and LDS destination(s)
-  auto load_units = [&](u32x4 (&v)[UNITS], long long ch) {
+    // operand unit q of this thread in a chunk: global source and LDS destination(s)
+    auto load_units = [&](u32x4 (&v)[UNITS], long long ch) {
 #pragma unroll
-    for (int q = 0; q < UNITS; ++q) {
-      const int u = tid + 256 * q;
-      if constexpr (FMT == F_F64 && M == 2) {
-        // [b][ld][2] doubles: 16 bytes = both columns of one k
-        const int ib = u / 32, part = u % 32;
-        const long long b = (long long)cb * IB + ib;
-        v[q] = *(const u32x4*)(Bg + ((b * ld + ch * (kShChunk / 8) + part) * 2) * 8);
-      } else {
-        const int col = u / 16, part = u % 16;
-        v[q] = *(const u32x4*)(Bg + ((long long)(cb * BN + col) * ld) * ES + ch * kShChunk + part * 16);
+      for (int q = 0; q < UNITS; ++q) {
+        const int u = tid + 256 * q;
+        if constexpr (FMT == F_F64 && M == 2) {
+          // [b][ld][2] doubles: 16 bytes = both columns of one k
+          const int ib = u / 32, part = u % 32;
+          const long long b = (long long)cb * IB + ib;
+          v[q] = *(const u32x4*)(Bg + ((b * ld + ch * (kShChunk / 8) + part) * 2) * 8);
+        } else {
+          const int col = u / 16, part = u % 16;
+          v[q] = *(const u32x4*)(Bg + ((long long)(cb * BN + col) * ld) * ES + ch * kShChunk + part * 16);
+        }
       }
-    }
-  };
-  auto store_units = [&](const u32x4 (&v)[UNITS], int buf) {
-    char* base = smem + buf * BN * kShPitch;
+    };
+    auto store_units = [&](const u32x4 (&v)[UNITS], int buf) {
+      char* base = smem + buf * BN * kShPitch;
 #pragma unroll
-    for (int q = 0; q < UNITS; ++q) {
-      const int u = tid + 256 * q;
-      if constexpr (FMT == F_F64 && M == 2) {
-        const int ib = u / 32, part = u % 32;
-        const f64x2 x = __builtin_bit_cast(f64x2, v[q]);
-        *(double*)(base + (2 * ib) * kShPitch + part * 8) = x[0];
-        *(double*)(base + (2 * ib + 1) * kShPitch + part * 8) = x[1];
-      } else {
-        const int col = u / 16, part = u % 16;
-        *(u32x4*)(base + col * kShPitch + part * 16) = v[q];
+      for (int q = 0; q < UNITS; ++q) {
+        const int u = tid + 256 * q;
+        if constexpr (FMT == F_F64 && M == 2) {
+          const int ib = u / 32, part = u % 32;
+          const f64x2 x = __builtin_bit_cast(f64x2, v[q]);
+          *(double*)(base + (2 * ib) * kShPitch + part * 8) = x[0];
+          *(double*)(base + (2 * ib + 1) * kShPitch + part * 8) = x[1];
+        } else {
+          const int col = u / 16, part = u % 16;
+          *(u32x4*)(base + col * kShPitch + part * 16) = v[q];
+        }
       }
-    }
-  };
-  const long long plane_bytes = sh.np * ld * ES;
-  auto load_a = [&](u32x4 (&av)[NSTEP][RT * PL], long long ch) {
+    };
+    const long long plane_bytes = sh.np * ld * ES;
+    auto load_a = [&](u32x4 (&av)[NSTEP][RT * PL], long long ch) {
 #pragma unroll
-    for (int s = 0; s < NSTEP; ++s)
+      for (int s = 0; s < NSTEP; ++s)
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int q = 0; q < PL; ++q) av[s][t * PL + q] = *(const u32x4*)(ap[t] + q * plane_bytes + ch * kShChunk + s * 64);
+    };
+
+    constexpr bool FLUSH = !F32ACC && FMT != F_F64;
+    Acc c[RT][CT];
+    double dacc[FLUSH ? RT : 1][FLUSH ? CT : 1][4];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int u = 0; u < CT; ++u) c[t][u] = Acc{0, 0, 0, 0};
+    if constexpr (FLUSH) {
 #pragma unroll
       for (int t = 0; t < RT; ++t)
 #pragma unroll
-        for (int q = 0; q < PL; ++q) av[s][t * PL + q] = *(const u32x4*)(ap[t] + q * plane_bytes + ch * kShChunk + s * 64);
-  };
+        for (int u = 0; u < CT; ++u)
+          for (int i = 0; i < 4; ++i) dacc[t][u][i] = 0.0;
+    }
 
-  constexpr bool F32ACC = sh_f32acc<FMT>();
-  constexpr bool FLUSH = !F32ACC && FMT != F_F64;
-  Acc c[RT][CT];
-  double dacc[FLUSH ? RT : 1][FLUSH ? CT : 1][4];
+    u32x4 bu[UNITS];
+    u32x4 a0[NSTEP][RT * PL], a1[NSTEP][RT * PL];
+    load_units(bu, 0);
+    load_a(a0, 0);
+    store_units(bu, 0);
+    __syncthreads();
+    auto compute = [&](const u32x4 (&av)[NSTEP][RT * PL], int buf) {
+      const char* base = smem + buf * BN * kShPitch;
 #pragma unroll
-  for (int t = 0; t < RT; ++t)
+      for (int s = 0; s < NSTEP; ++s) {
 #pragma unroll
-    for (int u = 0; u < CT; ++u) c[t][u] = Acc{0, 0, 0, 0};
-  if constexpr (FLUSH) {
+        for (int u = 0; u < CT; ++u) {
+          const u32x4 bv = *(const u32x4*)(base + (16 * u + r16) * kShPitch + s * 64 + g * 16);
+#pragma unroll
+          for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int q = 0; q < PL; ++q) c[t][u] = sh_mma<FMT>(av[s][t * PL + q], bv, c[t][u]);  // (hi + lo) b
+        }
+      }
+      if constexpr (FLUSH) {  // FP64 across chunks
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int u = 0; u < CT; ++u) {
+            for (int i = 0; i < 4; ++i) dacc[t][u][i] += (double)c[t][u][i];
+            c[t][u] = Acc{0, 0, 0, 0};
+          }
+      }
+    };
+    for (long long ch = 0; ch < nchunk; ch += 2) {
+      // chunk ch from buffer 0 / registers a0 while chunk ch+1 is fetched, then the reverse
+      const bool more1 = ch + 1 < nchunk;
+      if (more1) {
+        load_units(bu, ch + 1);
+        load_a(a1, ch + 1);
+      }
+      compute(a0, 0);
+      if (!more1) break;
+      store_units(bu, 1);
+      __syncthreads();
+      const bool more2 = ch + 2 < nchunk;
+      if (more2) {
+        load_units(bu, ch + 2);
+        load_a(a0, ch + 2);
+      }
+      compute(a1, 1);
+      if (!more2) break;
+      store_units(bu, 0);
+      __syncthreads();
+    }
+    __syncthreads();  // every wave is done with the operand tiles: the LDS now takes P
+
+    // lane (r16, g) holds column r16 of each 16x16 tile: rows 4g + i for the FP32-output
+    // instructions, rows g + 4i for the FP64 one (measured)
 #pragma unroll
     for (int t = 0; t < RT; ++t)
 #pragma unroll
       for (int u = 0; u < CT; ++u)
-        for (int i = 0; i < 4; ++i) dacc[t][u][i] = 0.0;
-  }
-
-  u32x4 bu[UNITS];
-  u32x4 a0[NSTEP][RT * PL], a1[NSTEP][RT * PL];
-  load_units(bu, 0);
-  load_a(a0, 0);
-  store_units(bu, 0);
-  __syncthreads();
-  auto compute = [&](const u32x4 (&av)[NSTEP][RT * PL], int buf) {
-    const char* base = smem + buf * BN * kShPitch;
-#pragma unroll
-    for (int s = 0; s < NSTEP; ++s) {
-#pragma unroll
-      for (int u = 0; u < CT; ++u) {
-        const u32x4 bv = *(const u32x4*)(base + (16 * u + r16) * kShPitch + s * 64 + g * 16);
-#pragma unroll
-        for (int t = 0; t < RT; ++t)
-#pragma unroll
-          for (int q = 0; q < PL; ++q) c[t][u] = sh_mma<FMT>(av[s][t * PL + q], bv, c[t][u]);  // (hi + lo) b
-      }
-    }
-    if constexpr (FLUSH) {  // FP64 across chunks
-#pragma unroll
-      for (int t = 0; t < RT; ++t)
-#pragma unroll
-        for (int u = 0; u < CT; ++u) {
-          for (int i = 0; i < 4; ++i) dacc[t][u][i] += (double)c[t][u][i];
-          c[t][u] = Acc{0, 0, 0, 0};
+        for (int i = 0; i < 4; ++i) {
+          const int rr = (FMT == F_F64) ? g + 4 * i : 4 * g + i;
+          const int row = w * 16 * RT + 16 * t + rr, col = 16 * u + r16;
+          if constexpr (FLUSH) sP[row * PP + col] = dacc[t][u][i];
+          else sP[row * PP + col] = (PT)c[t][u][i];
         }
-    }
-  };
-  for (long long ch = 0; ch < nchunk; ch += 2) {
-    // chunk ch from buffer 0 / registers a0 while chunk ch+1 is fetched, then the reverse
-    const bool more1 = ch + 1 < nchunk;
-    if (more1) {
-      load_units(bu, ch + 1);
-      load_a(a1, ch + 1);
-    }
-    compute(a0, 0);
-    if (!more1) break;
-    store_units(bu, 1);
-    __syncthreads();
-    const bool more2 = ch + 2 < nchunk;
-    if (more2) {
-      load_units(bu, ch + 2);
-      load_a(a0, ch + 2);
-    }
-    compute(a1, 1);
-    if (!more2) break;
-    store_units(bu, 0);
-    __syncthreads();
   }
-  __syncthreads();  // every wave is done with the operand tiles: the LDS now takes P
-
-  // P tile [BM][BN] (FP32 for 16-bit storage, else FP64).  Lane (r16, g) holds column
-  // r16 of each 16x16 tile: rows 4g + i for the FP32-output instructions, rows g + 4i
-  // for the FP64 one (measured)
-  using PT = typename std::conditional<F32ACC, float, double>::type;
-  PT* sP = (PT*)smem;
-  constexpr int PP = BN + 1;
-#pragma unroll
-  for (int t = 0; t < RT; ++t)
-#pragma unroll
-    for (int u = 0; u < CT; ++u)
-      for (int i = 0; i < 4; ++i) {
-        const int rr = (FMT == F_F64) ? g + 4 * i : 4 * g + i;
-        const int row = w * 16 * RT + 16 * t + rr, col = 16 * u + r16;
-        if constexpr (FLUSH) sP[row * PP + col] = dacc[t][u][i];
-        else sP[row * PP + col] = (PT)c[t][u][i];
-      }
   __syncthreads();
 
   // row epilogues: BM consecutive threads serve one instance
   const bool reduce = !(stage == ST_S2 || stage == ST_S3 || stage == ST_RHS);
   for (int e0 = 0; e0 < BM * IB; e0 += 256) {
     const int e = e0 + tid;
-    const int ib = e / BM, row = e % BM;
+    // BM is a multiple of 64, so a wave serves one instance: its index is wave-uniform
+    // and the instance's arguments come through scalar loads
+    const int ib = __builtin_amdgcn_readfirstlane(e / BM), row = e % BM;
     const int b = cb * IB + ib;
     double r0 = 0.0, r1 = 0.0;
     if (b < sh.B) {
@@ -1823,11 +1833,10 @@ int tile_kalign(int fmt, const Tile& t) {
 // (R, WR, WK, U, NT): the candidate set the autotuner times, per kernel family
 #define BS32_F64_TILES(X)                                                                                   \
   X(1, 4, 1, 4, 0) X(2, 1, 4, 2, 0) X(2, 2, 2, 2, 0) X(4, 1, 4, 2, 0) X(1, 1, 8, 2, 0) X(1, 1, 4, 8, 0)     \
-  X(2, 1, 4, 4, 0) X(1, 1, 8, 4, 0) X(2, 1, 4, 2, 1) X(4, 1, 4, 2, 1) X(1, 1, 4, 8, 1) X(2, 1, 8, 4, 0)     \
-  X(1, 1, 16, 2, 0)
+  X(2, 1, 4, 4, 0) X(1, 1, 8, 4, 0) X(2, 1, 4, 2, 1) X(4, 1, 4, 2, 1) X(1, 1, 4, 8, 1) X(2, 1, 8, 4, 0)
 #define BS32_F32_TILES(X)                                                                                   \
   X(1, 4, 1, 2, 0) X(1, 1, 4, 2, 0) X(2, 1, 4, 2, 0) X(1, 1, 8, 2, 0) X(1, 1, 4, 4, 0) X(2, 1, 4, 4, 0)     \
-  X(1, 1, 8, 4, 0) X(2, 1, 4, 2, 1) X(1, 1, 8, 4, 1) X(1, 1, 16, 2, 0)
+  X(1, 1, 8, 4, 0) X(2, 1, 4, 2, 1) X(1, 1, 8, 4, 1)
 #define BS32_MMA_TILES(X)                                                                    \
   X(1, 1, 8, 2, 0) X(1, 1, 8, 4, 0) X(1, 1, 8, 8, 0) X(2, 1, 8, 4, 0) X(1, 1, 4, 8, 0) X(2, 1, 4, 4, 0) \
   X(1, 1, 8, 4, 1) X(2, 1, 8, 4, 1) X(1, 1, 4, 4, 0) X(1, 1, 4, 8, 1) X(1, 1, 8, 8, 1)
@@ -1848,7 +1857,7 @@ static const Tile kMmaTiles[] = {BS32_MMA_TILES(BS32_TILE_MMA)};
 static const Tile kPairTiles[] = {BS32_PAIR_TILES(BS32_TILE_PAIR)};
 #undef BS32_TILE_PAIR
 #define BS32_TILE_SHARED(RT_, CT_) Tile{RT_, 4, 1, CT_, 0, 3},
-static const Tile kSharedTiles[] = {BS32_SHARED_TILES(BS32_TILE_SHARED)};
+static const Tile kSharedTiles[] = {BS32_SHARED_TILES(BS32_TILE_SHARED) Tile{1, 4, 1, 8, 1, 3}};
 #undef BS32_TILE_SHARED
 #undef BS32_TILE_VALU
 #undef BS32_TILE_MMA
@@ -1880,6 +1889,17 @@ template <int FMT, int M>
 static hipError_t launch_shared_t(const Shared* sh, const Tile& t, hipStream_t s) {
   const int total = sh ? sh->nrb * sh->ncb : 0;
   const unsigned grid = 8u * (unsigned)((total + 7) / 8);
+  if (t.NT) {  // library product + epilogue: 16-bit storage, 64 x 128 epilogue tiles
+    if constexpr (FMT == F_BF16 || FMT == F_F16 || FMT == F_BF16X2) {
+      if (t.R == 1 && t.U == 8) {
+        if (!sh) return hipSuccess;
+        if (sh->Pg[0] == nullptr || (FMT == F_BF16X2 && sh->Pg[1] == nullptr)) return hipErrorInvalidValue;
+        if (total > 0) k_shared_contract<FMT, M, 1, 8, true><<<grid, 256, 0, s>>>(*sh);
+        return hipGetLastError();
+      }
+    }
+    return hipErrorInvalidValue;
+  }
 #define X(RT_, CT_)                                                                       \
   if (t.R == RT_ && t.U == CT_) {                                                         \
     if constexpr (RT_ == 4 && !sh_f32acc<FMT>()) {                                        \
@@ -2009,6 +2029,8 @@ static hipError_t dispatch(const Launch& L, int m, int fmt, const Tile& t) {
 int kernel_name(int fmt, int m, const Tile& t, char* buf, size_t cap) {
   if (!tile_supported(fmt, m, t)) return -1;
   const char* nt = t.NT ? "true" : "false";
+  if (t.MM == 3 && t.NT)
+    return snprintf(buf, cap, "hipBLASLt product + k_shared_contract<%d, %d, %d, %d, true>", fmt, m, t.R, t.U);
   if (t.MM == 3) return snprintf(buf, cap, "k_shared_contract<%d, %d, %d, %d>", fmt, m, t.R, t.U);
   if (t.MM == 2)  // the system kind and weights also select the instance: name the family and tile
     return snprintf(buf, cap, "k_contract_pair<*, %s, *, %d, %d, %d>", fmt == F_F32 ? "true" : "false", t.R, t.WR,

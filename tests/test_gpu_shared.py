@@ -93,11 +93,14 @@ def test_shared_fp64_matches_oracle(bs, orc, kind, n, B):
     _check_against_oracle(b, s, orc, kind, base, params, gains, y0, t1, 1e-7, 0, 1e-10, (1, 0.01))
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5])
+LIBRARY_TILE = 6   # hipBLASLt product + the kernel's row epilogues (16-bit storage)
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, LIBRARY_TILE])
 @pytest.mark.parametrize("mode", [0, 1, 2, 3, 8])
 def test_shared_every_tile(bs, orc, tile, mode):
     """Every instantiated product tile in every storage format, on a ragged N and a
-    batch that does not fill the last column block."""
+    batch that does not fill the last column block; the library product too."""
     b, s = bs
     base, params, gains, y0 = _sweep("kuramoto", 333, 37, 77)
     y0 = y0[:37]
@@ -106,11 +109,13 @@ def test_shared_every_tile(bs, orc, tile, mode):
     s.set_options(tile=tile)
     try:
         s.set_shared_ensemble(base["kind"], 333, 37, A=base["A"], params=params, gains=gains)
-        if tile >= 4 and mode not in (2, 3):   # the 256-row tiles serve BF16 and FP16 only
+        served = (2, 3, 8) if tile == LIBRARY_TILE else (2, 3) if tile >= 4 else (0, 1, 2, 3, 8)
+        if mode not in served:   # the 256-row tiles serve BF16 and FP16, the library 16-bit storage
             with pytest.raises(b.BS32Error):
                 s.kernel_name(mode, tile)
             return
-        assert s.kernel_name(mode, tile).startswith("k_shared_contract<")
+        name = s.kernel_name(mode, tile)
+        assert name.startswith("hipBLASLt product + k_shared_contract<" if tile == LIBRARY_TILE else "k_shared_contract<")
         y, st, _ = s.solve_batch(y0.reshape(-1), 0.0, t1, 1e-6, mode=mode)
         assert np.all(st == 0)
         Y = y.reshape(37, -1)
@@ -130,6 +135,30 @@ def test_shared_reduced_tracks_oracle(bs, orc, mode):
     t1 = np.full(6, 2.0)
     say(f"[shared reduced] mode {mode}")
     _check_against_oracle(b, s, orc, "kuramoto", base, params, gains, y0, t1, 1e-6, mode, 2e-5, (2, 0.03))
+
+
+@pytest.mark.parametrize("mode", [2, 3, 8])
+def test_library_product_matches_fused(bs, mode):
+    """The library product (FP32 accumulation over the whole k) and the fused kernel
+    solve the same fixed-step sweep to FP32 summation-order differences."""
+    b, s = bs
+    base, params, gains, y0 = _sweep("kuramoto", 700, 37, 92)
+    say(f"[shared library vs fused] mode {mode}")
+    out = {}
+    try:
+        s.set_options(fixed_step=1, h0=0.02)
+        for tile in (1, LIBRARY_TILE):
+            s.set_options(tile=tile)
+            s.set_shared_ensemble(base["kind"], 700, 37, A=base["A"], params=params, gains=gains)
+            y, st, _ = s.solve_batch(y0.reshape(-1), 0.0, 1.0, 1e-6, mode=mode)
+            assert np.all(st == 0)
+            assert all(s.batch_stats(q)["n_accept"] == 50 for q in range(37))
+            out[tile] = y
+    finally:
+        s.set_options(tile=-1, fixed_step=0, h0=0.0)
+    rel = np.linalg.norm(out[1] - out[LIBRARY_TILE]) / np.linalg.norm(out[1])
+    say(f"   rel {rel:.2e}")
+    assert rel <= 1e-6
 
 
 def test_shared_equals_grouped_ensemble(bs):
