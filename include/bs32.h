@@ -251,11 +251,17 @@ bs32_status bs32_batch_stats(const bs32_ctx* ctx, int32_t instance, bs32_stats_t
    count gains (host; NULL = desc->gain).  Each instance keeps its own state,
    step size, counters and status; bs32_solve_batch and bs32_batch_stats work as
    for bs32_set_ensemble, and precision modes 0-3 (FP64, FP32, BF16, FP16
-   storage of A) are available.  The contraction of a stage for all instances is
-   one matrix product A [V_1 ... V_B] on the matrix cores (B x m x T operand
-   columns), followed by each instance's row epilogue in the same launch; this
-   is the general model (Sec. 2.1, eq. (1)) evaluated for many parameter sets at
-   once.  Replaces any system or ensemble; count in [1, 65536]. */
+   storage of A) and 8 (the BF16 pair) are available.  The contraction of a stage
+   for all instances is one matrix product A [V_1 ... V_B] on the matrix cores
+   (B x m x T operand columns), followed by each instance's row epilogue in the
+   same launch; this is the general model (Sec. 2.1, eq. (1)) evaluated for many
+   parameter sets at once.  With 16-bit storage (modes 2, 3, 8) one more tile
+   candidate computes the product as a plain library GEMM (hipBLASLt, FP32
+   accumulation and output, one product per plane of the BF16 pair) and then
+   launches the row epilogues on it; the autotuner takes it when it is faster,
+   and that path is enqueued eagerly (no graph capture) and allocates its P
+   buffer and workspace on first use.  Replaces any system or ensemble; count in
+   [1, 65536]. */
 bs32_status bs32_set_shared_ensemble(bs32_ctx* ctx, const bs32_system_desc* desc, int32_t count,
                                      const double* params, const double* gains);
 
