@@ -408,7 +408,9 @@ bs32_status autotune(bs32_ctx* c, int fmt) {
     HIPCHK(c, launch_prep(a, c->stream));
     HIPCHK(c, launch_contract(a, fmt, t, c->stream));
     HIPCHK(c, hipEventRecord(c->ev_start, c->stream));
-    for (int r = 0; r < 5; ++r) HIPCHK(c, launch_contract(a, fmt, t, c->stream));
+    // 20 launches: the candidates of a small system differ by a few percent, below the
+    // spread of a handful of launches
+    for (int r = 0; r < 20; ++r) HIPCHK(c, launch_contract(a, fmt, t, c->stream));
     HIPCHK(c, hipEventRecord(c->ev_stop, c->stream));
     HIPCHK(c, hipEventSynchronize(c->ev_stop));
     float ms = 0.f;
