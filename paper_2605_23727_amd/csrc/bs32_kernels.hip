@@ -66,10 +66,24 @@ __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
+// a double moved between lanes by a DPP control (both halves), VALU only
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xf, 0xf, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// maximum over the wave (NaN wins; exact, so the order does not matter): rotations by
+// 8, 4, 2, 1 lanes within each row of 16 (DPP row_ror), then across the four rows.
+// Every lane of the wave must be active.
 __device__ __forceinline__ double wave_nanmax(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = nanmax(v, __shfl_xor(v, off, 64));
-  return v;
+  v = nanmax(v, dpp_f64<0x128>(v));
+  v = nanmax(v, dpp_f64<0x124>(v));
+  v = nanmax(v, dpp_f64<0x122>(v));
+  v = nanmax(v, dpp_f64<0x121>(v));
+  v = nanmax(v, __shfl_xor(v, 16, 64));
+  return nanmax(v, __shfl_xor(v, 32, 64));
 }
 
 // XCD-aware block order: workgroups are dealt to the 8 XCDs round-robin; give each
@@ -1641,15 +1655,17 @@ __device__ __forceinline__ void finalize_block(const Args& a, int blk) {
     if (rflag) cl.status = kStatusRange;
     else s_want = finalize(a, &cl, m0, m1, writer, s_feat) ? 1 : 0;
     s_next = (a.stage == ST_INIT && !(cl.h0user > 0.0)) ? ST_H0 : ST_S2;
+    // without a learned proposal the rest of the step-size update follows at once
+    if ((a.stage == ST_S4 || a.stage == ST_D7) && cl.status == kRunning && !s_want) finalize_step(&cl, false, 0.0f);
     sc = cl;
   }
   __syncthreads();
-  if ((a.stage == ST_S4 || a.stage == ST_D7) && sc.status == kRunning) {
+  if ((a.stage == ST_S4 || a.stage == ST_D7) && sc.status == kRunning && s_want) {
     // learned proposal (whole workgroup), then the rest of the step-size update
-    const float delta = s_want ? mlp_forward_wg(a.mlp, s_feat, s_h1, s_h2, s_red) : 0.0f;
+    const float delta = mlp_forward_wg(a.mlp, s_feat, s_h1, s_h2, s_red);
     if (tid == 0) {
       Ctl cl = sc;
-      finalize_step(&cl, s_want != 0, delta);
+      finalize_step(&cl, true, delta);
       sc = cl;
     }
     __syncthreads();
