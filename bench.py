@@ -774,6 +774,8 @@ def bench_shared(args, torch, bs, modes, ref_rtol):
         single.set_system(bs.KURAMOTO, n, base["A"], omega[q].contiguous(), float(gains[q]))
         yq = theta0[q].contiguous()
         oq = torch.empty_like(yq)
+        # packing A and the autotuner run on the first solve of a system: outside the timing
+        single.solve(yq, 0.0, 1e-6 * t1, rtol, mode=bs.PREC_FP64, out=oq)
         torch.cuda.synchronize()
         tt = time.perf_counter()
         _, sst = single.solve(yq, 0.0, t1, rtol, mode=bs.PREC_FP64, out=oq)
