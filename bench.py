@@ -939,7 +939,7 @@ def bench_learned(args, torch, bs, ref_rtol):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported "
               "(the path would shard rows of A with one all-gather per stage).", file=sys.stderr)
         sys.exit(2)
     import torch
