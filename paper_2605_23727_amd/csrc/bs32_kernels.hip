@@ -1105,7 +1105,7 @@ __global__ __launch_bounds__(WR* WK * 64) void k_contract_mfma(Args a) {
   contract_mfma<FMT, M, T, RT, WR, WK, U, NT>(a, block_row(a));
 }
 template <int FMT, int M, int T, int RT, int WR, int WK, int U, bool NT>
-__global__ __launch_bounds__(WR* WK * 64) void k_group_mfma(Group g) {
+__global__ __launch_bounds__(WR* WK * 64, 2) void k_group_mfma(Group g) {
   BS32_GROUP_LOOP((contract_mfma<FMT, M, T, RT, WR, WK, U, NT, false>))
 }
 template <bool ATAN, bool G32, bool DENSE, int R, int WV, int UJ>
