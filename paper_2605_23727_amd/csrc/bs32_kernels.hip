@@ -1873,7 +1873,8 @@ static const Tile kMmaTiles[] = {BS32_MMA_TILES(BS32_TILE_MMA)};
 static const Tile kPairTiles[] = {BS32_PAIR_TILES(BS32_TILE_PAIR)};
 #undef BS32_TILE_PAIR
 #define BS32_TILE_SHARED(RT_, CT_) Tile{RT_, 4, 1, CT_, 0, 3},
-static const Tile kSharedTiles[] = {BS32_SHARED_TILES(BS32_TILE_SHARED) Tile{1, 4, 1, 8, 1, 3}};
+static const Tile kSharedTiles[] = {BS32_SHARED_TILES(BS32_TILE_SHARED) Tile{1, 4, 1, 8, 1, 3}, Tile{1, 4, 1, 4, 1, 3},
+                                     Tile{1, 4, 1, 2, 1, 3}};
 #undef BS32_TILE_SHARED
 #undef BS32_TILE_VALU
 #undef BS32_TILE_MMA
@@ -1905,12 +1906,16 @@ template <int FMT, int M>
 static hipError_t launch_shared_t(const Shared* sh, const Tile& t, hipStream_t s) {
   const int total = sh ? sh->nrb * sh->ncb : 0;
   const unsigned grid = 8u * (unsigned)((total + 7) / 8);
-  if (t.NT) {  // library product + epilogue: 16-bit storage, 64 x 128 epilogue tiles
+  if (t.NT) {  // library product + epilogue: 16-bit storage, 64 x 16 CT epilogue tiles
     if constexpr (FMT == F_BF16 || FMT == F_F16 || FMT == F_BF16X2) {
-      if (t.R == 1 && t.U == 8) {
+      if (t.R == 1 && (t.U == 8 || t.U == 4 || t.U == 2)) {
         if (!sh) return hipSuccess;
         if (sh->Pg[0] == nullptr || (FMT == F_BF16X2 && sh->Pg[1] == nullptr)) return hipErrorInvalidValue;
-        if (total > 0) k_shared_contract<FMT, M, 1, 8, true><<<grid, 256, 0, s>>>(*sh);
+        if (total > 0) {
+          if (t.U == 8) k_shared_contract<FMT, M, 1, 8, true><<<grid, 256, 0, s>>>(*sh);
+          else if (t.U == 4) k_shared_contract<FMT, M, 1, 4, true><<<grid, 256, 0, s>>>(*sh);
+          else k_shared_contract<FMT, M, 1, 2, true><<<grid, 256, 0, s>>>(*sh);
+        }
         return hipGetLastError();
       }
     }
