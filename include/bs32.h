@@ -169,6 +169,13 @@ typedef struct {
   int32_t accepted, proposer; /* proposer: 1 if the learned proposer chose h */
 } bs32_trace_rec;
 
+/* The recipe row the library evaluates (Table MP-Distrib) for precision_mode 5-7
+   and stage_row 0, 1, 2 (the paper's k2, k3, k4; the k4 row also serves the first
+   K1, the starting-step probe and bs32_rhs): flags[0] = F, flags[1] = Sigma,
+   flags[2] = G, each 1 for single and 0 for double.  Host only (no device or
+   context needed); EINVAL for other modes or rows. */
+bs32_status bs32_recipe_row(int precision_mode, int stage_row, int32_t flags[3]);
+
 /* Create a context on HIP device `device`.  hip_stream: a hipStream_t to run on, or
    NULL for a library-owned stream (default priority). */
 bs32_status bs32_create(bs32_ctx** out, int device, void* hip_stream);

@@ -98,6 +98,7 @@ def lib():
         L.orc_mlp_forward.argtypes = [P, P]
         L.orc_mlp_forward.restype = C.c_double
         L.orc_dp54_tableau.argtypes = [P, P, P, P]
+        L.orc_recipe_table.argtypes = [P]
         _lib = L
     return _lib
 
@@ -273,3 +274,14 @@ def dp54_tableau():
     c, a, b, bt = np.empty(7), np.empty(49), np.empty(7), np.empty(7)
     lib().orc_dp54_tableau(_ptr(c), _ptr(a), _ptr(b), _ptr(bt))
     return c, a.reshape(7, 7), b, bt
+
+
+def recipe_table():
+    """{(solver, stage): (F, Sigma, G)} with 1 = single, as the integrator uses it."""
+    out = np.zeros(27, dtype=np.int32)
+    lib().orc_recipe_table(_ptr(out))
+    t = {}
+    for r, solver in enumerate(("Single", "Mixed1", "Mixed2")):
+        for k, stage in enumerate(("k2", "k3", "k4")):
+            t[(solver, stage)] = tuple(int(v) for v in out[9 * r + 3 * k: 9 * r + 3 * k + 3])
+    return t

@@ -29,9 +29,12 @@
  * fixed point; quantizer bit patterns; DP5(4) against an independent library
  * integrator; the BF16-pair storage (hi + rounded remainder, the conclusion's
  * extension to other formats) by exact pairs, its 2^-17 bound and its reduction
- * to BF16 on BF16 weights.  The paper recipes (orc_rhs_recipe) are pinned only by their
- * reductions (all-double equals orc_rhs; single results are float values) and
- * are otherwise parity unpinned: the paper prints no per-test numbers.
+ * to BF16 on BF16 weights.  The paper recipes: the recipe table against the
+ * paper's Table MP-Distrib (a transcribed fixture), the stage each table row
+ * serves (one fixed-step attempt composed from single evaluations), and every
+ * single-precision branch of orc_rhs_recipe (pair term, its weight, the
+ * accumulation, the agent term, the gains and the eq. (CC) prefactor) by values
+ * derived by hand on inputs whose every rounding is known in closed form.
  */
 #include "bs32_oracle.h"
 #include <float.h>
@@ -594,6 +597,12 @@ static const int RECIPE[3][3][3] = {
     /* Mixed1 */ {{1, 1, 1}, {1, 1, 1}, {0, 0, 1}},
     /* Mixed2 */ {{0, 0, 1}, {0, 0, 1}, {0, 0, 1}},
 };
+
+void orc_recipe_table(int out[27]) {
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k)
+      for (int q = 0; q < 3; ++q) out[9 * r + 3 * k + q] = RECIPE[r][k][q];
+}
 
 /* stage: 2, 3, 4 (the first stage is always the FSAL copy of stage 4, and the
    very first one uses the stage-4 recipe: reading) */

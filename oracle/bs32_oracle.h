@@ -121,6 +121,11 @@ int orc_rhs_lowp(const orc_system* sys, int fmt, int split_fmt, int split_terms,
    {0 = double, 1 = single} for the agent term, the accumulation and the pair term. */
 int orc_rhs_recipe(const orc_system* sys, int pF, int pS, int pG, double t, const double* X, double* F);
 
+/* The recipe table the integrator uses (Table MP-Distrib): out[9 r + 3 k + q] for
+   solver r (0 Single, 1 Mixed1, 2 Mixed2), stage row k (0 k2, 1 k3, 2 k4) and
+   column q (0 F, 1 Sigma, 2 G); 1 = single, 0 = double. */
+void orc_recipe_table(int out[27]);
+
 /* ---- number formats ---------------------------------------------------- */
 /* Round-to-nearest-even of an FP64 value straight to the format (no double rounding);
    returns the rounded value as a double. */

@@ -100,6 +100,7 @@ _SIGS = {
                         C.c_void_p, C.c_void_p], C.c_int),
     "bs32_mlp_grad": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p], C.c_int),
     "bs32_set_controller": ([C.c_void_p, C.c_int, C.c_void_p, C.c_size_t], C.c_int),
+    "bs32_recipe_row": ([C.c_int, C.c_int, C.c_void_p], C.c_int),
     "bs32_last_error": ([C.c_void_p], C.c_char_p),
     "bs32_destroy": ([C.c_void_p], None),
 }
@@ -155,6 +156,15 @@ def mlp_features(trace, rtol):
     if rc != 0:
         raise BS32Error(rc, "bs32_mlp_features failed")
     return F[: n.value].copy(), Y[: n.value].copy()
+
+
+def recipe_row(mode, stage_row):
+    """(F, Sigma, G) single flags the library evaluates for a recipe mode and stage row (0 k2, 1 k3, 2 k4)."""
+    out = np.zeros(3, dtype=np.int32)
+    rc = lib().bs32_recipe_row(int(mode), int(stage_row), out.ctypes.data)
+    if rc != 0:
+        raise BS32Error(rc, "bs32_recipe_row failed")
+    return tuple(int(v) for v in out)
 
 
 class _Buf:

@@ -266,19 +266,28 @@ Geom geometry(const bs32_ctx* c, int fmt, const Tile& t) {
   return g;
 }
 
-// The paper's recipes (Sec. 2.3, Table MP-Distrib) on this path: the pair terms G
-// are single in every recipe (A stored FP32, the vector operand one FP32 term);
-// "F in S" evaluates the agent term and the coupling combination in FP32 and
-// "Sigma in S" accumulates the interaction sum in FP32; Single also keeps the
-// solution and stage inputs in FP32.  Rows k2, k3 are stages S2, S3; the k4 row
+// The paper's recipes (Sec. 2.3, Table MP-Distrib): rows k2, k3, k4 of Single,
+// Mixed1 and Mixed2; columns F, Sigma, G with 1 = single.
+constexpr int kRecipe[3][3][3] = {
+    {{1, 1, 1}, {1, 1, 1}, {1, 1, 1}},  // Single
+    {{1, 1, 1}, {1, 1, 1}, {0, 0, 1}},  // Mixed1
+    {{0, 0, 1}, {0, 0, 1}, {0, 0, 1}},  // Mixed2
+};
+
+// Table row a stage evaluates: S2 and S3 take rows k2 and k3; S4 takes k4, which
 // also serves the first K1, the starting-step probe and single evaluations.
+int recipe_row(int stage) { return stage == ST_S2 ? 0 : stage == ST_S3 ? 1 : 2; }
+
+// The recipes on this path: the pair terms G are single in every recipe (A
+// stored FP32, the vector operand one FP32 term); "F in S" evaluates the agent
+// term and the coupling combination in FP32 and "Sigma in S" accumulates the
+// interaction sum in FP32; Single also keeps the solution and stage inputs in FP32.
 void set_recipe(Args& a, int mode, int stage) {
-  if (mode < BS32_PREC_PAPER_SINGLE) return;
-  const bool k23 = stage == ST_S2 || stage == ST_S3;
-  const bool single = mode == BS32_PREC_PAPER_SINGLE || (mode == BS32_PREC_PAPER_MIXED1 && k23);
-  a.vsingle = 1;
-  a.fsingle = single ? 1 : 0;
-  a.sum32 = single ? 1 : 0;
+  if (mode < BS32_PREC_PAPER_SINGLE || mode > BS32_PREC_PAPER_MIXED2) return;
+  const int* p = kRecipe[mode - BS32_PREC_PAPER_SINGLE][recipe_row(stage)];
+  a.fsingle = p[0];
+  a.sum32 = p[1];
+  a.vsingle = p[2];
   a.sstate = mode == BS32_PREC_PAPER_SINGLE ? 1 : 0;
 }
 
@@ -544,6 +553,18 @@ bs32_status bs32_default_options(bs32_options* o) {
   o->use_graph = 1;
   o->trace_cap = 65536;
   o->tile = -1;
+  return BS32_OK;
+}
+
+bs32_status bs32_recipe_row(int mode, int stage_row, int32_t flags[3]) {
+  if (!flags || mode < BS32_PREC_PAPER_SINGLE || mode > BS32_PREC_PAPER_MIXED2 || stage_row < 0 || stage_row > 2)
+    return BS32_EINVAL;
+  const int stage = stage_row == 0 ? ST_S2 : stage_row == 1 ? ST_S3 : ST_S4;
+  Args a{};
+  set_recipe(a, mode, stage);
+  flags[0] = a.fsingle;
+  flags[1] = a.sum32;
+  flags[2] = a.vsingle;
   return BS32_OK;
 }
 
