@@ -12,9 +12,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbs32.so")
-SOURCES = ["bs32_kernels.hip", "bs32_mlp.hip", "bs32_lco.hip", "bs32_blas.cpp", "bs32_capi.cpp"]
+SOURCES = ["bs32_mlp.hip", "bs32_lco.hip", "bs32_blas.cpp", "bs32_capi.cpp"]
+# bs32_kernels.hip compiles as KERNEL_PARTS units, each instantiating its own kernel families
+KERNEL_PARTS = 9
 # hipBLASLt: the plain library product of 16-bit shared-coupling ensembles
-LIBS = ["-L/opt/rocm/lib", "-lhipblaslt"]
+LIBS = ["-L/opt/rocm/lib", "-lhipblaslt", "-Wl,--no-undefined"]
 
 FLAGS = [
     "--offload-arch=gfx950",
@@ -28,9 +30,12 @@ FLAGS = [
 ]
 
 
-def _compile(hipcc: str, src: str, verbose: bool) -> str:
-    obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(hipcc: str, unit: tuple, verbose: bool) -> str:
+    src, part = unit
+    stem = os.path.splitext(src)[0] + ("" if part is None else f"_p{part}")
+    obj = os.path.join(CSRC, stem + ".o")
+    defs = [] if part is None else [f"-DBS32_PART={part}"]
+    cmd = [hipcc, *FLAGS, *defs, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -45,8 +50,10 @@ def _compile(hipcc: str, src: str, verbose: bool) -> str:
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     # the translation units compile independently: one hipcc process each
-    with concurrent.futures.ThreadPoolExecutor(max_workers=min(len(SOURCES), 8)) as ex:
-        objs = list(ex.map(lambda src: _compile(hipcc, src, verbose), SOURCES))
+    units = [("bs32_kernels.hip", p) for p in range(KERNEL_PARTS)] + [(src, None) for src in SOURCES]
+    workers = max(1, min(len(units), os.cpu_count() or 1, 16))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
+        objs = list(ex.map(lambda u: _compile(hipcc, u, verbose), units))
     tmp = LIB + ".tmp"
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, *LIBS, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

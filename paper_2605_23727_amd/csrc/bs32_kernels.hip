@@ -21,6 +21,14 @@
 #include "bs32_internal.hpp"
 #include "bs32_mlp.hpp"
 
+// The file compiles as several translation units (BS32_PART = 0 .. 8), each
+// instantiating a disjoint family of kernels, so that the build runs them in
+// parallel; without BS32_PART it is a single unit holding everything.
+#ifndef BS32_PART
+#define BS32_PART -1
+#endif
+#define BS32_IN(p) (BS32_PART < 0 || BS32_PART == (p))
+
 namespace bs32 {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -37,17 +45,21 @@ __device__ __forceinline__ T ldA(const T* p) {
   else return *p;
 }
 
+#if BS32_IN(0)
 int dim_of(int kind) {
   return kind == 1 ? 2 : kind == 2 ? 2 : kind == 3 ? 1 : kind == 4 ? 3 : kind == 5 ? 4 : 0;
 }
 int vcols_of(int kind, int pairwise) { return (kind == 3 && !pairwise) ? 2 : 1; }
+#endif
 
 // constants of the clock / cell-cycle model, paper eq. (CC) (Sec. 2.1); k1 is per cell
 constexpr double kCcK0 = 2.0, kCcK2 = 0.144832, kCcK3 = 2.0, kCcA = 2.0, kCcB = 0.7, kCcC = 0.8,
                  kCcEps = 0.228249;
+#if BS32_IN(0)
 size_t fmt_bytes(int fmt) {
   return fmt == F_F64 ? 8 : (fmt == F_F32 || fmt == F_BF16X2) ? 4 : (fmt == F_BF16 || fmt == F_F16) ? 2 : 1;
 }
+#endif
 
 // ---------------------------------------------------------------------------
 // small helpers
@@ -1067,7 +1079,9 @@ __device__ __forceinline__ void prep_block(const Args& a, int blk) {
   else if (a.stage == ST_S2) y = sstore(a, X[i] + ctl->ha * (kA21 * K1[i]));
   write_operand(a, 0, i, y);
 }
+#if BS32_IN(0)
 __global__ void k_prep(Args a) { prep_block(a, blockIdx.x); }
+#endif
 
 // ---------------------------------------------------------------------------
 // kernels of one system (block index = row block) and of an ensemble (each
@@ -1112,7 +1126,9 @@ template <bool ATAN, bool G32, bool DENSE, int R, int WV, int UJ>
 __global__ __launch_bounds__(WV * 64) void k_contract_pair(Args a) {
   contract_pair<ATAN, G32, DENSE, R, WV, UJ>(a, block_row(a));
 }
+#if BS32_IN(0)
 __global__ __launch_bounds__(256) void k_group_prep(Group g) { BS32_GROUP_LOOP(prep_block) }
+#endif
 
 // ---------------------------------------------------------------------------
 // Shared-coupling ensembles: B instances with one coupling matrix A, each with
@@ -1181,11 +1197,13 @@ constexpr int sh_lds_bytes() {
   return tiles > part ? tiles : part;
 }
 
+#if BS32_IN(0)
 int shared_cols(int fmt, int m) {
   if (fmt == F_F64) return m;
   if (fmt == F_F32 || fmt == F_BF16 || fmt == F_F16 || fmt == F_BF16X2) return 2 * m;  // two split terms
   return 0;  // e4m3's three terms do not tile the product's columns
 }
+#endif
 
 template <int FMT, int M, int RT, int CT, bool FROMP = false>
 __global__ __launch_bounds__(256) void k_shared_contract(Shared sh) {
@@ -1689,6 +1707,7 @@ __device__ __forceinline__ void finalize_block(const Args& a, int blk) {
   }
 }
 
+#if BS32_IN(0)
 __global__ __launch_bounds__(256) void k_finalize(Args a) { finalize_block(a, blockIdx.x); }
 __global__ __launch_bounds__(256) void k_group_finalize(Group g) { BS32_GROUP_LOOP(finalize_block) }
 
@@ -1845,6 +1864,8 @@ int tile_kalign(int fmt, const Tile& t) {
   return fmt == F_F64 ? 128 : 256;
 }
 
+#endif  // BS32_IN(0)
+
 // ---- instantiated tiles ------------------------------------------------------
 // (R, WR, WK, U, NT): the candidate set the autotuner times, per kernel family
 #define BS32_F64_TILES(X)                                                                                   \
@@ -1864,6 +1885,7 @@ int tile_kalign(int fmt, const Tile& t) {
 // RT = 4 only for 16-bit storage (its FP32 P tile fits the LDS)
 #define BS32_SHARED_TILES(X) X(2, 4) X(1, 8) X(1, 4) X(2, 2) X(4, 4) X(4, 2)
 
+#if BS32_IN(0)
 #define BS32_TILE_VALU(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 0},
 #define BS32_TILE_MMA(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 1},
 static const Tile kF64Tiles[] = {BS32_F64_TILES(BS32_TILE_VALU)};
@@ -1901,6 +1923,28 @@ const Tile* shared_tile_candidates(int* count) {
   *count = (int)(sizeof(kSharedTiles) / sizeof(Tile));
   return kSharedTiles;
 }
+#endif  // BS32_IN(0)
+
+// one contraction launch: a single system (a) or an ensemble (g, ggrid workgroups)
+struct Launch {
+  const Args* a;
+  const Group* g;
+  unsigned ggrid;
+  hipStream_t s;
+  bool dry;
+};
+// the launchers of each kernel family (each defined in its own part)
+template <int M>
+hipError_t launch_f64(const Launch& L, const Tile& t);
+template <int M>
+hipError_t launch_f32(const Launch& L, const Tile& t);
+template <int FMT, int M, int T>
+hipError_t launch_mma(const Launch& L, const Tile& t);
+hipError_t launch_pair(const Launch& L, int fmt, const Tile& t);
+// sh == nullptr: only whether the instance exists
+hipError_t dispatch_shared(const Shared* sh, int m, int fmt, const Tile& t, hipStream_t s);
+
+#if BS32_IN(8)
 
 template <int FMT, int M>
 static hipError_t launch_shared_t(const Shared* sh, const Tile& t, hipStream_t s) {
@@ -1936,8 +1980,7 @@ static hipError_t launch_shared_t(const Shared* sh, const Tile& t, hipStream_t s
   return hipErrorInvalidValue;
 }
 
-// sh == nullptr: only whether the instance exists
-static hipError_t dispatch_shared(const Shared* sh, int m, int fmt, const Tile& t, hipStream_t s) {
+hipError_t dispatch_shared(const Shared* sh, int m, int fmt, const Tile& t, hipStream_t s) {
   if (t.MM != 3 || t.WR != 4) return hipErrorInvalidValue;
   switch (fmt) {
     case F_F64: return m == 2 ? launch_shared_t<F_F64, 2>(sh, t, s) : launch_shared_t<F_F64, 1>(sh, t, s);
@@ -1950,18 +1993,13 @@ static hipError_t dispatch_shared(const Shared* sh, int m, int fmt, const Tile& 
   }
 }
 
+#endif  // BS32_IN(8)
+
+#if BS32_IN(0)
 hipError_t launch_shared_contract(const Shared& sh, int m, int fmt, const Tile& t, hipStream_t s) {
   return dispatch_shared(&sh, m, fmt, t, s);
 }
-
-// one contraction launch: a single system (a) or an ensemble (g, ggrid workgroups)
-struct Launch {
-  const Args* a;
-  const Group* g;
-  unsigned ggrid;
-  hipStream_t s;
-  bool dry;
-};
+#endif
 #define BS32_LAUNCH(SINGLE, GROUP, THREADS)                                      \
   if (!L.dry) {                                                                  \
     if (L.g) GROUP<<<L.ggrid, THREADS, 0, L.s>>>(*L.g);                          \
@@ -1969,8 +2007,9 @@ struct Launch {
   }                                                                              \
   return L.dry ? hipSuccess : hipGetLastError();
 
+#if BS32_IN(1)
 template <int M>
-static hipError_t launch_f64(const Launch& L, const Tile& t) {
+hipError_t launch_f64(const Launch& L, const Tile& t) {
 #define X(R_, WR_, WK_, U_, NT_)                                                                 \
   if (t.R == R_ && t.WR == WR_ && t.WK == WK_ && t.U == U_ && t.NT == NT_) {                     \
     BS32_LAUNCH((k_contract_f64<M, R_, WR_, WK_, U_, NT_>), (k_group_f64<M, R_, WR_, WK_, U_, NT_>), \
@@ -1980,8 +2019,12 @@ static hipError_t launch_f64(const Launch& L, const Tile& t) {
 #undef X
   return hipErrorInvalidValue;
 }
+template hipError_t launch_f64<1>(const Launch&, const Tile&);
+template hipError_t launch_f64<2>(const Launch&, const Tile&);
+#endif
+#if BS32_IN(2)
 template <int M>
-static hipError_t launch_f32(const Launch& L, const Tile& t) {
+hipError_t launch_f32(const Launch& L, const Tile& t) {
 #define X(R_, WR_, WK_, U_, NT_)                                                                       \
   if (t.R == R_ && t.WR == WR_ && t.WK == WK_ && t.U == U_ && t.NT == NT_) {                           \
     BS32_LAUNCH((k_contract_f32<M, 2, R_, WR_, WK_, U_, NT_>), (k_group_f32<M, 2, R_, WR_, WK_, U_, NT_>), \
@@ -1991,8 +2034,12 @@ static hipError_t launch_f32(const Launch& L, const Tile& t) {
 #undef X
   return hipErrorInvalidValue;
 }
+template hipError_t launch_f32<1>(const Launch&, const Tile&);
+template hipError_t launch_f32<2>(const Launch&, const Tile&);
+#endif
+#if BS32_IN(3) || BS32_IN(4) || BS32_IN(5) || BS32_IN(6)
 template <int FMT, int M, int T>
-static hipError_t launch_mma(const Launch& L, const Tile& t) {
+hipError_t launch_mma(const Launch& L, const Tile& t) {
 #define X(R_, WR_, WK_, U_, NT_)                                                            \
   if (t.R == R_ && t.WR == WR_ && t.WK == WK_ && t.U == U_ && t.NT == NT_) {                \
     BS32_LAUNCH((k_contract_mfma<FMT, M, T, R_, WR_, WK_, U_, NT_>),                        \
@@ -2002,6 +2049,24 @@ static hipError_t launch_mma(const Launch& L, const Tile& t) {
 #undef X
   return hipErrorInvalidValue;
 }
+#endif
+#if BS32_IN(3)
+template hipError_t launch_mma<F_F32, 1, 2>(const Launch&, const Tile&);
+template hipError_t launch_mma<F_F32, 2, 2>(const Launch&, const Tile&);
+#endif
+#if BS32_IN(4)
+template hipError_t launch_mma<F_BF16, 1, 2>(const Launch&, const Tile&);
+template hipError_t launch_mma<F_BF16, 2, 2>(const Launch&, const Tile&);
+#endif
+#if BS32_IN(5)
+template hipError_t launch_mma<F_F16, 1, 2>(const Launch&, const Tile&);
+template hipError_t launch_mma<F_F16, 2, 2>(const Launch&, const Tile&);
+#endif
+#if BS32_IN(6)
+template hipError_t launch_mma<F_E4M3, 1, 3>(const Launch&, const Tile&);
+template hipError_t launch_mma<F_E4M3, 2, 3>(const Launch&, const Tile&);
+#endif
+#if BS32_IN(7)
 template <bool ATAN, bool G32, bool DENSE>
 static hipError_t launch_pair_t(const Launch& L, const Tile& t) {
 #define X(R_, WV_, UJ_)                                                                                  \
@@ -2016,7 +2081,7 @@ static hipError_t launch_pair_t(const Launch& L, const Tile& t) {
   return hipErrorInvalidValue;
 }
 // fmt F_F32 selects the FP32 pair term (the recipes), F_F64 the FP64 one
-static hipError_t launch_pair(const Launch& L, int fmt, const Tile& t) {
+hipError_t launch_pair(const Launch& L, int fmt, const Tile& t) {
   if (L.dry) return launch_pair_t<false, false, false>(L, t);
   if (L.g) return hipErrorInvalidValue;
   const bool atn = L.a->kind == 5, g32 = fmt == F_F32, dense = L.a->A != nullptr;
@@ -2027,8 +2092,10 @@ static hipError_t launch_pair(const Launch& L, int fmt, const Tile& t) {
   if (g32) return dense ? launch_pair_t<false, true, true>(L, t) : launch_pair_t<false, true, false>(L, t);
   return dense ? launch_pair_t<false, false, true>(L, t) : launch_pair_t<false, false, false>(L, t);
 }
+#endif  // BS32_IN(7)
 #undef BS32_LAUNCH
 
+#if BS32_IN(0)
 static hipError_t dispatch(const Launch& L, int m, int fmt, const Tile& t);
 bool tile_supported(int fmt, int m, const Tile& t);
 
@@ -2081,5 +2148,6 @@ hipError_t launch_group_finalize(const Group& g, unsigned grid, hipStream_t s) {
   k_group_finalize<<<grid, 256, 0, s>>>(g);
   return hipGetLastError();
 }
+#endif  // BS32_IN(0)
 
 }  // namespace bs32
