@@ -168,6 +168,7 @@ struct Tile {
   int R, WR, WK, U, NT;  // NT: non-temporal loads of A (shared products: 1 = library product + epilogue)
   int MM;                // 0: vector-ALU kernel, 1: matrix-core kernel (16-row tiles), 2: pairwise kernel,
                          // 3: shared-coupling product (R: 16-row tiles per wave of 4, U: 16-column tiles)
+  int EW = 0;            // single systems: one more wave that loads the rows' epilogue inputs and finishes them
 };
 const Tile* tile_candidates(int fmt, int* count);
 const Tile* pair_tile_candidates(int* count);

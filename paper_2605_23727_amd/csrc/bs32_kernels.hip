@@ -185,11 +185,13 @@ __device__ __forceinline__ P pick2(P const (&p)[2], int q) {
 // ---------------------------------------------------------------------------
 // vector operand of one agent and its split into reduced-format terms
 // ---------------------------------------------------------------------------
+// the vector operand of a coupled component y: (sin y, cos y) for the Kuramoto
+// matrix-vector form, y itself otherwise (linear couplings, pairwise forms)
 __device__ __forceinline__ void vec_of(const Args& a, double y, double* v) {
   if (a.kind == 3 && !a.pairwise) {
     sincos(y, &v[0], &v[1]);
   } else {
-    v[0] = y;  // linear couplings and the pairwise forms read the coupled component itself
+    v[0] = v[1] = y;
   }
 }
 
@@ -200,59 +202,99 @@ struct VSplit {
   static constexpr int S = VF == F_F32 ? 24 : VF == F_BF16 ? 8 : VF == F_F16 ? 11 : 4;
 };
 
+// FP64 -> FP32 rounded to odd: truncate toward zero, then set the last bit when the
+// value was inexact.  Rounding that result to a format of at most 22 significant
+// bits (to nearest, ties to even) gives the same value as rounding the FP64 value
+// straight to that format, so the hardware conversions from FP32 serve as an
+// exact FP64 rounding.
+__device__ __forceinline__ float f32_round_odd(double x) {
+  const float f = (float)x;
+  const double b = (double)f;
+  if (b == x) return f;
+  unsigned u = __float_as_uint(f);
+  if (fabs(b) > fabs(x)) --u;  // the nearest value lay away from zero: step back toward it
+  return __uint_as_float(u | 1u);
+}
+
+// one split term: Q(x) in storage format VF (round to nearest even from FP64; e4m3
+// saturates at +-448 like encode_rne); returns the term's value, *bits its encoding
+template <int VF>
+__device__ __forceinline__ double split_q(double x, uint32_t* bits) {
+  if constexpr (VF == F_BF16) {
+    const unsigned u = __float_as_uint(f32_round_odd(x));
+    const unsigned r = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;  // finite inputs: no carry into NaN
+    *bits = r;
+    return (double)__uint_as_float(r << 16);
+  } else if constexpr (VF == F_F16) {
+    const _Float16 h = (_Float16)f32_round_odd(x);
+    *bits = (uint32_t)__builtin_bit_cast(unsigned short, h);
+    return (double)(float)h;
+  } else {
+    if (x != x) {  // NaN keeps its encoding (the saturating clamp below would turn it into a number)
+      *bits = 0x7fu;
+      return x;
+    }
+    const float f = fminf(fmaxf(f32_round_odd(x), -448.0f), 448.0f);
+    const uint32_t b = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(f, f, 0, false) & 0xffu;
+    *bits = b;
+    return (double)__builtin_amdgcn_cvt_f32_fp8((int)b, 0);
+  }
+}
+
 // Vq layout: [c * T + t][ld]; term t holds Q(r_t 2^(t S)), r_0 = v,
 // r_{t+1} = r_t - 2^(-t S) Q(r_t 2^(t S)).  (Scaling by a power of two is exact,
-// so the products below equal ldexp.)
+// so the products below equal ldexp.)  Writes column c of agent i.
 template <int VF>
-__device__ __forceinline__ void write_vq_t(const Args& a, void* Vq, long long i, const double* v) {
+__device__ __forceinline__ void write_vq_t(const Args& a, void* Vq, long long i, int c, double v) {
   if constexpr (VF == F_F64) {
     return;
   } else {
     if (Vq == nullptr) return;
     constexpr int T = VSplit<VF>::T, S = VSplit<VF>::S;
+    double r = v;
+    if (fabs(r) > a.vmax && isfinite(r)) *a.rflag = 1u;
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      if (c >= a.m) break;
-      double r = v[c];
-      if (fabs(r) > a.vmax && isfinite(r)) *a.rflag = 1u;
-#pragma unroll
-      for (int t = 0; t < T; ++t) {
-        const long long idx = (long long)(c * T + t) * a.ld + i;
-        const double x = r * __builtin_ldexp(1.0, t * S);
-        double qv;
-        if constexpr (VF == F_F32) {
-          const float f = (a.vsingle && t > 0) ? 0.0f : (float)x;  // pair terms in single: one term
-          ((float*)Vq)[idx] = f;
-          qv = (double)f;
-        } else {
-          constexpr FmtDesc fd = fmt_desc(VF);
-          const uint32_t b = encode_rne(x, fd);
-          if constexpr (VF == F_E4M3) ((uint8_t*)Vq)[idx] = (uint8_t)b;
-          else ((uint16_t*)Vq)[idx] = (uint16_t)b;
-          qv = decode_bits(b, fd);
-        }
-        r = r - qv * __builtin_ldexp(1.0, -t * S);
+    for (int t = 0; t < T; ++t) {
+      const long long idx = (long long)(c * T + t) * a.ld + i;
+      const double x = r * __builtin_ldexp(1.0, t * S);
+      double qv;
+      if constexpr (VF == F_F32) {
+        const float f = (a.vsingle && t > 0) ? 0.0f : (float)x;  // pair terms in single: one term
+        ((float*)Vq)[idx] = f;
+        qv = (double)f;
+      } else {
+        uint32_t b;
+        qv = split_q<VF>(x, &b);
+        if constexpr (VF == F_E4M3) ((uint8_t*)Vq)[idx] = (uint8_t)b;
+        else ((uint16_t*)Vq)[idx] = (uint16_t)b;
       }
+      r = r - qv * __builtin_ldexp(1.0, -t * S);
     }
   }
 }
 
+// columns [c0, c1) of agent i's operand into buffer buf (FP64 copy and split terms)
+// (the row epilogues give the two Kuramoto columns to two lanes of one wave: both
+// take the one sincos, which runs once for the wave, and split one column each)
 template <int VF>
-__device__ __forceinline__ void write_operand_t(const Args& a, int buf, long long i, double y) {
+__device__ __forceinline__ void write_operand_t(const Args& a, int buf, long long i, double y, int c0, int c1) {
   double v[2];
   vec_of(a, y, v);
-  for (int c = 0; c < a.m; ++c) pick2(a.V64, buf)[i * a.m + c] = v[c];
-  write_vq_t<VF>(a, pick2(a.Vq, buf), i, v);
+  for (int c = c0; c < c1; ++c) {
+    const double vc = c ? v[1] : v[0];
+    pick2(a.V64, buf)[i * a.m + c] = vc;
+    write_vq_t<VF>(a, pick2(a.Vq, buf), i, c, vc);
+  }
 }
 
-// the same with the format known only at run time (prep and finalize serve every format)
+// every column, with the format known only at run time (prep and finalize serve every format)
 __device__ __forceinline__ void write_operand(const Args& a, int buf, long long i, double y) {
   switch (a.vfmt) {
-    case F_F32: write_operand_t<F_F32>(a, buf, i, y); break;
-    case F_BF16: write_operand_t<F_BF16>(a, buf, i, y); break;
-    case F_F16: write_operand_t<F_F16>(a, buf, i, y); break;
-    case F_E4M3: write_operand_t<F_E4M3>(a, buf, i, y); break;
-    default: write_operand_t<F_F64>(a, buf, i, y); break;
+    case F_F32: write_operand_t<F_F32>(a, buf, i, y, 0, a.m); break;
+    case F_BF16: write_operand_t<F_BF16>(a, buf, i, y, 0, a.m); break;
+    case F_F16: write_operand_t<F_F16>(a, buf, i, y, 0, a.m); break;
+    case F_E4M3: write_operand_t<F_E4M3>(a, buf, i, y, 0, a.m); break;
+    default: write_operand_t<F_F64>(a, buf, i, y, 0, a.m); break;
   }
 }
 
@@ -394,15 +436,22 @@ __device__ __forceinline__ void load_row(const Args& a, const Ctl* ctl, long lon
   }
 }
 
+// col: the operand column this thread writes (Kuramoto: 0 = sin, 1 = cos, on two
+// threads per row so that the two transcendentals and their splits run side by side);
+// the thread of column 0 also stores the row's stages and its maxima.  col = -1:
+// one thread does all of it.
 template <int VF, bool LEAN = false>
 __device__ __forceinline__ void epilogue(const Args& a, const Ctl* ctl, long long i, const double* P, const RowIn& r, double* r0,
-                         double* r1) {
+                         double* r1, int col) {
   const int d = a.d;
   const long long np = a.np;
   double y[4] = {0.0, 0.0, 0.0, 0.0}, k[4] = {0.0, 0.0, 0.0, 0.0};
   const double ha = ctl->ha;
   *r0 = 0.0;
   *r1 = 0.0;
+  if (col > 0 && a.stage != ST_S2 && a.stage != ST_S3) return;  // no operand to write
+  const bool lead = col <= 0;
+  const int c0 = col < 0 ? 0 : col, c1 = col < 0 ? a.m : col + 1;
   switch (a.stage) {
     case ST_INIT:
     case ST_RHS: {
@@ -436,10 +485,12 @@ __device__ __forceinline__ void epilogue(const Args& a, const Ctl* ctl, long lon
 #pragma unroll
       for (int c = 0; c < 4; ++c) y[c] = sstore(a, r.x[c] + ha * (kA21 * r.k1[c]));
       rhs_eval<LEAN>(a, y, P, r.vs, r.p, r.rs, k);
+      if (lead) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
-        if (c < d) a.K2[c * np + i] = k[c];
-      write_operand_t<VF>(a, 1, i, sstore(a, r.x[0] + ha * (kA32 * k[0])));  // stage-3 input of this agent
+        for (int c = 0; c < 4; ++c)
+          if (c < d) a.K2[c * np + i] = k[c];
+      }
+      write_operand_t<VF>(a, 1, i, sstore(a, r.x[0] + ha * (kA32 * k[0])), c0, c1);  // stage-3 input
       break;
     }
     case ST_S3: {
@@ -450,12 +501,14 @@ __device__ __forceinline__ void epilogue(const Args& a, const Ctl* ctl, long lon
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         if (c >= d) break;
-        a.K3[c * np + i] = k[c];
         const double xn = sstore(a, r.x[c] + ha * (kB1 * r.k1[c] + kB2 * r.k2[c] + kB3 * k[c]));
-        Xn[c * np + i] = xn;
+        if (lead) {
+          a.K3[c * np + i] = k[c];
+          Xn[c * np + i] = xn;
+        }
         y[c] = xn;
       }
-      write_operand_t<VF>(a, 0, i, y[0]);  // the FSAL stage is evaluated at X^{n+1}
+      write_operand_t<VF>(a, 0, i, y[0], c0, c1);  // the FSAL stage is evaluated at X^{n+1}
       break;
     }
     case ST_S4: {
@@ -488,7 +541,7 @@ __device__ __forceinline__ void epilogue(const Args& a, const Ctl* ctl, long lon
 // increasing order, FP64.
 template <int VF, int S>
 __device__ __forceinline__ void epilogue_dp_s(const Args& a, const Ctl* ctl, long long i, const double* P,
-                                              double* r0, double* r1) {
+                                              double* r0, double* r1, int col) {
   // every index below is a compile-time constant, so the stages live in registers
   const int d = a.d;
   const long long np = a.np;
@@ -529,7 +582,7 @@ __device__ __forceinline__ void epilogue_dp_s(const Args& a, const Ctl* ctl, lon
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     if (c >= d) break;
-    Ks[c * np + i] = k[c];
+    if (col <= 0) Ks[c * np + i] = k[c];
     K[S - 1][c] = k[c];
   }
   *r0 = 0.0;
@@ -543,10 +596,13 @@ __device__ __forceinline__ void epilogue_dp_s(const Args& a, const Ctl* ctl, lon
 #pragma unroll
       for (int l = 0; l < S; ++l) acc += kDpA[S][l] * K[l][c];
       yn[c] = x[c] + ha * acc;
-      if constexpr (S == 6) Xn[c * np + i] = yn[c];
+      if constexpr (S == 6) {
+        if (col <= 0) Xn[c * np + i] = yn[c];
+      }
     }
-    write_operand_t<VF>(a, vin_of(ST_D2 + S - 1), i, yn[0]);
+    write_operand_t<VF>(a, vin_of(ST_D2 + S - 1), i, yn[0], col < 0 ? 0 : col, col < 0 ? a.m : col + 1);
   } else {
+    if (col > 0) return;
     const double floor_w = ctl->atol / ctl->rtol;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -562,41 +618,68 @@ __device__ __forceinline__ void epilogue_dp_s(const Args& a, const Ctl* ctl, lon
 }
 
 template <int VF>
-__device__ __forceinline__ void epilogue_dp(const Args& a, const Ctl* ctl, long long i, const double* P, double* r0, double* r1) {
+__device__ __forceinline__ void epilogue_dp(const Args& a, const Ctl* ctl, long long i, const double* P, double* r0,
+                                            double* r1, int col) {
   switch (a.stage) {
-    case ST_D2: epilogue_dp_s<VF, 2>(a, ctl, i, P, r0, r1); break;
-    case ST_D3: epilogue_dp_s<VF, 3>(a, ctl, i, P, r0, r1); break;
-    case ST_D4: epilogue_dp_s<VF, 4>(a, ctl, i, P, r0, r1); break;
-    case ST_D5: epilogue_dp_s<VF, 5>(a, ctl, i, P, r0, r1); break;
-    case ST_D6: epilogue_dp_s<VF, 6>(a, ctl, i, P, r0, r1); break;
-    default: epilogue_dp_s<VF, 7>(a, ctl, i, P, r0, r1); break;
+    case ST_D2: epilogue_dp_s<VF, 2>(a, ctl, i, P, r0, r1, col); break;
+    case ST_D3: epilogue_dp_s<VF, 3>(a, ctl, i, P, r0, r1, col); break;
+    case ST_D4: epilogue_dp_s<VF, 4>(a, ctl, i, P, r0, r1, col); break;
+    case ST_D5: epilogue_dp_s<VF, 5>(a, ctl, i, P, r0, r1, col); break;
+    case ST_D6: epilogue_dp_s<VF, 6>(a, ctl, i, P, r0, r1, col); break;
+    default: epilogue_dp_s<VF, 7>(a, ctl, i, P, r0, r1, col); break;
   }
 }
 
-// the row this thread finishes (at most one: every tile has fewer rows than threads)
-__device__ __forceinline__ long long tail_row(const Args& a, int rb, int RB) {
-  return threadIdx.x < RB ? (long long)rb * RB + threadIdx.x : -1;
+// Lanes per row of the row epilogues: the 16-bit and e4m3 formats split each operand
+// column into terms by rounding, so the two Kuramoto columns get a lane each; the
+// FP32 and FP64 operands take one lane per row.
+template <int VF>
+__device__ __forceinline__ int tail_lanes(const Args& a) {
+  return (VF == F_BF16 || VF == F_F16 || VF == F_E4M3) ? a.m : 1;
+}
+
+// The row this thread finishes.  Tail threads start at thread tbase (the epilogue
+// wave of a single-system kernel, or thread 0); with nl lanes per row, tail threads
+// RB c .. RB c + RB - 1 take the block's rows for operand column c (every tile has
+// at least 2 RB tail threads).
+__device__ __forceinline__ long long tail_row(const Args& a, int rb, int RB, int tbase, int nl) {
+  const int tt = (int)threadIdx.x - tbase;
+  return (tt >= 0 && tt < RB * nl) ? (long long)rb * RB + tt % RB : -1;
 }
 
 // common tail of every contraction kernel: row epilogues and the block maxima (DP: the
 // kernel also serves Dormand-Prince attempts; the grouped ensemble kernels do not, and
 // leave that code out)
+// (tbase > 0: every tail thread is in the last wave, the epilogue wave)
 template <int M, int VF, bool DP = true>
-__device__ __forceinline__ void contract_tail(const Args& a, int rb, double (*sP)[M], int RB, const RowIn& rin) {
+__device__ __forceinline__ void contract_tail(const Args& a, int rb, double (*sP)[M], int RB, const RowIn& rin,
+                                              int tbase = 0) {
   __shared__ double sRed0[16], sRed1[16];
   const Ctl* ctl = a.ctl;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const long long i = tail_row(a, rb, RB);
+  const int nl = tail_lanes<VF>(a);
+  const long long i = tail_row(a, rb, RB, tbase, nl);
+  const int tt = tid - tbase, col = nl > 1 ? tt / RB : -1;
   double r0 = 0.0, r1 = 0.0;
   if (i >= 0 && i < a.n) {
     if constexpr (DP) {
-      if (a.stage >= ST_D2) epilogue_dp<VF>(a, ctl, i, sP[tid], &r0, &r1);
-      else epilogue<VF>(a, ctl, i, sP[tid], rin, &r0, &r1);
+      if (a.stage >= ST_D2) epilogue_dp<VF>(a, ctl, i, sP[tt % RB], &r0, &r1, col);
+      else epilogue<VF>(a, ctl, i, sP[tt % RB], rin, &r0, &r1, col);
     } else {  // the grouped ensemble kernels
-      epilogue<VF, true>(a, ctl, i, sP[tid], rin, &r0, &r1);
+      epilogue<VF, true>(a, ctl, i, sP[tt % RB], rin, &r0, &r1, col);
     }
   }
   if (a.stage == ST_S2 || a.stage == ST_S3 || a.stage == ST_RHS || (a.stage >= ST_D2 && a.stage < ST_D7)) return;
+  if (tbase > 0) {  // one wave holds every row: its maximum is the block's
+    if (tid < tbase) return;
+    r0 = wave_nanmax(r0);
+    r1 = wave_nanmax(r1);
+    if (tt == 0) {
+      a.ep0[rb] = r0;
+      a.ep1[rb] = r1;
+    }
+    return;
+  }
   r0 = wave_nanmax(r0);
   r1 = wave_nanmax(r1);
   const int lane = tid & 63, wave = tid >> 6, nw = (nthr + 63) >> 6;
@@ -617,8 +700,9 @@ __device__ __forceinline__ void contract_tail(const Args& a, int rb, double (*sP
 }
 
 // loads the tail row's inputs (issued before the contraction loop)
-__device__ __forceinline__ void prefetch_row(const Args& a, int rb, int RB, RowIn& rin) {
-  const long long i = tail_row(a, rb, RB);
+template <int VF>
+__device__ __forceinline__ void prefetch_row(const Args& a, int rb, int RB, RowIn& rin, int tbase = 0) {
+  const long long i = tail_row(a, rb, RB, tbase, tail_lanes<VF>(a));
   if (i >= 0 && i < a.n) load_row(a, a.ctl, i, rin);
 }
 
@@ -626,80 +710,89 @@ __device__ __forceinline__ void prefetch_row(const Args& a, int rb, int RB, RowI
 // FP64 contraction on the vector ALUs.  Wave (wr, wk) owns R rows and the k-slice
 // [wk KW, (wk+1) KW); lanes stride the row with 16-byte loads (2 doubles) and keep
 // U chunks of 128 columns in flight.  The WK slice sums are added in slice order.
+// EW (single systems): one more wave, the epilogue wave, loads the rows' epilogue
+// inputs while the others stream A and then finishes the rows.  Loads of one wave
+// complete in order, so a streaming wave that requested those inputs itself would
+// hold up its own stream behind their address dependence on the control state.
 // ---------------------------------------------------------------------------
-template <int M, int R, int WR, int WK, int U, bool NT, bool DP = true>
+template <int M, int R, int WR, int WK, int U, bool NT, bool DP = true, bool EW = false>
 __device__ __forceinline__ void contract_f64(const Args& a, int rb) {
   constexpr int RB = R * WR;
+  constexpr int TB = EW ? WR * WK * 64 : 0;  // first tail thread
   __shared__ double sPart[WK][RB][M];
   __shared__ double sP[RB][M];
   if (a.ctl->status != kRunning) return;
   RowIn rin;
-  prefetch_row(a, rb, RB, rin);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wr = w % WR, wk = w / WR;
-  const long long row0 = (long long)rb * RB + wr * R;
-  const double* __restrict__ Ab = (const double*)a.A + row0 * a.ld;
-  const double* __restrict__ V = pick2(a.V64, vin_of(a.stage));
-  const long long jb = (long long)wk * a.KW;
-  const long long je = min(jb + (long long)a.KW, a.ld);
-  double acc[R][M];
+  if (EW && w == WR * WK) {
+    prefetch_row<F_F64>(a, rb, RB, rin, TB);
+  } else {
+    if constexpr (!EW) prefetch_row<F_F64>(a, rb, RB, rin);
+    const int wr = w % WR, wk = w / WR;
+    const long long row0 = (long long)rb * RB + wr * R;
+    const double* __restrict__ Ab = (const double*)a.A + row0 * a.ld;
+    const double* __restrict__ V = pick2(a.V64, vin_of(a.stage));
+    const long long jb = (long long)wk * a.KW;
+    const long long je = min(jb + (long long)a.KW, a.ld);
+    double acc[R][M];
 #pragma unroll
-  for (int r = 0; r < R; ++r)
+    for (int r = 0; r < R; ++r)
 #pragma unroll
-    for (int c = 0; c < M; ++c) acc[r][c] = 0.0;
-  long long j0 = jb;
-  for (; j0 + 128 * U <= je; j0 += 128 * U) {
-    f64x2 av[U][R];
-    f64x2 vv[U][M];
+      for (int c = 0; c < M; ++c) acc[r][c] = 0.0;
+    long long j0 = jb;
+    for (; j0 + 128 * U <= je; j0 += 128 * U) {
+      f64x2 av[U][R];
+      f64x2 vv[U][M];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const long long j = j0 + 128 * u + 2 * lane;
+      for (int u = 0; u < U; ++u) {
+        const long long j = j0 + 128 * u + 2 * lane;
 #pragma unroll
-      for (int r = 0; r < R; ++r) av[u][r] = ldA<NT>((const f64x2*)(Ab + r * a.ld + j));
+        for (int r = 0; r < R; ++r) av[u][r] = ldA<NT>((const f64x2*)(Ab + r * a.ld + j));
 #pragma unroll
-      for (int c = 0; c < M; ++c) vv[u][c] = *(const f64x2*)(V + j * M + 2 * c);
+        for (int c = 0; c < M; ++c) vv[u][c] = *(const f64x2*)(V + j * M + 2 * c);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (M == 1) {
+            acc[r][0] = fma(av[u][r].x, vv[u][0].x, acc[r][0]);
+            acc[r][0] = fma(av[u][r].y, vv[u][0].y, acc[r][0]);
+          } else {
+            // vv[u][0] = (V[j][0], V[j][1]), vv[u][1] = (V[j+1][0], V[j+1][1])
+            acc[r][0] = fma(av[u][r].x, vv[u][0].x, acc[r][0]);
+            acc[r][M - 1] = fma(av[u][r].x, vv[u][0].y, acc[r][M - 1]);
+            acc[r][0] = fma(av[u][r].y, vv[u][M - 1].x, acc[r][0]);
+            acc[r][M - 1] = fma(av[u][r].y, vv[u][M - 1].y, acc[r][M - 1]);
+          }
+        }
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
+    for (; j0 < je; j0 += 128) {
+      const long long j = j0 + 2 * lane;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
+        const f64x2 x = ldA<NT>((const f64x2*)(Ab + r * a.ld + j));
+        const f64x2 v0 = *(const f64x2*)(V + j * M);
         if (M == 1) {
-          acc[r][0] = fma(av[u][r].x, vv[u][0].x, acc[r][0]);
-          acc[r][0] = fma(av[u][r].y, vv[u][0].y, acc[r][0]);
+          acc[r][0] = fma(x.x, v0.x, acc[r][0]);
+          acc[r][0] = fma(x.y, v0.y, acc[r][0]);
         } else {
-          // vv[u][0] = (V[j][0], V[j][1]), vv[u][1] = (V[j+1][0], V[j+1][1])
-          acc[r][0] = fma(av[u][r].x, vv[u][0].x, acc[r][0]);
-          acc[r][M - 1] = fma(av[u][r].x, vv[u][0].y, acc[r][M - 1]);
-          acc[r][0] = fma(av[u][r].y, vv[u][M - 1].x, acc[r][0]);
-          acc[r][M - 1] = fma(av[u][r].y, vv[u][M - 1].y, acc[r][M - 1]);
+          const f64x2 v1 = *(const f64x2*)(V + j * M + 2);
+          acc[r][0] = fma(x.x, v0.x, acc[r][0]);
+          acc[r][M - 1] = fma(x.x, v0.y, acc[r][M - 1]);
+          acc[r][0] = fma(x.y, v1.x, acc[r][0]);
+          acc[r][M - 1] = fma(x.y, v1.y, acc[r][M - 1]);
         }
       }
-  }
-  for (; j0 < je; j0 += 128) {
-    const long long j = j0 + 2 * lane;
+    }
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const f64x2 x = ldA<NT>((const f64x2*)(Ab + r * a.ld + j));
-      const f64x2 v0 = *(const f64x2*)(V + j * M);
-      if (M == 1) {
-        acc[r][0] = fma(x.x, v0.x, acc[r][0]);
-        acc[r][0] = fma(x.y, v0.y, acc[r][0]);
-      } else {
-        const f64x2 v1 = *(const f64x2*)(V + j * M + 2);
-        acc[r][0] = fma(x.x, v0.x, acc[r][0]);
-        acc[r][M - 1] = fma(x.x, v0.y, acc[r][M - 1]);
-        acc[r][0] = fma(x.y, v1.x, acc[r][0]);
-        acc[r][M - 1] = fma(x.y, v1.y, acc[r][M - 1]);
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        const double s = wave_sum(acc[r][c]);
+        if (lane == 0) sPart[wk][wr * R + r][c] = s;
       }
-    }
   }
-#pragma unroll
-  for (int r = 0; r < R; ++r)
-#pragma unroll
-    for (int c = 0; c < M; ++c) {
-      const double s = wave_sum(acc[r][c]);
-      if (lane == 0) sPart[wk][wr * R + r][c] = s;
-    }
   __syncthreads();
   for (int e = threadIdx.x; e < RB * M; e += blockDim.x) {
     double s = 0.0;
@@ -707,7 +800,7 @@ __device__ __forceinline__ void contract_f64(const Args& a, int rb) {
     sP[e / M][e % M] = s;
   }
   __syncthreads();
-  contract_tail<M, F_F64, DP>(a, rb, sP, RB, rin);
+  contract_tail<M, F_F64, DP>(a, rb, sP, RB, rin, TB);
 }
 
 // ---------------------------------------------------------------------------
@@ -715,71 +808,76 @@ __device__ __forceinline__ void contract_f64(const Args& a, int rb) {
 // T FP32 terms; each lane forms 4-element FP32 dot products per term and adds
 // them to FP64 accumulators (FP32 within a chunk, FP64 across chunks).
 // ---------------------------------------------------------------------------
-template <int M, int T, int R, int WR, int WK, int U, bool NT, bool DP = true>
+template <int M, int T, int R, int WR, int WK, int U, bool NT, bool DP = true, bool EW = false>
 __device__ __forceinline__ void contract_f32(const Args& a, int rb) {
   constexpr int RB = R * WR;
   constexpr int NC = M * T;
+  constexpr int TB = EW ? WR * WK * 64 : 0;  // first tail thread (EW: the epilogue wave, see contract_f64)
   __shared__ double sPart[WK][RB][NC];
   __shared__ double sP[RB][M];
   if (a.ctl->status != kRunning) return;
   RowIn rin;
-  prefetch_row(a, rb, RB, rin);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wr = w % WR, wk = w / WR;
-  const long long row0 = (long long)rb * RB + wr * R;
-  const float* __restrict__ Ab = (const float*)a.A + row0 * a.ld;
-  const float* __restrict__ Vq = (const float*)pick2(a.Vq, vin_of(a.stage));
-  const long long jb = (long long)wk * a.KW;
-  const long long je = min(jb + (long long)a.KW, a.ld);
-  double acc[R][NC];
-  float accf[R][NC];  // the recipes' single sum
+  if (EW && w == WR * WK) {
+    prefetch_row<F_F32>(a, rb, RB, rin, TB);
+  } else {
+    if constexpr (!EW) prefetch_row<F_F32>(a, rb, RB, rin);
+    const int wr = w % WR, wk = w / WR;
+    const long long row0 = (long long)rb * RB + wr * R;
+    const float* __restrict__ Ab = (const float*)a.A + row0 * a.ld;
+    const float* __restrict__ Vq = (const float*)pick2(a.Vq, vin_of(a.stage));
+    const long long jb = (long long)wk * a.KW;
+    const long long je = min(jb + (long long)a.KW, a.ld);
+    double acc[R][NC];
+    float accf[R][NC];  // the recipes' single sum
 #pragma unroll
-  for (int r = 0; r < R; ++r)
+    for (int r = 0; r < R; ++r)
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      acc[r][c] = 0.0;
-      accf[r][c] = 0.0f;
-    }
-  long long j0 = jb;
-  for (; j0 < je; j0 += 256 * U) {
-    const int uu = (int)min((long long)U, (je - j0) / 256);
-    f32x4 av[U][R];
-    f32x4 vv[U][NC];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (u < uu) {
-        const long long j = j0 + 256 * u + 4 * lane;
-#pragma unroll
-        for (int r = 0; r < R; ++r) av[u][r] = ldA<NT>((const f32x4*)(Ab + r * a.ld + j));
-#pragma unroll
-        for (int c = 0; c < NC; ++c) vv[u][c] = *(const f32x4*)(Vq + c * a.ld + j);
+      for (int c = 0; c < NC; ++c) {
+        acc[r][c] = 0.0;
+        accf[r][c] = 0.0f;
       }
+    long long j0 = jb;
+    for (; j0 < je; j0 += 256 * U) {
+      const int uu = (int)min((long long)U, (je - j0) / 256);
+      f32x4 av[U][R];
+      f32x4 vv[U][NC];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (u < uu) {
+          const long long j = j0 + 256 * u + 4 * lane;
+#pragma unroll
+          for (int r = 0; r < R; ++r) av[u][r] = ldA<NT>((const f32x4*)(Ab + r * a.ld + j));
+#pragma unroll
+          for (int c = 0; c < NC; ++c) vv[u][c] = *(const f32x4*)(Vq + c * a.ld + j);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          float s = 0.0f;
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            if (u < uu) {
+              s = fmaf(av[u][r].x, vv[u][c].x, s);
+              s = fmaf(av[u][r].y, vv[u][c].y, s);
+              s = fmaf(av[u][r].z, vv[u][c].z, s);
+              s = fmaf(av[u][r].w, vv[u][c].w, s);
+            }
+          }
+          if (a.sum32) accf[r][c] += s;
+          else acc[r][c] += (double)s;
+        }
     }
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        float s = 0.0f;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          if (u < uu) {
-            s = fmaf(av[u][r].x, vv[u][c].x, s);
-            s = fmaf(av[u][r].y, vv[u][c].y, s);
-            s = fmaf(av[u][r].z, vv[u][c].z, s);
-            s = fmaf(av[u][r].w, vv[u][c].w, s);
-          }
-        }
-        if (a.sum32) accf[r][c] += s;
-        else acc[r][c] += (double)s;
+        const double s = a.sum32 ? (double)wave_sum_f32(accf[r][c]) : wave_sum(acc[r][c]);
+        if (lane == 0) sPart[wk][wr * R + r][c] = s;
       }
   }
-#pragma unroll
-  for (int r = 0; r < R; ++r)
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const double s = a.sum32 ? (double)wave_sum_f32(accf[r][c]) : wave_sum(acc[r][c]);
-      if (lane == 0) sPart[wk][wr * R + r][c] = s;
-    }
   __syncthreads();
   for (int e = threadIdx.x; e < RB * M; e += blockDim.x) {
     const int row = e / M, cc = e % M;
@@ -798,7 +896,7 @@ __device__ __forceinline__ void contract_f32(const Args& a, int rb) {
     sP[row][cc] = a.scale * p;
   }
   __syncthreads();
-  contract_tail<M, F_F32, DP>(a, rb, sP, RB, rin);
+  contract_tail<M, F_F32, DP>(a, rb, sP, RB, rin, TB);
 }
 
 // ---------------------------------------------------------------------------
@@ -847,13 +945,14 @@ __device__ __forceinline__ f32x4 mma(u32x4 av, u32x4 bv, f32x4 c) {
   }
 }
 
-template <int FMT, int M, int T, int RT, int WR, int WK, int U, bool NT, bool DP = true>
+template <int FMT, int M, int T, int RT, int WR, int WK, int U, bool NT, bool DP = true, bool EW = false>
 __device__ __forceinline__ void contract_mfma(const Args& a, int rb) {
   constexpr int NC = M * T;
   static_assert(NC <= 16, "vector terms exceed the MFMA tile width");
   constexpr int RB = 16 * RT * WR;
+  static_assert(!EW || 2 * RB <= 64, "the epilogue wave holds every row of the block");
+  constexpr int TB = EW ? WR * WK * 64 : 0;  // first tail thread (EW: the epilogue wave, see contract_f64)
   constexpr int ES = (FMT == F_E4M3) ? 1 : (FMT == F_F32) ? 4 : 2;  // bytes per element
-  constexpr int KB = 64 / ES;  // k elements per 16-byte lane load x 4 lane groups
   constexpr int KC = 8;                        // k-groups kept in FP32 before an FP64 flush
   static_assert(U == 2 || U == 4 || U == 8, "staged batches of 2, 4 or 8 steps");
   constexpr int RPI = 16 / U;                  // rows per staged load instruction
@@ -865,111 +964,117 @@ __device__ __forceinline__ void contract_mfma(const Args& a, int rb) {
   __shared__ double sP[RB][M];
   __shared__ __attribute__((aligned(16))) unsigned char sA[STAGE ? WR * WK : 1][STAGE ? RT * 16 * SROW : 16];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wr = w % WR, wk = w / WR;
-  const int r16 = lane & 15, g = lane >> 4;
-  const long long row_base = (long long)rb * RB + wr * 16 * RT;
-  const long long kb = (long long)wk * a.KW;
-  const long long ke = min(kb + (long long)a.KW, a.ld);
-  const char* Ab = (const char*)a.A;
-  const bool bcol = r16 < NC;
-  const char* bp = (const char*)pick2(a.Vq, vin_of(a.stage)) + ((long long)(bcol ? r16 : 0) * a.ld + kb) * ES + g * 16;
-  // staged path: instruction q reads rows q*RPI + srow of the wave's 16*RT, bytes scol..scol+15
-  unsigned char* const slab = sA[w];
-  const int srow = lane / LPR, scol = (lane % LPR) * 16;
-  const char* const sp = Ab + ((row_base + srow) * a.ld + kb) * ES + scol;
-  const long long qstride = (long long)RPI * a.ld * ES;
-  f32x4 c[RT];
-  double dacc[RT][4];
+  RowIn rin;
+  if (EW && w == WR * WK) {
+    if (a.ctl->status != kRunning) return;
+    prefetch_row<FMT>(a, rb, RB, rin, TB);
+  } else {
+    const int wr = w % WR, wk = w / WR;
+    const int r16 = lane & 15, g = lane >> 4;
+    const long long row_base = (long long)rb * RB + wr * 16 * RT;
+    const long long kb = (long long)wk * a.KW;
+    const long long ke = min(kb + (long long)a.KW, a.ld);
+    const char* Ab = (const char*)a.A;
+    const bool bcol = r16 < NC;
+    const char* bp = (const char*)pick2(a.Vq, vin_of(a.stage)) + ((long long)(bcol ? r16 : 0) * a.ld + kb) * ES + g * 16;
+    // staged path: instruction q reads rows q*RPI + srow of the wave's 16*RT, bytes scol..scol+15
+    unsigned char* const slab = sA[STAGE ? w : 0];
+    const int srow = lane / LPR, scol = (lane % LPR) * 16;
+    const char* const sp = Ab + ((row_base + srow) * a.ld + kb) * ES + scol;
+    const long long qstride = (long long)RPI * a.ld * ES;
+    f32x4 c[RT];
+    double dacc[RT][4];
 #pragma unroll
-  for (int t = 0; t < RT; ++t) {
-    c[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int i = 0; i < 4; ++i) dacc[t][i] = 0.0;
-  }
-  const u32x4 zero = {0u, 0u, 0u, 0u};
-  int kc = 0;
-  long long off = 0;  // byte offset from the slice start
-  const long long span = (ke > kb) ? (ke - kb) * ES : 0;
-  // Software pipeline over batches of U 64-byte steps: the loads of the next batch
-  // are in flight while the matrix cores consume the current one (two register
-  // buffers, ping-pong).  Same products, same order as a plain loop.
-  constexpr long long BATCH = 64LL * U;
-  const long long full = span / BATCH * BATCH;
-  u32x4 a0[NQ], b0[U], a1[NQ], b1[U];
-  auto load = [&](u32x4 (&xa)[NQ], u32x4 (&xb)[U], long long o) {
-    if constexpr (STAGE) {
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) xa[q] = ldA<NT>((const u32x4*)(sp + q * qstride + o));
-    } else {  // operand layout straight from HBM: element u*RT + t is step u of row tile t
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int t = 0; t < RT; ++t)
-          xa[u * RT + t] =
-              ldA<NT>((const u32x4*)(Ab + ((row_base + 16 * t + r16) * a.ld + kb) * ES + g * 16 + o + 64 * u));
+    for (int t = 0; t < RT; ++t) {
+      c[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int i = 0; i < 4; ++i) dacc[t][i] = 0.0;
     }
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+    int kc = 0;
+    long long off = 0;  // byte offset from the slice start
+    const long long span = (ke > kb) ? (ke - kb) * ES : 0;
+    // Software pipeline over batches of U 64-byte steps: the loads of the next batch
+    // are in flight while the matrix cores consume the current one (two register
+    // buffers, ping-pong).  Same products, same order as a plain loop.
+    constexpr long long BATCH = 64LL * U;
+    const long long full = span / BATCH * BATCH;
+    u32x4 a0[NQ], b0[U], a1[NQ], b1[U];
+    auto load = [&](u32x4 (&xa)[NQ], u32x4 (&xb)[U], long long o) {
+      if constexpr (STAGE) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) xb[u] = bcol ? *(const u32x4*)(bp + o + 64 * u) : zero;
-  };
-  auto step = [&](const u32x4 (&xa)[NQ], const u32x4 (&xb)[U]) {
-    if constexpr (STAGE) {
+        for (int q = 0; q < NQ; ++q) xa[q] = ldA<NT>((const u32x4*)(sp + q * qstride + o));
+      } else {  // operand layout straight from HBM: element u*RT + t is step u of row tile t
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) *(u32x4*)(slab + (q * RPI + srow) * SROW + scol) = xa[q];
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int u = 0; u < U; ++u)
+          for (int t = 0; t < RT; ++t)
+            xa[u * RT + t] =
+                ldA<NT>((const u32x4*)(Ab + ((row_base + 16 * t + r16) * a.ld + kb) * ES + g * 16 + o + 64 * u));
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) xb[u] = bcol ? *(const u32x4*)(bp + o + 64 * u) : zero;
+    };
+    auto step = [&](const u32x4 (&xa)[NQ], const u32x4 (&xb)[U]) {
+      if constexpr (STAGE) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) *(u32x4*)(slab + (q * RPI + srow) * SROW + scol) = xa[q];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int t = 0; t < RT; ++t) {
+            const u32x4 av = *(const u32x4*)(slab + (16 * t + r16) * SROW + 64 * u + 16 * g);
+            c[t] = mma<FMT>(av, xb[u], c[t]);
+          }
+      } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int t = 0; t < RT; ++t) c[t] = mma<FMT>(xa[u * RT + t], xb[u], c[t]);
+      }
+      kc += U;
+      if (kc >= KC && !a.sum32) {  // FP64 flush (the recipes' single sum keeps FP32 throughout)
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
-          const u32x4 av = *(const u32x4*)(slab + (16 * t + r16) * SROW + 64 * u + 16 * g);
-          c[t] = mma<FMT>(av, xb[u], c[t]);
+          for (int i = 0; i < 4; ++i) dacc[t][i] += (double)c[t][i];
+          c[t] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
-    } else {
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int t = 0; t < RT; ++t) c[t] = mma<FMT>(xa[u * RT + t], xb[u], c[t]);
-    }
-    kc += U;
-    if (kc >= KC && !a.sum32) {  // FP64 flush (the recipes' single sum keeps FP32 throughout)
-#pragma unroll
-      for (int t = 0; t < RT; ++t) {
-        for (int i = 0; i < 4; ++i) dacc[t][i] += (double)c[t][i];
-        c[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        kc = 0;
       }
-      kc = 0;
+    };
+    // The first batch is in flight while the control state arrives; a finished solve
+    // streams nothing more (the host enqueues attempts ahead of its checks, and those
+    // of a finished solve must cost no more than their launch).
+    if (full > 0) load(a0, b0, 0);
+    if (a.ctl->status != kRunning) return;
+    if constexpr (!EW) prefetch_row<FMT>(a, rb, RB, rin);
+    while (off < full) {
+      if (off + BATCH < full) load(a1, b1, off + BATCH);
+      step(a0, b0);
+      off += BATCH;
+      if (off >= full) break;
+      if (off + BATCH < full) load(a0, b0, off + BATCH);
+      step(a1, b1);
+      off += BATCH;
     }
-  };
-  if (full > 0) load(a0, b0, 0);
-  // the first batch is in flight while the control state arrives
-  if (a.ctl->status != kRunning) return;
-  RowIn rin;
-  prefetch_row(a, rb, RB, rin);
-  while (off < full) {
-    if (off + BATCH < full) load(a1, b1, off + BATCH);
-    step(a0, b0);
-    off += BATCH;
-    if (off >= full) break;
-    if (off + BATCH < full) load(a0, b0, off + BATCH);
-    step(a1, b1);
-    off += BATCH;
-  }
-  // steps left over after the last whole batch: operand layout straight from HBM
-  for (; off < span; off += 64) {
-    u32x4 av[RT];
+    // steps left over after the last whole batch: operand layout straight from HBM
+    for (; off < span; off += 64) {
+      u32x4 av[RT];
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+        av[t] = ldA<NT>((const u32x4*)(Ab + ((row_base + 16 * t + r16) * a.ld + kb) * ES + g * 16 + off));
+      const u32x4 bv = bcol ? *(const u32x4*)(bp + off) : zero;
+#pragma unroll
+      for (int t = 0; t < RT; ++t) c[t] = mma<FMT>(av[t], bv, c[t]);
+    }
 #pragma unroll
     for (int t = 0; t < RT; ++t)
-      av[t] = ldA<NT>((const u32x4*)(Ab + ((row_base + 16 * t + r16) * a.ld + kb) * ES + g * 16 + off));
-    const u32x4 bv = bcol ? *(const u32x4*)(bp + off) : zero;
+      for (int i = 0; i < 4; ++i) dacc[t][i] += (double)c[t][i];
+    // C layout: lane l holds rows 4 (l/16) + i of column l%16
+    if (bcol) {
 #pragma unroll
-    for (int t = 0; t < RT; ++t) c[t] = mma<FMT>(av[t], bv, c[t]);
-  }
-#pragma unroll
-  for (int t = 0; t < RT; ++t)
-    for (int i = 0; i < 4; ++i) dacc[t][i] += (double)c[t][i];
-  (void)KB;
-  // C layout: lane l holds rows 4 (l/16) + i of column l%16
-  if (bcol) {
-#pragma unroll
-    for (int t = 0; t < RT; ++t)
-      for (int i = 0; i < 4; ++i) sPart[wk][wr * 16 * RT + 16 * t + 4 * g + i][r16] = dacc[t][i];
+      for (int t = 0; t < RT; ++t)
+        for (int i = 0; i < 4; ++i) sPart[wk][wr * 16 * RT + 16 * t + 4 * g + i][r16] = dacc[t][i];
+    }
   }
   __syncthreads();
   for (int e = threadIdx.x; e < RB * M; e += blockDim.x) {
@@ -989,7 +1094,7 @@ __device__ __forceinline__ void contract_mfma(const Args& a, int rb) {
     sP[row][cc] = a.scale * p;
   }
   __syncthreads();
-  contract_tail<M, FMT, DP>(a, rb, sP, RB, rin);
+  contract_tail<M, FMT, DP>(a, rb, sP, RB, rin, TB);
 }
 
 // ---------------------------------------------------------------------------
@@ -1019,7 +1124,7 @@ __device__ __forceinline__ void contract_pair(const Args& a, int rb) {
   __shared__ double sP[RB][1];
   if (a.ctl->status != kRunning) return;
   RowIn rin;
-  prefetch_row(a, rb, RB, rin);
+  prefetch_row<F_F64>(a, rb, RB, rin);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const long long row0 = (long long)rb * RB + (long long)w * R;
   const double* __restrict__ V = pick2(a.V64, vin_of(a.stage));
@@ -1098,25 +1203,27 @@ __device__ __forceinline__ const Args& group_args(const Group& g, const Item& w)
     __syncthreads();                                                \
   }
 
-template <int M, int R, int WR, int WK, int U, bool NT>
-__global__ __launch_bounds__(WR* WK * 64) void k_contract_f64(Args a) {
-  contract_f64<M, R, WR, WK, U, NT>(a, block_row(a));
+// EW: a single-system kernel with one more wave than the tile's streaming waves,
+// the epilogue wave (see contract_f64); the autotuner tries both forms
+template <int M, int R, int WR, int WK, int U, bool NT, bool EW>
+__global__ __launch_bounds__(WR* WK * 64 + (EW ? 64 : 0)) void k_contract_f64(Args a) {
+  contract_f64<M, R, WR, WK, U, NT, true, EW>(a, block_row(a));
 }
 template <int M, int R, int WR, int WK, int U, bool NT>
 __global__ __launch_bounds__(WR* WK * 64) void k_group_f64(Group g) {
   BS32_GROUP_LOOP((contract_f64<M, R, WR, WK, U, NT, false>))
 }
-template <int M, int T, int R, int WR, int WK, int U, bool NT>
-__global__ __launch_bounds__(WR* WK * 64) void k_contract_f32(Args a) {
-  contract_f32<M, T, R, WR, WK, U, NT>(a, block_row(a));
+template <int M, int T, int R, int WR, int WK, int U, bool NT, bool EW>
+__global__ __launch_bounds__(WR* WK * 64 + (EW ? 64 : 0)) void k_contract_f32(Args a) {
+  contract_f32<M, T, R, WR, WK, U, NT, true, EW>(a, block_row(a));
 }
 template <int M, int T, int R, int WR, int WK, int U, bool NT>
 __global__ __launch_bounds__(WR* WK * 64) void k_group_f32(Group g) {
   BS32_GROUP_LOOP((contract_f32<M, T, R, WR, WK, U, NT, false>))
 }
-template <int FMT, int M, int T, int RT, int WR, int WK, int U, bool NT>
-__global__ __launch_bounds__(WR* WK * 64) void k_contract_mfma(Args a) {
-  contract_mfma<FMT, M, T, RT, WR, WK, U, NT>(a, block_row(a));
+template <int FMT, int M, int T, int RT, int WR, int WK, int U, bool NT, bool EW>
+__global__ __launch_bounds__(WR* WK * 64 + (EW ? 64 : 0)) void k_contract_mfma(Args a) {
+  contract_mfma<FMT, M, T, RT, WR, WK, U, NT, true, EW>(a, block_row(a));
 }
 template <int FMT, int M, int T, int RT, int WR, int WK, int U, bool NT>
 __global__ __launch_bounds__(WR* WK * 64, 2) void k_group_mfma(Group g) {
@@ -1412,7 +1519,7 @@ __global__ __launch_bounds__(256) void k_shared_contract(Shared sh) {
           for (int tt = 0; tt < T; ++tt) p += ldexp((double)sP[row * PP + ib * C + mm * T + tt], -tt * sh.vshift);
           P[mm] = sh.scale * p;
         }
-        epilogue<sh_opfmt<FMT>(), true>(a, ctl, i, P, rin, &r0, &r1);
+        epilogue<sh_opfmt<FMT>(), true>(a, ctl, i, P, rin, &r0, &r1, -1);
       }
     }
     if (!reduce) continue;
@@ -1888,9 +1995,13 @@ int tile_kalign(int fmt, const Tile& t) {
 #if BS32_IN(0)
 #define BS32_TILE_VALU(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 0},
 #define BS32_TILE_MMA(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 1},
-static const Tile kF64Tiles[] = {BS32_F64_TILES(BS32_TILE_VALU)};
-static const Tile kF32Tiles[] = {BS32_F32_TILES(BS32_TILE_VALU) BS32_MMA_TILES(BS32_TILE_MMA)};
-static const Tile kMmaTiles[] = {BS32_MMA_TILES(BS32_TILE_MMA)};
+#define BS32_TILE_VALU_EW(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 0, 1},
+#define BS32_TILE_MMA_EW(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 1, 1},
+// every tile, then (single systems only) the same tiles with an epilogue wave
+static const Tile kF64Tiles[] = {BS32_F64_TILES(BS32_TILE_VALU) BS32_F64_TILES(BS32_TILE_VALU_EW)};
+static const Tile kF32Tiles[] = {BS32_F32_TILES(BS32_TILE_VALU) BS32_MMA_TILES(BS32_TILE_MMA)
+                                     BS32_F32_TILES(BS32_TILE_VALU_EW) BS32_MMA_TILES(BS32_TILE_MMA_EW)};
+static const Tile kMmaTiles[] = {BS32_MMA_TILES(BS32_TILE_MMA) BS32_MMA_TILES(BS32_TILE_MMA_EW)};
 #define BS32_TILE_PAIR(R_, WV_, UJ_) Tile{R_, WV_, 1, UJ_, 0, 2},
 static const Tile kPairTiles[] = {BS32_PAIR_TILES(BS32_TILE_PAIR)};
 #undef BS32_TILE_PAIR
@@ -1900,6 +2011,8 @@ static const Tile kSharedTiles[] = {BS32_SHARED_TILES(BS32_TILE_SHARED) Tile{1, 
 #undef BS32_TILE_SHARED
 #undef BS32_TILE_VALU
 #undef BS32_TILE_MMA
+#undef BS32_TILE_VALU_EW
+#undef BS32_TILE_MMA_EW
 
 const Tile* pair_tile_candidates(int* count) {
   *count = (int)(sizeof(kPairTiles) / sizeof(Tile));
@@ -2000,11 +2113,15 @@ hipError_t launch_shared_contract(const Shared& sh, int m, int fmt, const Tile& 
   return dispatch_shared(&sh, m, fmt, t, s);
 }
 #endif
-#define BS32_LAUNCH(SINGLE, GROUP, THREADS)                                      \
-  if (!L.dry) {                                                                  \
-    if (L.g) GROUP<<<L.ggrid, THREADS, 0, L.s>>>(*L.g);                          \
-    else SINGLE<<<(unsigned)L.a->nrb, THREADS, 0, L.s>>>(*L.a);                  \
-  }                                                                              \
+// THREADS: the tile's streaming waves; a single-system kernel with an epilogue wave
+// (tile EW) has one more, and the grouped kernels have none
+#define BS32_LAUNCH(SINGLE_EW, SINGLE, GROUP, THREADS)                                           \
+  if (L.g && t.EW) return hipErrorInvalidValue;                                                  \
+  if (!L.dry) {                                                                                  \
+    if (L.g) GROUP<<<L.ggrid, THREADS, 0, L.s>>>(*L.g);                                          \
+    else if (t.EW) SINGLE_EW<<<(unsigned)L.a->nrb, THREADS + 64, 0, L.s>>>(*L.a);                \
+    else SINGLE<<<(unsigned)L.a->nrb, THREADS, 0, L.s>>>(*L.a);                                  \
+  }                                                                                              \
   return L.dry ? hipSuccess : hipGetLastError();
 
 #if BS32_IN(1)
@@ -2012,8 +2129,8 @@ template <int M>
 hipError_t launch_f64(const Launch& L, const Tile& t) {
 #define X(R_, WR_, WK_, U_, NT_)                                                                 \
   if (t.R == R_ && t.WR == WR_ && t.WK == WK_ && t.U == U_ && t.NT == NT_) {                     \
-    BS32_LAUNCH((k_contract_f64<M, R_, WR_, WK_, U_, NT_>), (k_group_f64<M, R_, WR_, WK_, U_, NT_>), \
-                WR_ * WK_ * 64)                                                                  \
+    BS32_LAUNCH((k_contract_f64<M, R_, WR_, WK_, U_, NT_, true>), (k_contract_f64<M, R_, WR_, WK_, U_, NT_, false>), \
+                (k_group_f64<M, R_, WR_, WK_, U_, NT_>), WR_ * WK_ * 64)                          \
   }
   BS32_F64_TILES(X)
 #undef X
@@ -2027,8 +2144,9 @@ template <int M>
 hipError_t launch_f32(const Launch& L, const Tile& t) {
 #define X(R_, WR_, WK_, U_, NT_)                                                                       \
   if (t.R == R_ && t.WR == WR_ && t.WK == WK_ && t.U == U_ && t.NT == NT_) {                           \
-    BS32_LAUNCH((k_contract_f32<M, 2, R_, WR_, WK_, U_, NT_>), (k_group_f32<M, 2, R_, WR_, WK_, U_, NT_>), \
-                WR_ * WK_ * 64)                                                                        \
+    BS32_LAUNCH((k_contract_f32<M, 2, R_, WR_, WK_, U_, NT_, true>),                                   \
+                (k_contract_f32<M, 2, R_, WR_, WK_, U_, NT_, false>),                                  \
+                (k_group_f32<M, 2, R_, WR_, WK_, U_, NT_>), WR_ * WK_ * 64)                             \
   }
   BS32_F32_TILES(X)
 #undef X
@@ -2042,7 +2160,8 @@ template <int FMT, int M, int T>
 hipError_t launch_mma(const Launch& L, const Tile& t) {
 #define X(R_, WR_, WK_, U_, NT_)                                                            \
   if (t.R == R_ && t.WR == WR_ && t.WK == WK_ && t.U == U_ && t.NT == NT_) {                \
-    BS32_LAUNCH((k_contract_mfma<FMT, M, T, R_, WR_, WK_, U_, NT_>),                        \
+    BS32_LAUNCH((k_contract_mfma<FMT, M, T, R_, WR_, WK_, U_, NT_, true>),                  \
+                (k_contract_mfma<FMT, M, T, R_, WR_, WK_, U_, NT_, false>),                 \
                 (k_group_mfma<FMT, M, T, R_, WR_, WK_, U_, NT_>), WR_ * WK_ * 64)           \
   }
   BS32_MMA_TILES(X)
@@ -2123,11 +2242,14 @@ int kernel_name(int fmt, int m, const Tile& t, char* buf, size_t cap) {
   if (t.MM == 2)  // the system kind and weights also select the instance: name the family and tile
     return snprintf(buf, cap, "k_contract_pair<*, %s, *, %d, %d, %d>", fmt == F_F32 ? "true" : "false", t.R, t.WR,
                     t.U);
-  if (fmt == F_F64) return snprintf(buf, cap, "k_contract_f64<%d, %d, %d, %d, %d, %s>", m, t.R, t.WR, t.WK, t.U, nt);
+  const char* ew = t.EW ? "true" : "false";
+  if (fmt == F_F64)
+    return snprintf(buf, cap, "k_contract_f64<%d, %d, %d, %d, %d, %s, %s>", m, t.R, t.WR, t.WK, t.U, nt, ew);
   if (fmt == F_F32 && !t.MM)
-    return snprintf(buf, cap, "k_contract_f32<%d, 2, %d, %d, %d, %d, %s>", m, t.R, t.WR, t.WK, t.U, nt);
+    return snprintf(buf, cap, "k_contract_f32<%d, 2, %d, %d, %d, %d, %s, %s>", m, t.R, t.WR, t.WK, t.U, nt, ew);
   const int T = fmt == F_E4M3 ? 3 : 2;
-  return snprintf(buf, cap, "k_contract_mfma<%d, %d, %d, %d, %d, %d, %d, %s>", fmt, m, T, t.R, t.WR, t.WK, t.U, nt);
+  return snprintf(buf, cap, "k_contract_mfma<%d, %d, %d, %d, %d, %d, %d, %s, %s>", fmt, m, T, t.R, t.WR, t.WK, t.U, nt,
+                  ew);
 }
 
 bool tile_supported(int fmt, int m, const Tile& t) {
