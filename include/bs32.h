@@ -363,6 +363,23 @@ bs32_status bs32_mlp_train(bs32_ctx* ctx, const float* features, const float* la
 bs32_status bs32_mlp_grad(bs32_ctx* ctx, const float* weights, const float* features, const float* labels, size_t n,
                           double* grad_out, double* loss_out);
 
+/* Allocation-free variant of bs32_mlp_grad, for callers that cannot allocate device
+   memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+   allocation).  Same kernels and the same result, bit for bit, as bs32_mlp_grad on
+   the same inputs; no call allocates or frees memory.  Every buffer is device memory
+   on the context's device, owned by the caller: weights (BS32_MLP_PARAMS floats, the
+   layout above), features (9 n raw floats), labels (n floats), grad_out
+   (BS32_MLP_PARAMS doubles; zero for mu and inv_sd) and loss_out (one double, may be
+   NULL).  1 <= n <= BS32_MLP_NOALLOC_MAX, else BS32_EINVAL.  Intermediate results
+   live in a fixed device array of the library (about 5.3 MiB per GPU, held until the
+   process ends), shared by every call on that GPU: calls that overlap on one GPU
+   (several contexts or streams) race and must be serialized by the caller.  The
+   work is enqueued on the context's stream and the call returns without waiting;
+   the outputs are valid once that stream has completed it. */
+#define BS32_MLP_NOALLOC_MAX 16384
+bs32_status bs32_mlp_grad_noalloc(bs32_ctx* ctx, const float* weights, const float* features, const float* labels,
+                                  size_t n, double* grad_out, double* loss_out);
+
 /* Select the step-size controller of later solves: kind 0 = standard (weights
    ignored), kind 1 = learned proposer with `count` = BS32_MLP_PARAMS finite FP32
    values (host); the network weights are stored rounded to BF16.  Sets

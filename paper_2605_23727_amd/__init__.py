@@ -28,6 +28,7 @@ DIM = {OSC2: 2, LCO_PAPER: 2, KURAMOTO: 1, GOODWIN3: 3, CLOCK4: 4}
 (PREC_FP64, PREC_RHS_FP32, PREC_RHS_BF16, PREC_RHS_FP16, PREC_RHS_FP8_E4M3,
  PREC_PAPER_SINGLE, PREC_PAPER_MIXED1, PREC_PAPER_MIXED2, PREC_RHS_BF16X2) = range(9)
 MLP_PARAMS = 4883  # BS32_MLP_PARAMS
+MLP_NOALLOC_MAX = 16384  # BS32_MLP_NOALLOC_MAX
 METHOD_BS32, METHOD_DP54 = 0, 1  # bs32_method
 MLP_IN = 9
 MODE_NAMES = {0: "fp64", 1: "rhs_fp32", 2: "rhs_bf16", 3: "rhs_fp16", 4: "rhs_fp8_e4m3", 5: "paper_single",
@@ -99,6 +100,8 @@ _SIGS = {
     "bs32_mlp_train": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_int, C.c_float, C.c_uint64,
                         C.c_void_p, C.c_void_p], C.c_int),
     "bs32_mlp_grad": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p], C.c_int),
+    "bs32_mlp_grad_noalloc": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p],
+                              C.c_int),
     "bs32_set_controller": ([C.c_void_p, C.c_int, C.c_void_p, C.c_size_t], C.c_int),
     "bs32_recipe_row": ([C.c_int, C.c_int, C.c_void_p], C.c_int),
     "bs32_last_error": ([C.c_void_p], C.c_char_p),
@@ -425,6 +428,16 @@ class Solver:
         self._check(lib().bs32_mlp_train(self._ctx, F.ctypes.data, Y.ctypes.data, n, int(epochs), int(batch),
                                          float(lr), int(seed), W.ctypes.data, L.ctypes.data))
         return W, L
+
+    def mlp_grad_noalloc(self, weights, features, labels, grad_out, loss_out=None):
+        """bs32_mlp_grad_noalloc on device buffers (torch tensors or raw device pointers):
+        weights / features / labels FP32, grad_out (MLP_PARAMS) and loss_out (1) FP64.
+        Enqueued on the context's stream; returns without waiting."""
+        def ptr(x):
+            return None if x is None else (x if isinstance(x, int) else x.data_ptr())
+        n = (features.numel() if hasattr(features, "numel") else 0) // MLP_IN
+        self._check(lib().bs32_mlp_grad_noalloc(self._ctx, ptr(weights), ptr(features), ptr(labels), n,
+                                                ptr(grad_out), ptr(loss_out)))
 
     def mlp_grad(self, weights, features, labels):
         """(gradient [MLP_PARAMS] float64, loss) of the training loss at BF16-rounded weights."""

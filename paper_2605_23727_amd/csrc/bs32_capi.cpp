@@ -603,6 +603,11 @@ bs32_status bs32_create(bs32_ctx** out, int device, void* hip_stream) {
     bs32_destroy(c);
     return BS32_ENOMEM;
   }
+  // the allocation-free gradient's scratch array: this device's copy, looked up once
+  if (noalloc_bind(device) != hipSuccess) {
+    bs32_destroy(c);
+    return BS32_EDEVICE;
+  }
   std::memset(c->ctl_h[0], 0, sizeof(Ctl));
   std::memset(c->ctl_h[1], 0, sizeof(Ctl));
   *out = c;

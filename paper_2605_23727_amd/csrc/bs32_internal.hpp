@@ -208,6 +208,12 @@ hipError_t launch_mlp_reduce(const float* part, int nparts, double* out, hipStre
 hipError_t launch_mlp_adam(float* master, float* m1, float* m2, float* wq, const float* part, int nparts, float lr,
                            float beta1, float beta2, float eps, float bc1, float bc2, hipStream_t s);
 hipError_t launch_bf16_copy(const float* src, float* dst, int n_round, int n, hipStream_t s);
+// allocation-free gradient: samples at most kNaMaxSamples; noalloc_bind (once per device,
+// with that device current) looks up the device's copy of the scratch array
+constexpr int kNaMaxSamples = 16384;  // BS32_MLP_NOALLOC_MAX
+hipError_t noalloc_bind(int device);
+hipError_t launch_mlp_grad_noalloc(int device, const float* W, const float* F, const float* Y, int n, double* grad,
+                                   double* loss, hipStream_t s);
 hipError_t launch_round_f32(double* x, long long n, hipStream_t s);
 // analytic solution of the coupled linear oscillators and the real local error (bs32_lco.hip)
 hipError_t launch_lco_flow(const double* X, const double* h, long long n, long long count, double* out,

@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <mutex>
+
 #include "bs32_internal.hpp"
 #include "bs32_mlp.hpp"
 
@@ -184,6 +186,83 @@ hipError_t launch_bf16_copy(const float* src, float* dst, int n_round, int n, hi
   if (n <= 0) return hipSuccess;
   k_bf16_copy<<<(n + 255) / 256, 256, 0, s>>>(src, dst, n_round, n);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free gradient (bs32_mlp_grad_noalloc): the same kernels as
+// bs32_mlp_grad, with every intermediate buffer in one file-scope device array.
+// Layout: standardized features [kNaMaxSamples][9] FP32 | BF16 copy of the
+// weights [kMlpParams] FP32 | tile gradients [kNaMaxSamples/64][kMlpNet] FP32 |
+// tile losses [kNaMaxSamples/64] FP64.  Every kernel below writes each byte it
+// later reads, so nothing needs clearing between calls.
+// ---------------------------------------------------------------------------
+constexpr size_t kNaX = (size_t)kNaMaxSamples * kMlpIn * sizeof(float);
+constexpr size_t kNaWq = ((size_t)kMlpParams * sizeof(float) + 255) / 256 * 256;
+constexpr size_t kNaPart = (size_t)(kNaMaxSamples / kTile) * kMlpNet * sizeof(float);
+constexpr size_t kNaLoss = (size_t)(kNaMaxSamples / kTile) * sizeof(double);
+constexpr size_t kNaBytes = kNaX + kNaWq + kNaPart + kNaLoss;
+static_assert(kNaX % 256 == 0 && kNaPart % 256 == 0, "scratch sections stay 256-byte aligned");
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+// the array's address on each device (host code never uses its name for memory)
+constexpr int kNaMaxDevices = 64;
+static void* g_scratch_dev[kNaMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+hipError_t noalloc_bind(int device) {
+  if (device < 0 || device >= kNaMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));  // the current device's copy
+  if (e != hipSuccess) return e;
+  g_scratch_dev[device] = ptr;
+  return hipSuccess;
+}
+
+// FP32 standardization of raw features, the same two roundings as bs32_mlp_grad's host loop
+__global__ void k_na_standardize(const float* __restrict__ W, const float* __restrict__ F, int n,
+                                 float* __restrict__ X) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * kMlpIn) return;
+  const int k = e % kMlpIn;
+  X[e] = (F[e] - W[kMlpMu + k]) * W[kMlpInvSd + k];
+}
+
+// the untrained standardization gets a zero gradient; the loss is the tile losses
+// summed in tile order, over n
+__global__ void k_na_finish(const double* __restrict__ lp, int tiles, int n, double* __restrict__ grad,
+                            double* __restrict__ loss) {
+  const int t = threadIdx.x;
+  if (t < kMlpParams - kMlpNet) grad[kMlpNet + t] = 0.0;
+  if (t == 0 && loss) {
+    double L = 0.0;
+    for (int q = 0; q < tiles; ++q) L += lp[q];
+    *loss = L / (double)n;
+  }
+}
+
+hipError_t launch_mlp_grad_noalloc(int device, const float* W, const float* F, const float* Y, int n, double* grad,
+                                   double* loss, hipStream_t s) {
+  if (device < 0 || device >= kNaMaxDevices || !g_scratch_dev[device]) return hipErrorNotInitialized;
+  if (n < 1 || n > kNaMaxSamples) return hipErrorInvalidValue;
+  unsigned char* base = (unsigned char*)g_scratch_dev[device];
+  float* X = (float*)base;
+  float* wq = (float*)(base + kNaX);
+  float* part = (float*)(base + kNaX + kNaWq);
+  double* lp = (double*)(base + kNaX + kNaWq + kNaPart);
+  const int tiles = (n + kTile - 1) / kTile;
+  k_na_standardize<<<(n * kMlpIn + 255) / 256, 256, 0, s>>>(W, F, n, X);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = launch_bf16_copy(W, wq, kMlpNet, kMlpParams, s);
+  if (e == hipSuccess) e = launch_mlp_grad(wq, X, Y, nullptr, n, 1.0f / (float)n, kMlpOverW, part, lp, s);
+  if (e == hipSuccess) e = launch_mlp_reduce(part, tiles, grad, s);
+  if (e == hipSuccess) {
+    k_na_finish<<<1, 64, 0, s>>>(lp, tiles, n, grad, loss);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 }  // namespace bs32

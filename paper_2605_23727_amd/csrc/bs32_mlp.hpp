@@ -35,6 +35,7 @@ constexpr double kMlpDeltaMin = -1.6094379124341003;  // log 0.2
 constexpr double kMlpDeltaMax = 1.6094379124341003;   // log 5
 constexpr double kMlpTrust = 0.6931471805599453;      // log 2
 constexpr float kMlpXMax = 4.0f;
+constexpr float kMlpOverW = 4.0f;  // loss weight of an overshooting proposal (a rejection costs 3 RHS)
 
 // Forward pass of one sample by one workgroup (blockDim >= 64): feat[9] in LDS,
 // h1/h2 scratch [64] in LDS; returns the output on every thread (NaN when a
