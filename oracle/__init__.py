@@ -79,6 +79,7 @@ def lib():
         L.orc_rhs.argtypes = [P, C.c_double, P, P]
         L.orc_rhs_rows.argtypes = [P, P, C.c_int64, P, C.c_double, P, P]
         L.orc_rhs_lowp.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, P, P]
+        L.orc_rhs_lowp_rows.argtypes = [P, C.c_int, C.c_double, P, C.c_int64, P, C.c_double, P, P]
         L.orc_rhs_recipe.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_double, P, P]
         L.orc_round_fmt.argtypes = [C.c_double, C.c_int]
         L.orc_round_fmt.restype = C.c_double
@@ -153,6 +154,21 @@ def rhs_lowp(kind, n, y, fmt, A=None, param=None, gain=1.0, stimulus=0.0, split_
     y = _f64(y)
     f = np.empty_like(y)
     assert lib().orc_rhs_lowp(s.ref, fmt, split_fmt, split_terms, split_shift, t, _ptr(y), _ptr(f)) == 0
+    return f
+
+
+def rhs_lowp_rows(kind, n, rows, y, fmt, scale, A_rows=None, param=None, gain=1.0, stimulus=0.0, t=0.0):
+    """Reduced-precision right-hand side of the listed rows; scale = matrix_scale of the
+    whole matrix (of its largest magnitude)."""
+    s = _Sys(kind, n, None, param, gain, stimulus)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    y = _f64(y)
+    Ar = None if A_rows is None else _f64(A_rows).reshape(-1)
+    if Ar is not None:
+        assert Ar.size == rows.size * n
+    f = np.empty(rows.size * DIM[kind])
+    rc = lib().orc_rhs_lowp_rows(s.ref, fmt, float(scale), _ptr(rows), rows.size, _ptr(Ar), t, _ptr(y), _ptr(f))
+    assert rc == 0
     return f
 
 

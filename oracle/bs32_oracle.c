@@ -419,14 +419,12 @@ static double split_sum(double v, const lowp_ctx* c) {
   return r;
 }
 
-static int lowp_rhs(const lowp_ctx* c, const double* X, double* F) {
+/* split reconstructions of the vector operand: vt[2j] = x_j (or sin th_j),
+   vt[2j+1] = cos th_j (Kuramoto) */
+static void lowp_operand(const lowp_ctx* c, const double* X, double* vt) {
   const orc_system* s = c->s;
-  const int64_t n = s->n;
   const int d = orc_dim(s->kind);
-  const double invN = 1.0 / (double)n;
-  double* vt = (double*)malloc(sizeof(double) * (size_t)(2 * n));
-  if (!vt) return ORC_EINVAL;
-  for (int64_t j = 0; j < n; ++j) {
+  for (int64_t j = 0; j < s->n; ++j) {
     if (s->kind == ORC_KURAMOTO) {
       vt[2 * j] = split_sum(sin(X[j]), c);
       vt[2 * j + 1] = split_sum(cos(X[j]), c);
@@ -435,38 +433,52 @@ static int lowp_rhs(const lowp_ctx* c, const double* X, double* F) {
       vt[2 * j + 1] = 0.0;
     }
   }
-#pragma omp parallel for schedule(static) if (n >= 64)
-  for (int64_t i = 0; i < n; ++i) {
-    const double* Xi = X + i * d;
-    double* Fi = F + i * d;
-    double p0 = 0.0, p1 = 0.0;
-    for (int64_t j = 0; j < n; ++j) {
-      p0 += c->Ahat[i * n + j] * vt[2 * j];
-      p1 += c->Ahat[i * n + j] * vt[2 * j + 1];
+}
+
+/* agent i from its row of stored weights Ai, their sum rs and the operand vt */
+static void lowp_row(const orc_system* s, int64_t i, const double* Ai, double rs, const double* vt, const double* X,
+                     double* Fi) {
+  const int d = orc_dim(s->kind);
+  const double invN = 1.0 / (double)s->n;
+  const double* Xi = X + i * d;
+  double p0 = 0.0, p1 = 0.0;
+  for (int64_t j = 0; j < s->n; ++j) {
+    p0 += Ai[j] * vt[2 * j];
+    p1 += Ai[j] * vt[2 * j + 1];
+  }
+  switch (s->kind) {
+    case ORC_OSC2: {
+      double w = agent_param(s, i);
+      Fi[0] = Xi[1];
+      Fi[1] = -w * w * Xi[0] + invN * (p0 - Xi[0] * rs);
+      break;
     }
-    switch (s->kind) {
-      case ORC_OSC2: {
-        double w = agent_param(s, i);
-        Fi[0] = Xi[1];
-        Fi[1] = -w * w * Xi[0] + invN * (p0 - Xi[0] * c->rsum[i]);
-        break;
-      }
-      case ORC_LCO_PAPER:
-        Fi[0] = Xi[1] + invN * (p0 - Xi[0] * c->rsum[i]);
-        Fi[1] = -Xi[0];
-        break;
-      case ORC_KURAMOTO:
-        Fi[0] = agent_param(s, i) + s->gain * invN * (cos(Xi[0]) * p0 - sin(Xi[0]) * p1);
-        break;
-      case ORC_GOODWIN3: {
-        double b = agent_param(s, i);
-        Fi[0] = 1.0 / (1.0 + pow(Xi[2], 10.0)) - b * Xi[0] + s->gain * invN * (p0 - Xi[0] * c->rsum[i]);
-        Fi[1] = Xi[0] - b * Xi[1];
-        Fi[2] = Xi[1] - b * Xi[2];
-        break;
-      }
+    case ORC_LCO_PAPER:
+      Fi[0] = Xi[1] + invN * (p0 - Xi[0] * rs);
+      Fi[1] = -Xi[0];
+      break;
+    case ORC_KURAMOTO:
+      Fi[0] = agent_param(s, i) + s->gain * invN * (cos(Xi[0]) * p0 - sin(Xi[0]) * p1);
+      break;
+    case ORC_GOODWIN3: {
+      double b = agent_param(s, i);
+      Fi[0] = 1.0 / (1.0 + pow(Xi[2], 10.0)) - b * Xi[0] + s->gain * invN * (p0 - Xi[0] * rs);
+      Fi[1] = Xi[0] - b * Xi[1];
+      Fi[2] = Xi[1] - b * Xi[2];
+      break;
     }
   }
+}
+
+static int lowp_rhs(const lowp_ctx* c, const double* X, double* F) {
+  const orc_system* s = c->s;
+  const int64_t n = s->n;
+  const int d = orc_dim(s->kind);
+  double* vt = (double*)malloc(sizeof(double) * (size_t)(2 * n));
+  if (!vt) return ORC_EINVAL;
+  lowp_operand(c, X, vt);
+#pragma omp parallel for schedule(static) if (n >= 64)
+  for (int64_t i = 0; i < n; ++i) lowp_row(s, i, c->Ahat + i * n, c->rsum[i], vt, X, F + i * d);
   free(vt);
   return ORC_OK;
 }
@@ -480,6 +492,47 @@ int orc_rhs_lowp(const orc_system* s, int fmt, int sfmt, int terms, int shift, d
   if (rc == ORC_OK) rc = lowp_rhs(&c, X, F);
   lowp_free(&c);
   return rc;
+}
+
+/* The same definition for a subset of rows: the stored weights of the listed rows
+   are formed from their FP64 values with the per-tensor scale of the whole matrix
+   (passed in: it depends only on max|A|), everything else as in orc_rhs_lowp. */
+int orc_rhs_lowp_rows(const orc_system* s, int fmt, double scale, const int64_t* rows, int64_t nrows,
+                      const double* Arows, double t, const double* X, double* F_rows) {
+  (void)t;
+  const int64_t n = s->n;
+  const int d = orc_dim(s->kind);
+  if (d == 0 || n <= 0 || s->kind == ORC_CLOCK4 || !(scale > 0.0)) return ORC_EINVAL;
+  for (int64_t r = 0; r < nrows; ++r)
+    if (rows[r] < 0 || rows[r] >= n) return ORC_EINVAL;
+  lowp_ctx c;
+  c.s = s;
+  c.Ahat = NULL;
+  c.rsum = NULL;
+  int dfm, dt, dsh;
+  split_defaults(fmt, &dfm, &dt, &dsh);
+  c.sfmt = dfm;
+  c.terms = dt;
+  c.shift = dsh;
+  double* vt = (double*)malloc(sizeof(double) * (size_t)(2 * n));
+  double* Ahat = (double*)malloc(sizeof(double) * (size_t)(nrows * n));
+  if (!vt || !Ahat) {
+    free(vt);
+    free(Ahat);
+    return ORC_EINVAL;
+  }
+  for (int64_t k = 0; k < nrows * n; ++k)
+    Ahat[k] = Arows ? scale * orc_round_fmt(Arows[k] / scale, fmt) : 1.0;
+  lowp_operand(&c, X, vt);
+#pragma omp parallel for schedule(static) if (nrows >= 8)
+  for (int64_t r = 0; r < nrows; ++r) {
+    double rs = 0.0;
+    for (int64_t j = 0; j < n; ++j) rs += Ahat[r * n + j];
+    lowp_row(s, rows[r], Ahat + r * n, rs, vt, X, F_rows + r * d);
+  }
+  free(vt);
+  free(Ahat);
+  return ORC_OK;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -117,6 +117,13 @@ int orc_rhs_rows(const orc_system* sys, const int64_t* rows, int64_t nrows, cons
 int orc_rhs_lowp(const orc_system* sys, int fmt, int split_fmt, int split_terms, int split_shift,
                  double t, const double* X, double* F);
 
+/* The reduced-precision definition for a subset of rows (checks of sampled outputs
+   at full size): Arows holds the listed agents' FP64 rows (nrows*n, NULL = all
+   ones), scale the per-tensor scale of the whole matrix (orc_matrix_scale; it
+   depends only on max|A|), the split of the vector operand the format's default. */
+int orc_rhs_lowp_rows(const orc_system* sys, int fmt, double scale, const int64_t* rows, int64_t nrows,
+                      const double* Arows, double t, const double* X, double* F_rows);
+
 /* Paper recipe evaluation of one stage (Sec. 2.3, Table MP-Distrib): pF, pS, pG in
    {0 = double, 1 = single} for the agent term, the accumulation and the pair term. */
 int orc_rhs_recipe(const orc_system* sys, int pF, int pS, int pG, double t, const double* X, double* F);

@@ -148,3 +148,22 @@ def test_bf16_pair_mode_reduces_to_bf16_on_bf16_weights(orc):
     err = {f: np.max(np.abs(orc.rhs_lowp(orc.KURAMOTO, n, th, f, A=A, param=om, gain=2.0) - ref))
            for f in (orc.FMT_F32, orc.FMT_BF16X2, orc.FMT_BF16)}
     assert err[orc.FMT_F32] < err[orc.FMT_BF16X2] < err[orc.FMT_BF16] / 30
+
+
+@pytest.mark.parametrize("fmt", [1, 2, 3, 4])
+@pytest.mark.parametrize("kind", [1, 3, 4])
+def test_lowp_rows_equal_whole_system(orc, kind, fmt):
+    """The sampled-row reduced-precision evaluation equals the whole-system one on
+    every listed row (same stored weights from the scale of max|A|, same split)."""
+    import workloads
+    make = {1: workloads.osc2, 3: workloads.kuramoto, 4: workloads.goodwin3}[kind]
+    w = make(150, seed=90 + kind)
+    full = orc.rhs_lowp(w["kind"], w["n"], w["y0"], fmt, A=w["A"], param=w["param"], gain=w["gain"])
+    rows = np.array([0, 7, 149, 64, 3])
+    scale = orc.matrix_scale(np.array([np.max(np.abs(w["A"]))]), fmt)
+    assert scale == orc.matrix_scale(w["A"], fmt)
+    part = orc.rhs_lowp_rows(w["kind"], w["n"], rows, w["y0"], fmt, scale, A_rows=w["A"][rows], param=w["param"],
+                             gain=w["gain"])
+    d = workloads.DIM[kind]
+    ref = full.reshape(-1, d)[rows].reshape(-1)
+    assert np.array_equal(part, ref)
