@@ -137,7 +137,12 @@ typedef struct {
 typedef struct {
   int64_t i_max;         /* attempt limit (default 100000, Sec. 2.2) */
   double time_limit_s;   /* wall-time limit (default 5400 s, Sec. 2.2); <= 0 disables */
-  double slow_limit_s;   /* "slow solver" time (default 2700 s, Sec. 2.2); <= 0 disables */
+  double slow_limit_s;   /* "slow solver" time (default 2700 s, Sec. 2.2); <= 0 disables.
+                            Both are checked by the host between chunks of attempts (2..64):
+                            the chunk in flight when a limit is noticed still runs, so up to
+                            64 more attempts count; the solve then returns BS32_TIMEOUT /
+                            BS32_TOO_SLOW with y_out the last accepted state and the time and
+                            counts reached in bs32_stats (per instance for a batch) */
   double h_max;          /* <= 0: 0.1 |t1 - t0| */
   double h0;             /* > 0: initial step (skips the starting-step evaluation) */
   double safety, facmin, facmax; /* controller constants (defaults 0.9, 0.2, 5) */
