@@ -171,3 +171,35 @@ def test_format_switch_single_system(bs):
         np.testing.assert_array_equal(y, y2)
     finally:
         s.set_options(tile=-1)
+
+
+def test_range_stop_is_per_instance(bs):
+    """One instance whose operand leaves the e4m3 range (|x| > 448) stops with
+    BS32_RANGE; the others run on and equal their single-system solves."""
+    b, s = bs
+    ws = [workloads.osc2(int(n), seed=140 + q, t1=2.0) for q, n in enumerate((200, 150, 260, 90))]
+    ws[2]["y0"] = ws[2]["y0"].copy()
+    ws[2]["y0"][0::2] *= 1000.0  # positions far outside e4m3's range
+    say("[range per instance] osc2 B=4, instance 2 out of range, e4m3")
+    s.set_options(tile=0)
+    try:
+        s.set_ensemble(ws)
+        y0 = np.concatenate([w["y0"] for w in ws])
+        y, st, tot = s.solve_batch(y0, 0.0, np.full(4, 2.0), 1e-6, mode=4)
+        say(f"   statuses {list(st)}")
+        assert st[2] == b.RANGE
+        assert all(st[q] == 0 for q in (0, 1, 3))
+        single = b.Solver(0)
+        single.set_options(tile=0)
+        off = 0
+        for q, w in enumerate(ws):
+            m = w["y0"].size
+            if q != 2:
+                single.set_workload(w)
+                ys, sst = single.solve(w["y0"], 0.0, 2.0, 1e-6, mode=4)
+                assert sst["status"] == 0
+                assert np.array_equal(ys, y[off:off + m]), q
+            off += m
+        single.close()
+    finally:
+        s.set_options(tile=-1)
