@@ -92,6 +92,8 @@ def lib():
         L.orc_split.argtypes = [C.c_double, C.c_int, C.c_int, C.c_int, P]
         L.orc_bs32_solve.argtypes = [P, P, C.c_int, P, C.c_double, C.c_double, P, P, P, C.c_int64, P]
         L.orc_dp54_solve.argtypes = [P, P, P, C.c_double, C.c_double, P, P]
+        L.orc_rkf45_solve.argtypes = [P, P, P, C.c_double, C.c_double, P, P]
+        L.orc_rkf45_tableau.argtypes = [P, P, P, P]
         L.orc_bs32_attempt.argtypes = [P, C.c_double, C.c_double, P, P, C.c_double, C.c_double, P, P, P]
         L.orc_bs32_tableau.argtypes = [P, P, P, P]
         L.orc_set_threads.argtypes = [C.c_int]
@@ -266,6 +268,22 @@ def dp54_solve(kind, n, y0, t0, t1, rtol, atol=None, A=None, param=None, gain=1.
     st = Stats()
     lib().orc_dp54_solve(s.ref, C.byref(o), _ptr(y0), t0, t1, _ptr(y), C.byref(st))
     return y, st.as_dict()
+
+
+def rkf45_solve(kind, n, y0, t0, t1, rtol, atol=None, A=None, param=None, gain=1.0, stimulus=0.0, **opt):
+    s = _Sys(kind, n, A, param, gain, stimulus)
+    o = options(rtol, atol, **opt)
+    y0 = _f64(y0)
+    y = np.empty_like(y0)
+    st = Stats()
+    lib().orc_rkf45_solve(s.ref, C.byref(o), _ptr(y0), t0, t1, _ptr(y), C.byref(st))
+    return y, st.as_dict()
+
+
+def rkf45_tableau():
+    c, a, b, bh = np.empty(6), np.empty(36), np.empty(6), np.empty(6)
+    lib().orc_rkf45_tableau(_ptr(c), _ptr(a), _ptr(b), _ptr(bh))
+    return c, a.reshape(6, 6), b, bh
 
 
 def bs32_attempt(kind, n, t, h, X, K1, rtol, atol=None, A=None, param=None, gain=1.0, stimulus=0.0):

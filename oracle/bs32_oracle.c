@@ -92,6 +92,30 @@ void orc_dp54_tableau(double c[7], double a[49], double b[7], double bt[7]) {
   }
 }
 
+/* Fehlberg 4(5) (the embedded Fehlberg pair the paper's conclusion names): six
+   stages, the fourth-order solution is propagated and the fifth-order one only
+   measures its error.  Published coefficients. */
+static const double FE_C[6] = {0.0, 1.0 / 4.0, 3.0 / 8.0, 12.0 / 13.0, 1.0, 1.0 / 2.0};
+static const double FE_A[6][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 4.0, 0, 0, 0, 0, 0},
+    {3.0 / 32.0, 9.0 / 32.0, 0, 0, 0, 0},
+    {1932.0 / 2197.0, -7200.0 / 2197.0, 7296.0 / 2197.0, 0, 0, 0},
+    {439.0 / 216.0, -8.0, 3680.0 / 513.0, -845.0 / 4104.0, 0, 0},
+    {-8.0 / 27.0, 2.0, -3544.0 / 2565.0, 1859.0 / 4104.0, -11.0 / 40.0, 0},
+};
+static const double FE_B[6] = {25.0 / 216.0, 0.0, 1408.0 / 2565.0, 2197.0 / 4104.0, -1.0 / 5.0, 0.0};
+static const double FE_BH[6] = {16.0 / 135.0, 0.0, 6656.0 / 12825.0, 28561.0 / 56430.0, -9.0 / 50.0, 2.0 / 55.0};
+
+void orc_rkf45_tableau(double c[6], double a[36], double b[6], double bh[6]) {
+  for (int i = 0; i < 6; ++i) {
+    c[i] = FE_C[i];
+    b[i] = FE_B[i];
+    bh[i] = FE_BH[i];
+    for (int j = 0; j < 6; ++j) a[6 * i + j] = FE_A[i][j];
+  }
+}
+
 void orc_set_threads(int n) {
 #ifdef _OPENMP
   if (n > 0) omp_set_num_threads(n);
@@ -979,6 +1003,94 @@ int orc_bs32_solve(const orc_system* s, const orc_options* o, int mode, const do
 /* ------------------------------------------------------------------------ */
 /* DP5(4) reference integrator (FSAL, weighted max norm, order-5 controller) */
 /* ------------------------------------------------------------------------ */
+/* Adaptive Fehlberg 4(5) with the paper's acceptance rule and weighted max norm
+   (Sec. 2.2): stages K_l = f(X + h sum_q a_lq K_q), the fourth-order solution
+   X_new = X + h sum_l b_l K_l, the error h sum_l (b_l - bh_l) K_l against the fifth
+   order, accept iff E < Rel; then t += h, X = X_new and K_1 = f(X_new) (the pair has
+   no shared last stage).  Step factor safety (Rel / E)^(1/5) clipped to
+   [facmin, facmax] (growth capped at 1 right after a rejection); the starting step
+   with the order 4. */
+int orc_rkf45_solve(const orc_system* s, const orc_options* o, const double* y0, double t0, double t1,
+                    double* y_out, orc_stats* st) {
+  const int d = orc_dim(s->kind);
+  if (d == 0 || s->n <= 0 || !(o->rtol > 0.0) || !(t1 >= t0)) return ORC_EINVAL;
+  const int64_t m = (int64_t)d * s->n;
+  memset(st, 0, sizeof(*st));
+  if (t1 == t0) {
+    memmove(y_out, y0, sizeof(double) * (size_t)m);
+    st->t_reached = t0;
+    return ORC_OK;
+  }
+  double h_max, safety, facmin, facmax;
+  int64_t i_max;
+  fill_defaults(o, t0, t1, &h_max, &i_max, &safety, &facmin, &facmax);
+  evaluator ev = {s, ORC_PREC_FP64, {0}, 0};
+  double* K[6];
+  for (int l = 0; l < 6; ++l) K[l] = (double*)malloc(sizeof(double) * (size_t)m);
+  double* X = (double*)malloc(sizeof(double) * (size_t)m);
+  double* Xn = (double*)malloc(sizeof(double) * (size_t)m);
+  double* Y = (double*)malloc(sizeof(double) * (size_t)m);
+  memcpy(X, y0, sizeof(double) * (size_t)m);
+  double t = t0;
+  orc_rhs(s, t, X, K[0]);
+  st->n_fev = 1;
+  double h = (o->h0 > 0.0) ? o->h0 : start_step(&ev, 4, t0, X, K[0], m, o->rtol, o->atol, h_max, &st->n_fev);
+  int last_rejected = 0, status = ORC_OK;
+  const double snap = 4.0 * DBL_EPSILON * fabs(t1);
+  while (t < t1) {
+    const double ha = fmin(h, t1 - t);
+    for (int l = 1; l < 6; ++l) {
+      for (int64_t k = 0; k < m; ++k) {
+        double acc = 0.0;
+        for (int q = 0; q < l; ++q) acc += FE_A[l][q] * K[q][k];
+        Y[k] = X[k] + ha * acc;
+      }
+      orc_rhs(s, t + FE_C[l] * ha, Y, K[l]);
+    }
+    st->n_fev += 5;
+    double E = 0.0;
+    const double fw = o->atol / o->rtol;
+    for (int64_t k = 0; k < m; ++k) {
+      double acc = 0.0, err = 0.0;
+      for (int q = 0; q < 6; ++q) {
+        acc += FE_B[q] * K[q][k];
+        err += (FE_B[q] - FE_BH[q]) * K[q][k];
+      }
+      Xn[k] = X[k] + ha * acc;
+      double W = fmax(fmax(fabs(X[k]), fabs(Xn[k])), fw);
+      double v = fabs(ha * err) / W;
+      if (isnan(v) || isnan(E)) E = NAN;
+      else if (v > E) E = v;
+    }
+    if (!isfinite(E)) { status = ORC_NONFINITE; break; }
+    double fac = (E > 0.0) ? safety * pow(o->rtol / E, 0.2) : facmax;
+    if (E < o->rtol) {
+      st->n_accept++;
+      t = (t + ha >= t1 - snap) ? t1 : t + ha;
+      double* tmp = X; X = Xn; Xn = tmp;
+      orc_rhs(s, t, X, K[0]);
+      st->n_fev += 1;
+      h = ha * fmin(last_rejected ? 1.0 : facmax, fmax(facmin, fac));
+      last_rejected = 0;
+    } else {
+      st->n_reject++;
+      h = ha * fmax(facmin, fac);
+      last_rejected = 1;
+    }
+    h = fmin(h, h_max);
+    st->err_last = E;
+    if (t >= t1) break;
+    if (st->n_accept + st->n_reject > i_max) { status = ORC_MAX_STEPS; break; }
+    if (h <= 100.0 * DBL_EPSILON) { status = ORC_H_TOO_SMALL; break; }
+  }
+  st->t_reached = t;
+  st->status = status;
+  memcpy(y_out, X, sizeof(double) * (size_t)m);
+  for (int l = 0; l < 6; ++l) free(K[l]);
+  free(X); free(Xn); free(Y);
+  return status;
+}
+
 int orc_dp54_solve(const orc_system* s, const orc_options* o, const double* y0, double t0, double t1,
                    double* y_out, orc_stats* st) {
   const int d = orc_dim(s->kind);

@@ -155,6 +155,14 @@ int orc_bs32_solve(const orc_system* sys, const orc_options* opt, int prec_mode,
 int orc_dp54_solve(const orc_system* sys, const orc_options* opt,
                    const double* y0, double t0, double t1, double* y_out, orc_stats* st);
 
+/* Fehlberg 4(5): the embedded Fehlberg pair (published coefficients), fourth-order
+   solution propagated, the same norm, acceptance rule and step factor exponent 1/5 as
+   orc_dp54_solve; K_1 is evaluated afresh after every accepted step (no shared last
+   stage), so n_fev = 1 + (starting step) + 5 attempts + accepted steps. */
+void orc_rkf45_tableau(double c[6], double a[36], double b[6], double bh[6]);
+int orc_rkf45_solve(const orc_system* sys, const orc_options* opt,
+                    const double* y0, double t0, double t1, double* y_out, orc_stats* st);
+
 /* ---- learned step-size proposer ----------------------------------------
    An extension: Sec. 2.2 only says that the error estimate drives the step-size
    correction.  9 -> 64 -> 64 -> 1 network with tanh hidden layers on standardized

@@ -136,3 +136,23 @@ def test_bs32_steps_scale_as_cube_root(orc):
         _, st, _ = orc.bs32_solve(1, 16, w["y0"], 0.0, 5.0, rtol, A=w["A"], param=w["param"])
         n_acc.append(st["n_accept"])
     assert 7.0 < n_acc[1] / n_acc[0] < 14.0  # 10^(3/3) = 10
+
+
+def test_rkf45_against_library(orc):
+    """The oracle's Fehlberg 4(5) solve against scipy's DOP853 at a tight tolerance;
+    fourth-order error estimate: two decades of tolerance cost about 10^(2/5) more steps."""
+    w = _kur(n=8, seed=32, t1=5.0)
+    A, om, K, n = w["A"], w["param"], w["gain"], 8
+
+    def f(t, th):
+        return orc.rhs(3, n, th, A=A, param=om, gain=K)
+
+    ref = scipy.integrate.solve_ivp(f, (0.0, 5.0), w["y0"], method="DOP853", rtol=1e-13, atol=1e-13).y[:, -1]
+    y, st = orc.rkf45_solve(3, n, w["y0"], 0.0, 5.0, 1e-11, A=A, param=om, gain=K)
+    assert st["status"] == 0 and st["t_reached"] == 5.0
+    assert np.max(np.abs(y - ref)) < 1e-8
+    # every accepted step costs five new stages plus the fresh first stage
+    assert st["n_fev"] == 2 + 5 * (st["n_accept"] + st["n_reject"]) + st["n_accept"]
+    _, st2 = orc.rkf45_solve(3, n, w["y0"], 0.0, 5.0, 1e-9, A=A, param=om, gain=K)
+    ratio = st["n_accept"] / st2["n_accept"]
+    assert 1.8 < ratio < 3.5
