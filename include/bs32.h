@@ -164,9 +164,15 @@ typedef struct {
    with seven FSAL stages per attempt, the same weighted max norm and acceptance
    rule (E < Rel) and the step factor safety * (Rel / E)^(1/5), clipped to
    [facmin, facmax] (growth capped at 1 right after a rejection); the starting
-   step uses the exponent 1/6.  Not with the paper's recipes (modes 5-7), the
-   learned proposer or ensembles (EUNSUPPORTED). */
-typedef enum { BS32_METHOD_BS32 = 0, BS32_METHOD_DP54 = 1 } bs32_method;
+   step uses the exponent 1/6.  BS32_METHOD_RKF45 runs the embedded Fehlberg pair
+   the conclusion also names (Fehlberg 4(5), published coefficients) on the same
+   kernels: six stages, the fourth-order solution propagated and the fifth-order one
+   measuring its error, the same norm, acceptance rule and step factor
+   (exponent 1/5), starting step exponent 1/5; each attempt also evaluates f at
+   its new solution, which becomes the next first stage (six evaluations per
+   attempt, like DP5(4)).  Neither seven-stage pair serves the paper's recipes
+   (modes 5-7), the learned proposer or ensembles (EUNSUPPORTED). */
+typedef enum { BS32_METHOD_BS32 = 0, BS32_METHOD_DP54 = 1, BS32_METHOD_RKF45 = 2 } bs32_method;
 
 /* One record per step attempt of the last solve (when options.trace = 1). */
 typedef struct {

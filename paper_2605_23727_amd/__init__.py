@@ -29,7 +29,7 @@ DIM = {OSC2: 2, LCO_PAPER: 2, KURAMOTO: 1, GOODWIN3: 3, CLOCK4: 4}
  PREC_PAPER_SINGLE, PREC_PAPER_MIXED1, PREC_PAPER_MIXED2, PREC_RHS_BF16X2) = range(9)
 MLP_PARAMS = 4883  # BS32_MLP_PARAMS
 MLP_NOALLOC_MAX = 16384  # BS32_MLP_NOALLOC_MAX
-METHOD_BS32, METHOD_DP54 = 0, 1  # bs32_method
+METHOD_BS32, METHOD_DP54, METHOD_RKF45 = 0, 1, 2  # bs32_method
 MLP_IN = 9
 MODE_NAMES = {0: "fp64", 1: "rhs_fp32", 2: "rhs_bf16", 3: "rhs_fp16", 4: "rhs_fp8_e4m3", 5: "paper_single",
               6: "paper_mixed1", 7: "paper_mixed2", 8: "rhs_bf16x2"}

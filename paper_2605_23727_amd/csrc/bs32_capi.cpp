@@ -342,6 +342,7 @@ Args make_args(bs32_ctx* c, int fmt, const Geom& g, int stage) {
   a.nrb = g.nrb;
   a.RB = g.RB;
   a.KW = g.KW;
+  a.pair = c->opt.method;
   return a;
 }
 
@@ -477,7 +478,7 @@ bs32_status prepare(bs32_ctx* c, int mode, Geom* g, int* fmt) {
     c->vq_fmt = *fmt;
   }
   char key[128];
-  snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%p/%p/%lld/%d", mode, t.R, t.WR, t.WK, t.U, t.NT, t.MM,
+  snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%d/%p/%p/%lld/%d", mode, t.R, t.WR, t.WK, t.U, t.NT, t.MM, t.EW,
            (void*)c->trace_d, (void*)(c->in_solve ? c->rec : nullptr), c->rec_cap, c->opt.method);
   if (c->graph_key != key) {
     free_graphs(c);
@@ -489,7 +490,7 @@ bs32_status prepare(bs32_ctx* c, int mode, Geom* g, int* fmt) {
 hipError_t enqueue_attempt(bs32_ctx* c, int fmt, const Geom& g) {
   hipError_t e;
   Args a{};
-  if (c->opt.method == BS32_METHOD_DP54) {
+  if (c->opt.method != BS32_METHOD_BS32) {  // Dormand-Prince 5(4) or Fehlberg 4(5): six contractions
     for (int st = ST_D2; st <= ST_D7; ++st) {
       a = make_args(c, fmt, g, st);
       if ((e = launch_contract(a, fmt, g.t, c->stream)) != hipSuccess) return e;
@@ -645,7 +646,7 @@ bs32_status bs32_set_options(bs32_ctx* c, const bs32_options* o) {
   if (o->fixed_step && !(o->h0 > 0)) return fail(c, BS32_EINVAL, "fixed_step needs h0 > 0");
   if (o->controller != 0 && o->controller != 1) return fail(c, BS32_EINVAL, "unknown controller %d", o->controller);
   if (o->controller == 1 && !c->mlp_w) return fail(c, BS32_ESTATE, "learned controller needs bs32_set_controller");
-  if (o->method != BS32_METHOD_BS32 && o->method != BS32_METHOD_DP54)
+  if (o->method != BS32_METHOD_BS32 && o->method != BS32_METHOD_DP54 && o->method != BS32_METHOD_RKF45)
     return fail(c, BS32_EINVAL, "unknown method %d", o->method);
   c->opt = *o;
   free_graphs(c);
@@ -823,7 +824,7 @@ bs32_status bs32_solve(bs32_ctx* c, const double* y0, double t0, double t1, doub
     ~InSolve() { c->in_solve = false; }
   } in_solve(c);
   const bs32_options& o = c->opt;
-  if (o.method == BS32_METHOD_DP54) {
+  if (o.method != BS32_METHOD_BS32) {
     if (mode >= BS32_PREC_PAPER_SINGLE)
       return fail(c, BS32_EUNSUPPORTED, "the paper's recipes are defined for the Bogacki-Shampine stages");
     if (o.controller == 1) return fail(c, BS32_EUNSUPPORTED, "the learned proposer serves the Bogacki-Shampine pair");

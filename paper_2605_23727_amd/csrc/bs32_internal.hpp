@@ -29,6 +29,23 @@ constexpr double kDpB[7] = {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0, -2
 constexpr double kDpBt[7] = {5179.0 / 57600.0, 0.0, 7571.0 / 16695.0, 393.0 / 640.0, -92097.0 / 339200.0,
                              187.0 / 2100.0, 1.0 / 40.0};
 
+// ---- Fehlberg 4(5), the embedded Fehlberg pair of the conclusion, laid out like the
+// Dormand-Prince arrays above: rows 1..5 build the inputs of stages 2..6, row 6 holds
+// the propagated fourth-order weights (the seventh evaluation, at X^{n+1}, becomes the
+// next step's first stage), and the error weights b - bt leave the seventh stage out.
+// Published coefficients.
+constexpr double kFeA[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 4.0, 0, 0, 0, 0, 0},
+    {3.0 / 32.0, 9.0 / 32.0, 0, 0, 0, 0},
+    {1932.0 / 2197.0, -7200.0 / 2197.0, 7296.0 / 2197.0, 0, 0, 0},
+    {439.0 / 216.0, -8.0, 3680.0 / 513.0, -845.0 / 4104.0, 0, 0},
+    {-8.0 / 27.0, 2.0, -3544.0 / 2565.0, 1859.0 / 4104.0, -11.0 / 40.0, 0},
+    {25.0 / 216.0, 0.0, 1408.0 / 2565.0, 2197.0 / 4104.0, -1.0 / 5.0, 0.0},
+};
+constexpr double kFeB[7] = {25.0 / 216.0, 0.0, 1408.0 / 2565.0, 2197.0 / 4104.0, -1.0 / 5.0, 0.0, 0.0};
+constexpr double kFeBt[7] = {16.0 / 135.0, 0.0, 6656.0 / 12825.0, 28561.0 / 56430.0, -9.0 / 50.0, 2.0 / 55.0, 0.0};
+
 // internal solver status (public codes are bs32_status values >= 0)
 constexpr int kRunning = 100;
 constexpr int kStatusRange = 7;  // BS32_RANGE
@@ -73,7 +90,7 @@ struct Ctl {
   long long nhist;        // attempts recorded in the history
   long long n_mlp;        // steps chosen by the learned proposer
   int prop_cur;           // 1 if the current step size came from the learned proposer
-  int method;             // 0: Bogacki-Shampine 3(2), 1: Dormand-Prince 5(4)
+  int method;             // 0: Bogacki-Shampine 3(2), 1: Dormand-Prince 5(4), 2: Fehlberg 4(5)
 };
 
 struct TraceRec {
@@ -128,6 +145,7 @@ struct Args {
   double stim;            // I_0 of the clock / cell-cycle model
   double* rec;            // solution record (initial value, then one state per accepted step), or null
   long long rec_cap;      // states the record holds (d * n agent-major doubles each)
+  int pair;               // seven-stage attempts (ST_D2 .. ST_D7): 1 Dormand-Prince 5(4), 2 Fehlberg 4(5)
 };
 
 // Ensembles: one work item = (instance, row block) for a contraction, or

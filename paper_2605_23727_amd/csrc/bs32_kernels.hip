@@ -534,7 +534,14 @@ __device__ __forceinline__ void epilogue(const Args& a, const Ctl* ctl, long lon
   }
 }
 
-// Dormand-Prince 5(4) stage s = 2..7 of one row: K_s from the contraction of the
+// coefficients of the seven-stage pair in use (a.pair: 2 Fehlberg 4(5), else Dormand-Prince 5(4))
+__device__ __forceinline__ double pair_a(const Args& a, int s, int l) { return a.pair == 2 ? kFeA[s][l] : kDpA[s][l]; }
+__device__ __forceinline__ double pair_e(const Args& a, int l) {
+  return a.pair == 2 ? kFeB[l] - kFeBt[l] : kDpB[l] - kDpBt[l];
+}
+
+// Stage s = 2..7 of a seven-stage attempt (Dormand-Prince 5(4), or Fehlberg 4(5)
+// with its fourth-order solution in row 6) of one row: K_s from the contraction of the
 // stage input, then the next stage's input X + h sum_l a_{s+1,l} K_l (stage 6 writes
 // it as X^{n+1} too), or at stage 7 (FSAL, evaluated at X^{n+1}) the difference of
 // the two solutions h sum_l (b_l - bt_l) K_l and its weights.  The sums run over l in
@@ -573,7 +580,7 @@ __device__ __forceinline__ void epilogue_dp_s(const Args& a, const Ctl* ctl, lon
     } else {
       double acc = 0.0;
 #pragma unroll
-      for (int l = 0; l < S - 1; ++l) acc += kDpA[S - 1][l] * K[l][c];
+      for (int l = 0; l < S - 1; ++l) acc += pair_a(a, S - 1, l) * K[l][c];
       y[c] = x[c] + ha * acc;
     }
   }
@@ -594,7 +601,7 @@ __device__ __forceinline__ void epilogue_dp_s(const Args& a, const Ctl* ctl, lon
       if (c >= d) break;
       double acc = 0.0;
 #pragma unroll
-      for (int l = 0; l < S; ++l) acc += kDpA[S][l] * K[l][c];
+      for (int l = 0; l < S; ++l) acc += pair_a(a, S, l) * K[l][c];
       yn[c] = x[c] + ha * acc;
       if constexpr (S == 6) {
         if (col <= 0) Xn[c * np + i] = yn[c];
@@ -609,7 +616,7 @@ __device__ __forceinline__ void epilogue_dp_s(const Args& a, const Ctl* ctl, lon
       if (c >= d) break;
       double acc = 0.0;
 #pragma unroll
-      for (int l = 0; l < 7; ++l) acc += (kDpB[l] - kDpBt[l]) * K[l][c];
+      for (int l = 0; l < 7; ++l) acc += pair_e(a, l) * K[l][c];
       const double W = fmax(fmax(fabs(x[c]), fabs(y[c])), floor_w);
       *r0 = nanmax(*r0, fabs(ha * acc) / W);
       *r1 = nanmax(*r1, fabs(K[0][c]) / fmax(fabs(x[c]), floor_w));
@@ -1586,8 +1593,9 @@ __device__ __forceinline__ bool finalize(const Args& a, Ctl* c, double m0, doubl
       const double h0 = c->h0probe;
       const double d2 = m0 / h0;
       const double dm = fmax(c->d1, d2);
-      // exponent 1/(p+1) of the method's order p: 3 (BS3(2)) or 5 (DP5(4))
-      const double h1 = (dm <= 1e-15) ? fmax(1e-6, h0 * 1e-3) : pow(0.01 / dm, c->method ? 1.0 / 6.0 : 0.25);
+      // exponent 1/(p+1) of the order p of the propagated solution: 3 (BS3(2)), 5 (DP5(4)), 4 (RKF4(5))
+      const double ex = c->method == 1 ? 1.0 / 6.0 : c->method == 2 ? 0.2 : 0.25;
+      const double h1 = (dm <= 1e-15) ? fmax(1e-6, h0 * 1e-3) : pow(0.01 / dm, ex);
       c->h = fmin(fmin(100.0 * h0, h1), c->h_max);
       c->ha = fmin(c->h, c->t1 - c->t);
       break;
@@ -1651,7 +1659,7 @@ __device__ __forceinline__ bool finalize(const Args& a, Ctl* c, double m0, doubl
       }
       return want;
     }
-    case ST_D7: {  // a Dormand-Prince 5(4) attempt: estimate O(h^5), exponent 1/5
+    case ST_D7: {  // a seven-stage attempt (DP5(4) or RKF4(5)): estimate O(h^5), exponent 1/5
       const double E = m0;
       const double ha = c->ha;
       c->n_fev += 6;
@@ -1808,7 +1816,7 @@ __device__ __forceinline__ void finalize_block(const Args& a, int blk) {
   if (sc.status != kRunning) return;
   if (i < a.n) {
     const double x = xc[sc.xi], k1 = kc[sc.ki];
-    const double a21 = sc.method ? kDpA[1][0] : kA21;
+    const double a21 = sc.method == 1 ? kDpA[1][0] : sc.method == 2 ? kFeA[1][0] : kA21;
     const double y = (s_next == ST_H0) ? x + sc.h0probe * k1 : sstore(a, x + sc.ha * (a21 * k1));
     write_operand(a, 0, i, y);
   }
