@@ -14,11 +14,18 @@ one (i, j) term of one right-hand-side evaluation (n_fev * N^2 per solve).
 
 Also reported: time-to-t_end of each precision mode next to plain FP64, the
 normalized final error ||y - y_ref||_2 / sqrt(N) (paper eq. (Metric)) against an
-FP64 reference at a tight tolerance, the roofline of the contraction kernel
-(algorithmic bytes N^2 * bytes(A) per launch over its event-timed mean
-duration, and the HBM traffic the PMC counters measured for the same kernel
-when the committed summary matches the kernel sources), and the CPU oracle
-timed on a bounded sample.
+FP64 reference at a tight tolerance (the oracle's Dormand-Prince 5(4) solution at
+rtol 1e-12 for the default workload, tests/golden/kuramoto_n4096_ref.npy, with
+the GPU's own FP64 Dormand-Prince 5(4) reference and its distance to the
+oracle's; the GPU reference elsewhere), each reduced mode's error split into a
+storage part (the reference integrator on the dequantized stored matrix against
+the reference on A) and an arithmetic part (the mode against the reference on
+the dequantized matrix), a tolerance sweep 1e-4 .. 1e-8 of FP64, FP32 and BF16
+(default workload), the roofline of the contraction kernel (algorithmic bytes
+N^2 * bytes(A) per launch over its event-timed mean duration, whether the matrix
+fits the Infinity Cache, and the HBM traffic the PMC counters measured for the
+same kernel when the committed summary matches the kernel sources), and the
+CPU oracle timed on a bounded sample.
 
 Other measurement configurations, one JSON line each:
   c3  Goodwin clock network N = 16384 (state 49152), t in [0, 500],
@@ -89,13 +96,17 @@ def parse():
     ap.add_argument("--ref-rtol", type=float, default=None, help="tolerance of the FP64 reference solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ref", action="store_true", help="skip the reference solution")
+    ap.add_argument("--no-attribution", action="store_true",
+                    help="skip the storage / arithmetic split of each reduced mode's error")
+    ap.add_argument("--sweep", action=argparse.BooleanOptionalAction, default=None,
+                    help="tolerance sweep 1e-4 .. 1e-8 (FP64, FP32, BF16; default on for c2)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB of a plain device copy run first (calibrates PMC byte counters)")
     ap.add_argument("--instances", type=int, default=None, help="c4 / f3: ensemble size (512 / 256)")
     ap.add_argument("--no-graph", action="store_true", help="launch attempts directly instead of from HIP graphs")
-    ap.add_argument("--method", default="bs32", choices=["bs32", "dp54"],
-                    help="single-system configs: the embedded pair (dp54: Dormand-Prince 5(4), modes 0-4)")
+    ap.add_argument("--method", default="bs32", choices=["bs32", "dp54", "rkf45"],
+                    help="single-system configs: the embedded pair (dp54: Dormand-Prince 5(4), rkf45: Fehlberg 4(5); modes 0-4)")
     return ap.parse_args()
 
 
@@ -199,14 +210,19 @@ def base_line(args, value, ms_per_step, dtype, config):
             "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
 
 
-# vector-ALU peaks of MI355X in lane-operations per second (an FMA counts once):
-# FP32 157.3 TFLOP/s and FP64 78.6 TFLOP/s of fused multiply-adds
-VALU_PEAK = {"f32": 157.3e12 / 2, "f64": 78.6e12 / 2}
+# vector-ALU issue peak of MI355X in lane-cycles per second: 256 CUs x 4 SIMDs x 16
+# lanes x 2.4 GHz = 39.3e12, one FP32 or FP64 instruction per lane per cycle (packed
+# FP32 is not used: the published 157.3 TFLOP/s FP32 counts packed FMAs, 4 flops per
+# lane-cycle, and 78.6 TFLOP/s FP64 an FMA, 2 flops).  Transcendental instructions
+# (reciprocal, square root, ...) issue at a quarter of that rate and count 4 cycles.
+VALU_PEAK = {"f32": 256 * 4 * 16 * 2.4e9, "f64": 256 * 4 * 16 * 2.4e9}
 
 
 def valu_ops_per_pair(workload, kernel):
-    """VALU lane-operations per pair evaluation of a pairwise kernel instance, from the
-    committed PMC summary (SQ_INSTS_VALU x 64 / pairs), or None."""
+    """VALU issue lane-cycles per pair evaluation of a pairwise kernel instance, from the
+    committed PMC summary ((SQ_INSTS_VALU + 3 SQ_INSTS_VALU_TRANS_F32 + 3
+    SQ_INSTS_VALU_TRANS_F64) x 64 / pairs: a transcendental occupies four issue
+    cycles), or None."""
     path = os.path.join(ROOT, "profiles", f"valu_{workload}.md")
     if not os.path.exists(path):
         return None
@@ -233,15 +249,23 @@ def alu_roofline(workload, rh, n):
     pairs_per_s = n * n / (rh["contraction_ms"] * 1e-3)
     ach = None if ops is None else pairs_per_s * ops
     return dict(bound="alu", achieved=None if ach is None else round(ach / 1e12, 3),
-                peak=round(VALU_PEAK[prec] / 1e12, 2), unit="T VALU lane-ops/s",
+                peak=round(VALU_PEAK[prec] / 1e12, 2), unit="T VALU lane-cycles/s",
                 frac=None if ach is None else round(ach / VALU_PEAK[prec], 4), traffic=None, kernel=rh["kernel"],
                 pair_evaluations_per_s=pairs_per_s, valu_ops_per_pair=ops, avg_launch_ms=rh["contraction_ms"])
 
 
+MALL_BYTES = 256 << 20  # Infinity Cache of MI355X
+
+
 def roofline(kms, bytes_per_launch, kernel, traffic):
     gbs = bytes_per_launch / (kms * 1e-3) / 1e9
+    # a matrix that fits the 256 MB Infinity Cache stays there across the launches of a
+    # solve: the stream is then served from that cache, and 8 TB/s is the stated HBM
+    # ceiling rather than the one that binds
+    resident = bytes_per_launch <= MALL_BYTES
     return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4),
-                traffic=traffic, kernel=kernel, bytes_per_launch=bytes_per_launch, avg_launch_ms=kms)
+                traffic=traffic, kernel=kernel, bytes_per_launch=bytes_per_launch, avg_launch_ms=kms,
+                residency="infinity-cache" if resident else "hbm")
 
 
 # ---------------------------------------------------------------------------
@@ -457,8 +481,8 @@ def bench_single(args, torch, bs, workload, w, modes, ref_rtol):
     s = bs.Solver(0)
     if args.no_graph:
         s.set_options(use_graph=0)
-    if args.method == "dp54":
-        s.set_options(method=bs.METHOD_DP54)
+    if args.method != "bs32":
+        s.set_options(method=bs.METHOD_DP54 if args.method == "dp54" else bs.METHOD_RKF45)
         modes = [m for m in modes if m < 5]
     A = dev_t(w["A"])
     torch.cuda.synchronize()
@@ -468,20 +492,26 @@ def bench_single(args, torch, bs, workload, w, modes, ref_rtol):
     setup_ms = (time.perf_counter() - t_setup) * 1e3
     del A
 
-    ref = None
+    ref, ref_info = None, None
     if not args.no_ref:
-        log(f"reference solve (FP64, rtol={ref_rtol:g}) n={n}")
-        s.set_options(i_max=10_000_000)
-        ref_t = torch.empty_like(y0)
-        _, rst = s.solve(y0, 0.0, t1, ref_rtol, ref_rtol, mode=bs.PREC_FP64, out=ref_t)
-        s.set_options(i_max=100000)
-        ref = ref_t.cpu().numpy()
+        log(f"reference solve (GPU FP64 Dormand-Prince 5(4), rtol={ref_rtol:g}) n={n}")
+        ref_gpu, rst = reference_solve(bs, torch, w, dev_t(w["A"]), ref_rtol, pairwise)
         log(f"  reference: {rst['n_accept']} accepted, {rst['solve_ms'] / 1e3:.1f} s, status {rst['status']}")
+        ref, ref_info = ref_gpu, {"reference": f"GPU FP64 Dormand-Prince 5(4), rtol=atol={ref_rtol:g}"}
+        golden = GOLDEN_REF.get((workload, float(t1), w.get("seed")))
+        if golden is not None and os.path.exists(golden):
+            ref_o = np.load(golden)
+            ref = ref_o
+            ref_info = {"reference": "oracle FP64 Dormand-Prince 5(4), rtol=atol=1e-12 (" +
+                                     os.path.relpath(golden, ROOT) + ")",
+                        "gpu_reference": ref_info["reference"],
+                        "gpu_reference_rel_l2_vs_oracle": float(np.linalg.norm(ref_gpu - ref_o) / np.linalg.norm(ref_o))}
+            log(f"  oracle reference: GPU reference differs by {ref_info['gpu_reference_rel_l2_vs_oracle']:.3e}")
 
     def final_err(y):
         return None if ref is None else float(np.linalg.norm(y - ref) / math.sqrt(n))
 
-    results = {}
+    results, ys = {}, {}
     for mode in sorted(set([0] + modes)):
         log(f"mode {bs.MODE_NAMES[mode]}: {args.warmup} warm-up + {args.steps} timed solves")
         fmt_bytes = BYTES[1] if mode >= 5 else BYTES[mode]
@@ -499,6 +529,7 @@ def bench_single(args, torch, bs, workload, w, modes, ref_rtol):
             times.append(time.perf_counter() - t0)
             pairs += stats["pair_interactions"]
         y = out.cpu().numpy()
+        ys[mode] = y
         kms = s.time_contraction(mode, repeat=100)
         gbs = n * n * fmt_bytes / (kms * 1e-3) / 1e9
         results[mode] = dict(
@@ -527,6 +558,50 @@ def bench_single(args, torch, bs, workload, w, modes, ref_rtol):
         traffic = traffic_lookup(workload, "rhs_fp32" if head >= 5 else rh["name"], rh["kernel"])
         roof = roofline(rh["contraction_ms"], n * n * rh["fmt_bytes"], rh["kernel"], traffic)
 
+    # storage versus arithmetic (eq. (Metric) errors): each reduced mode against the same
+    # reference integrator run on the dequantized stored matrix (A_hat = s Q(A/s))
+    attribution = None
+    if ref is not None and not pairwise and n <= 8192 and not args.no_attribution:
+        attribution = {}
+        refs_hat = {}
+        for mode in sorted(results):
+            if mode == 0 or mode == 8:
+                continue
+            sm = 1 if mode >= 5 else mode  # the recipes store A in FP32
+            if sm not in refs_hat:
+                bits, scale = s.packed_coupling(sm)
+                A_hat = torch.from_numpy(dequantize(np, bits, sm) * scale).to(dev)
+                log(f"reference solve on the dequantized {bs.MODE_NAMES[sm]} matrix")
+                refs_hat[sm], _ = reference_solve(bs, torch, w, A_hat, ref_rtol, pairwise)
+                del A_hat
+            r_hat = refs_hat[sm]
+            attribution[results[mode]["name"]] = {
+                "final_error": results[mode]["final_error"],
+                "storage_error": float(np.linalg.norm(r_hat - ref) / math.sqrt(n)),
+                "arithmetic_error": float(np.linalg.norm(ys[mode] - r_hat) / math.sqrt(n))}
+        attribution["fp64"] = {"final_error": r0["final_error"], "storage_error": 0.0,
+                               "arithmetic_error": r0["final_error"]}
+
+    # work-precision: time to t_end and final error over the tolerance sweep
+    sweep = None
+    if ref is not None and args.sweep:
+        sweep = []
+        for rt in (1e-4, 1e-5, 1e-6, 1e-7, 1e-8):
+            for mode in [m for m in (0, 1, 2) if m in results]:
+                s.solve(y0, 0.0, t1, rt, mode=mode, out=out)
+                times = []
+                for _ in range(3):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    _, st = s.solve(y0, 0.0, t1, rt, mode=mode, out=out)
+                    torch.cuda.synchronize()
+                    times.append(time.perf_counter() - t0)
+                e = float(np.linalg.norm(out.cpu().numpy() - ref) / math.sqrt(n))
+                sweep.append({"rtol": rt, "mode": bs.MODE_NAMES[mode], "time_to_t_end_s": float(np.median(times)),
+                              "final_error": e, "accepted": int(st["n_accept"]), "rejected": int(st["n_reject"]),
+                              "status": int(st["status"])})
+                log(f"  sweep rtol {rt:g} {bs.MODE_NAMES[mode]}: {np.median(times) * 1e3:.2f} ms, error {e:.3e}")
+
     cpu = None
     if not args.no_cpu:
         log(f"CPU oracle baseline (~{args.cpu_seconds:g} s)")
@@ -534,7 +609,8 @@ def bench_single(args, torch, bs, workload, w, modes, ref_rtol):
 
     line = base_line(args, rh["pairs_per_s"], rh["ms_per_step"],
                      ("f32-recipe" if head >= 5 else DTYPE[head] + "+f64-update"),
-                     {"workload": workload_desc(workload, w) + (" pair=dormand-prince-5(4)" if args.method == "dp54" else ""),
+                     {"workload": workload_desc(workload, w) + {"bs32": "", "dp54": " pair=dormand-prince-5(4)",
+                                                                  "rkf45": " pair=fehlberg-4(5)"}[args.method],
                       "precision_mode": rh["name"], "global_batch": 1,
                       "seq_len": None})
     line.update({
@@ -544,6 +620,7 @@ def bench_single(args, torch, bs, workload, w, modes, ref_rtol):
         "final_error": rh["final_error"],
         "fp64_final_error": r0["final_error"],
         "reference_rtol": None if ref is None else ref_rtol,
+        "reference": ref_info,
         "matched_error": (None if rh["final_error"] is None else rh["final_error"] <= 2.0 * r0["final_error"]),
         "accepted_steps_per_s": rh["accepted_steps_per_s"],
         "beta": (r0["accepted"] + r0["rejected"]) / max(1, rh["accepted"] + rh["rejected"]),
@@ -555,8 +632,54 @@ def bench_single(args, torch, bs, workload, w, modes, ref_rtol):
         "roofline": roof,
         "cpu_baseline": cpu,
     })
+    if attribution is not None:
+        line["error_attribution"] = attribution
+    if sweep is not None:
+        line["rtol_sweep"] = sweep
     s.close()
     return line
+
+
+# oracle references written by tests/golden/make_kuramoto_reference.py, by (workload, t1, seed)
+GOLDEN_REF = {("kuramoto_n4096", 50.0, 2000): os.path.join(ROOT, "tests", "golden", "kuramoto_n4096_ref.npy")}
+
+
+def reference_solve(bs, torch, w, A, rtol, pairwise):
+    """FP64 Dormand-Prince 5(4) solve of w with coupling A (a device tensor) at rtol = atol
+    on a context of its own; returns (y at t1 as numpy, stats)."""
+    dev = torch.device("cuda:0")
+
+    def dev_t(x):
+        if x is None:
+            return None
+        return x.to(dev) if hasattr(x, "to") else torch.from_numpy(x).to(dev)
+
+    r = bs.Solver(0)
+    try:
+        r.set_options(i_max=10_000_000, method=bs.METHOD_DP54)
+        r.set_system(w["kind"], w["n"], A, dev_t(w["param"]), w["gain"], w.get("stimulus", 0.0), pairwise)
+        y0 = dev_t(w["y0"])
+        out = torch.empty_like(y0)
+        _, st = r.solve(y0, 0.0, w["t1"], rtol, rtol, mode=bs.PREC_FP64, out=out)
+        return out.cpu().numpy(), st
+    finally:
+        r.close()
+
+
+def dequantize(np, bits, mode):
+    """Stored values of a packed matrix (bs32_get_packed_coupling) as FP64, before the scale."""
+    if mode == 1:
+        return bits.astype(np.float64)
+    if mode == 2:
+        return (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    if mode == 3:
+        return bits.view(np.float16).astype(np.float64)
+    # OCP e4m3fn: sign, 4 exponent bits (bias 7), 3 fraction bits; S.1111.111 is NaN
+    b = np.arange(256)
+    e, f = (b >> 3) & 15, b & 7
+    val = np.where(e == 0, f * 2.0**-9, (8 + f) * np.exp2(e - 10.0))
+    val = np.where((e == 15) & (f == 7), np.nan, val) * np.where(b >> 7, -1.0, 1.0)
+    return val[bits]
 
 
 def workload_desc(workload, w):
@@ -609,7 +732,7 @@ def bench_ensemble(args, torch, bs, modes, ref_rtol):
     torch.cuda.empty_cache()
     out = torch.empty_like(y0)
 
-    results = {}
+    results, ys = {}, {}
     for mode in sorted(set([0] + modes)):
         log(f"mode {bs.MODE_NAMES[mode]}: {args.warmup} warm-up + {args.steps} timed batch solves")
         for _ in range(args.warmup):
@@ -950,6 +1073,8 @@ def main():
     dev = torch.device("cuda:0")
     calib_copy(torch, dev, args.calib_copy)
     modes = None if args.modes is None else [int(m) for m in args.modes.split(",") if m != ""]
+    if args.sweep is None:
+        args.sweep = args.config == "c2"
     if args.config == "c2":
         n = args.n or 4096
         w = workloads.kuramoto(n, seed=2000, K=2.0, t1=args.t1 or 50.0, rtol=args.rtol or 1e-6)
