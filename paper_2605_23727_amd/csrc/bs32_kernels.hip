@@ -1993,6 +1993,11 @@ int tile_kalign(int fmt, const Tile& t) {
   X(1, 1, 8, 2, 0) X(1, 1, 8, 4, 0) X(1, 1, 8, 8, 0) X(2, 1, 8, 4, 0) X(1, 1, 4, 8, 0) X(2, 1, 4, 4, 0) \
   X(1, 1, 8, 4, 1) X(2, 1, 8, 4, 1) X(1, 1, 4, 4, 0) X(1, 1, 4, 8, 1) X(1, 1, 8, 8, 1)
 
+// the matrix-core tiles that also run with an epilogue wave: one 16-row tile per wave and
+// batches of at most four steps (the others would spill with the extra wave's share of
+// the register file)
+#define BS32_MMA_EW_OK(R_, U_) ((R_) == 1 && (U_) <= 4)
+
 // pairwise kernels: (R rows per wave, WV waves, UJ column chunks per step)
 #define BS32_PAIR_TILES(X) X(2, 4, 1) X(4, 4, 1) X(8, 4, 1) X(4, 4, 2)
 
@@ -2004,7 +2009,13 @@ int tile_kalign(int fmt, const Tile& t) {
 #define BS32_TILE_VALU(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 0},
 #define BS32_TILE_MMA(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 1},
 #define BS32_TILE_VALU_EW(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 0, 1},
-#define BS32_TILE_MMA_EW(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 1, 1},
+#define BS32_TILE_MMA_EW(R_, WR_, WK_, U_, NT_) BS32_TILE_MMA_EW_##R_##_##U_(R_, WR_, WK_, U_, NT_)
+#define BS32_TILE_MMA_EW_1_2(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 1, 1},
+#define BS32_TILE_MMA_EW_1_4(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 1, 1},
+#define BS32_TILE_MMA_EW_1_8(R_, WR_, WK_, U_, NT_)
+#define BS32_TILE_MMA_EW_2_2(R_, WR_, WK_, U_, NT_)
+#define BS32_TILE_MMA_EW_2_4(R_, WR_, WK_, U_, NT_)
+#define BS32_TILE_MMA_EW_2_8(R_, WR_, WK_, U_, NT_)
 // every tile, then (single systems only) the same tiles with an epilogue wave
 static const Tile kF64Tiles[] = {BS32_F64_TILES(BS32_TILE_VALU) BS32_F64_TILES(BS32_TILE_VALU_EW)};
 static const Tile kF32Tiles[] = {BS32_F32_TILES(BS32_TILE_VALU) BS32_MMA_TILES(BS32_TILE_MMA)
@@ -2021,6 +2032,12 @@ static const Tile kSharedTiles[] = {BS32_SHARED_TILES(BS32_TILE_SHARED) Tile{1, 
 #undef BS32_TILE_MMA
 #undef BS32_TILE_VALU_EW
 #undef BS32_TILE_MMA_EW
+#undef BS32_TILE_MMA_EW_1_2
+#undef BS32_TILE_MMA_EW_1_4
+#undef BS32_TILE_MMA_EW_1_8
+#undef BS32_TILE_MMA_EW_2_2
+#undef BS32_TILE_MMA_EW_2_4
+#undef BS32_TILE_MMA_EW_2_8
 
 const Tile* pair_tile_candidates(int* count) {
   *count = (int)(sizeof(kPairTiles) / sizeof(Tile));
@@ -2123,12 +2140,21 @@ hipError_t launch_shared_contract(const Shared& sh, int m, int fmt, const Tile& 
 #endif
 // THREADS: the tile's streaming waves; a single-system kernel with an epilogue wave
 // (tile EW) has one more, and the grouped kernels have none
-#define BS32_LAUNCH(SINGLE_EW, SINGLE, GROUP, THREADS)                                           \
+#define BS32_LAUNCH(SINGLE_EW, SINGLE, GROUP, THREADS) BS32_LAUNCH_IF(true, SINGLE_EW, SINGLE, GROUP, THREADS)
+#define BS32_LAUNCH_IF(EWOK, SINGLE_EW, SINGLE, GROUP, THREADS)                                  \
   if (L.g && t.EW) return hipErrorInvalidValue;                                                  \
-  if (!L.dry) {                                                                                  \
-    if (L.g) GROUP<<<L.ggrid, THREADS, 0, L.s>>>(*L.g);                                          \
-    else if (t.EW) SINGLE_EW<<<(unsigned)L.a->nrb, THREADS + 64, 0, L.s>>>(*L.a);                \
-    else SINGLE<<<(unsigned)L.a->nrb, THREADS, 0, L.s>>>(*L.a);                                  \
+  if constexpr (!(EWOK)) {                                                                       \
+    if (t.EW) return hipErrorInvalidValue;                                                       \
+    if (!L.dry) {                                                                                \
+      if (L.g) GROUP<<<L.ggrid, THREADS, 0, L.s>>>(*L.g);                                        \
+      else SINGLE<<<(unsigned)L.a->nrb, THREADS, 0, L.s>>>(*L.a);                                \
+    }                                                                                            \
+  } else {                                                                                       \
+    if (!L.dry) {                                                                                \
+      if (L.g) GROUP<<<L.ggrid, THREADS, 0, L.s>>>(*L.g);                                        \
+      else if (t.EW) SINGLE_EW<<<(unsigned)L.a->nrb, THREADS + 64, 0, L.s>>>(*L.a);              \
+      else SINGLE<<<(unsigned)L.a->nrb, THREADS, 0, L.s>>>(*L.a);                                \
+    }                                                                                            \
   }                                                                                              \
   return L.dry ? hipSuccess : hipGetLastError();
 
@@ -2168,9 +2194,9 @@ template <int FMT, int M, int T>
 hipError_t launch_mma(const Launch& L, const Tile& t) {
 #define X(R_, WR_, WK_, U_, NT_)                                                            \
   if (t.R == R_ && t.WR == WR_ && t.WK == WK_ && t.U == U_ && t.NT == NT_) {                \
-    BS32_LAUNCH((k_contract_mfma<FMT, M, T, R_, WR_, WK_, U_, NT_, true>),                  \
-                (k_contract_mfma<FMT, M, T, R_, WR_, WK_, U_, NT_, false>),                 \
-                (k_group_mfma<FMT, M, T, R_, WR_, WK_, U_, NT_>), WR_ * WK_ * 64)           \
+    BS32_LAUNCH_IF(BS32_MMA_EW_OK(R_, U_), (k_contract_mfma<FMT, M, T, R_, WR_, WK_, U_, NT_, true>), \
+                   (k_contract_mfma<FMT, M, T, R_, WR_, WK_, U_, NT_, false>),                 \
+                   (k_group_mfma<FMT, M, T, R_, WR_, WK_, U_, NT_>), WR_ * WK_ * 64)           \
   }
   BS32_MMA_TILES(X)
 #undef X
