@@ -217,3 +217,50 @@ def test_ensemble_with_learned_proposer_matches_single(bs):
         single.close()
     finally:
         s.set_options(tile=-1)
+
+
+def _safety_traces(b, s, seeds, rtols, n=384, t1=10.0):
+    """Traces at three controller safety factors, so that the features cover steps on
+    both sides of the classical choice (the labels are the steps that would have put
+    the next estimate at 0.8 Rel)."""
+    F, Y = [], []
+    for sd in seeds:
+        w = _kur(n, sd, t1=t1)
+        s.set_workload(w)
+        for rtol in rtols:
+            for safety in (0.75, 0.9, 0.97):
+                s.set_options(trace=1, trace_cap=1 << 18, safety=safety)
+                s.solve(w["y0"], 0.0, t1, rtol)
+                f, y = b.mlp_features(s.trace(), rtol)
+                F.append(f)
+                Y.append(y)
+    s.set_options(trace=0, safety=0.9)
+    return np.concatenate(F), np.concatenate(Y)
+
+
+def test_trained_proposer_saves_evaluations_on_held_out_system(bs, orc):
+    """Trained on traces of two Kuramoto systems, the proposer solves a held-out one
+    (another seed and size) with fewer RHS evaluations than the standard controller,
+    at a final error within 2x of the standard controller's against the oracle's
+    Dormand-Prince 5(4) solution at rtol 1e-12; the estimate alone decides acceptance."""
+    b, s = bs
+    F, Y = _safety_traces(b, s, [2501, 2502], [1e-6, 1e-7, 1e-8])
+    W, losses = s.mlp_train(F, Y, epochs=40, batch=256, lr=1e-3, seed=5)
+    say(f"[mlp gain] {len(F)} samples, loss {losses[0]:.3g} -> {losses[-1]:.3g}")
+    rtol = 1e-7
+    w = _kur(640, 2599, t1=20.0)
+    y0, st0, _ = _gpu_solve(s, w, rtol)
+    y1, st1, tr = _gpu_solve(s, w, rtol, W)
+    ref, rst = orc.dp54_solve(w["kind"], w["n"], w["y0"], 0.0, w["t1"], 1e-12, A=w["A"], param=w["param"],
+                              gain=w["gain"], i_max=10_000_000)
+    assert rst["status"] == 0
+    e0 = np.linalg.norm(y0 - ref) / math.sqrt(w["n"])
+    e1 = np.linalg.norm(y1 - ref) / math.sqrt(w["n"])
+    say(f"[mlp gain] RHS evaluations standard {st0['n_fev']} learned {st1['n_fev']} "
+        f"({100.0 * (1.0 - st1['n_fev'] / st0['n_fev']):.1f} % fewer); rejected {st0['n_reject']} / {st1['n_reject']}; "
+        f"steps chosen by the network {st1['n_learned']}; error {e0:.3e} / {e1:.3e}")
+    assert st0["status"] == 0 and st1["status"] == 0
+    assert st1["n_learned"] > 0
+    assert np.all(tr["err"][tr["accepted"] == 1] < rtol)
+    assert st1["n_fev"] < st0["n_fev"]
+    assert e1 <= 2.0 * e0
