@@ -68,6 +68,7 @@ std::vector<Tile> candidates(int fmt) {
 struct Geom {
   Tile t;
   int RB, nrb, KW;
+  long long kn;
 };
 
 }  // namespace
@@ -261,8 +262,11 @@ Geom geometry(const bs32_ctx* c, int fmt, const Tile& t) {
   Geom g;
   g.t = t;
   g.RB = tile_rows(fmt, t);
-  g.nrb = (int)((c->np + g.RB - 1) / g.RB);
-  g.KW = (int)roundup((c->ld + t.WK - 1) / t.WK, tile_kalign(fmt, t));
+  // row blocks that hold a row below n, and columns up to n rounded to the tile's k
+  // step: the zero padding of the stored matrix beyond them is never streamed
+  g.nrb = (int)((c->n + g.RB - 1) / g.RB);
+  g.kn = std::min<long long>(c->ld, roundup(c->n, tile_kalign(fmt, t)));
+  g.KW = (int)roundup((g.kn + t.WK - 1) / t.WK, tile_kalign(fmt, t));
   return g;
 }
 
@@ -342,6 +346,7 @@ Args make_args(bs32_ctx* c, int fmt, const Geom& g, int stage) {
   a.nrb = g.nrb;
   a.RB = g.RB;
   a.KW = g.KW;
+  a.kn = g.kn;
   a.pair = c->opt.method;
   return a;
 }

@@ -128,6 +128,7 @@ struct Args {
   double gain, invN, scale; // coupling gain, 1/N, per-tensor scale of A (power of two)
   double vmax;            // largest magnitude the vector terms may hold (format range check)
   long long n, np, ld;    // agents, padded rows, leading dimension (elements)
+  long long kn;           // columns the contraction streams: n rounded up to the tile's k step (<= ld)
   int kind, d, m;         // system kind, components per agent, vector columns
   int stage;
   int nrb;                // row blocks (workgroups of the contraction)
@@ -158,6 +159,7 @@ struct Group {
   const Args* inst;       // [(instance * kStages + stage) * 2 + parity]
   const Item* items;      // live work items
   const unsigned* count;  // number of live items
+  const unsigned* xs;     // contraction lists: item ranges of the 8 XCDs, xs[x] .. xs[x + 1]
   int stage, par;
 };
 

@@ -734,13 +734,13 @@ __device__ __forceinline__ void contract_f64(const Args& a, int rb) {
   if (EW && w == WR * WK) {
     prefetch_row<F_F64>(a, rb, RB, rin, TB);
   } else {
-    if constexpr (!EW) prefetch_row<F_F64>(a, rb, RB, rin);
+    if constexpr (!EW && DP) prefetch_row<F_F64>(a, rb, RB, rin);
     const int wr = w % WR, wk = w / WR;
     const long long row0 = (long long)rb * RB + wr * R;
     const double* __restrict__ Ab = (const double*)a.A + row0 * a.ld;
     const double* __restrict__ V = pick2(a.V64, vin_of(a.stage));
     const long long jb = (long long)wk * a.KW;
-    const long long je = min(jb + (long long)a.KW, a.ld);
+    const long long je = min(jb + (long long)a.KW, a.kn);
     double acc[R][M];
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -801,6 +801,7 @@ __device__ __forceinline__ void contract_f64(const Args& a, int rb) {
       }
   }
   __syncthreads();
+  if constexpr (!DP) prefetch_row<F_F64>(a, rb, RB, rin);  // grouped kernels: after the stream
   for (int e = threadIdx.x; e < RB * M; e += blockDim.x) {
     double s = 0.0;
     for (int q = 0; q < WK; ++q) s += sPart[q][e / M][e % M];
@@ -828,13 +829,13 @@ __device__ __forceinline__ void contract_f32(const Args& a, int rb) {
   if (EW && w == WR * WK) {
     prefetch_row<F_F32>(a, rb, RB, rin, TB);
   } else {
-    if constexpr (!EW) prefetch_row<F_F32>(a, rb, RB, rin);
+    if constexpr (!EW && DP) prefetch_row<F_F32>(a, rb, RB, rin);
     const int wr = w % WR, wk = w / WR;
     const long long row0 = (long long)rb * RB + wr * R;
     const float* __restrict__ Ab = (const float*)a.A + row0 * a.ld;
     const float* __restrict__ Vq = (const float*)pick2(a.Vq, vin_of(a.stage));
     const long long jb = (long long)wk * a.KW;
-    const long long je = min(jb + (long long)a.KW, a.ld);
+    const long long je = min(jb + (long long)a.KW, a.kn);
     double acc[R][NC];
     float accf[R][NC];  // the recipes' single sum
 #pragma unroll
@@ -886,6 +887,7 @@ __device__ __forceinline__ void contract_f32(const Args& a, int rb) {
       }
   }
   __syncthreads();
+  if constexpr (!DP) prefetch_row<F_F32>(a, rb, RB, rin);  // grouped kernels: after the stream
   for (int e = threadIdx.x; e < RB * M; e += blockDim.x) {
     const int row = e / M, cc = e % M;
     double p = 0.0;
@@ -958,6 +960,7 @@ __device__ __forceinline__ void contract_mfma(const Args& a, int rb) {
   static_assert(NC <= 16, "vector terms exceed the MFMA tile width");
   constexpr int RB = 16 * RT * WR;
   static_assert(!EW || 2 * RB <= 64, "the epilogue wave holds every row of the block");
+  static_assert(EW || WR * WK * 64 >= 2 * RB, "the tail needs two threads per row (one per operand column)");
   constexpr int TB = EW ? WR * WK * 64 : 0;  // first tail thread (EW: the epilogue wave, see contract_f64)
   constexpr int ES = (FMT == F_E4M3) ? 1 : (FMT == F_F32) ? 4 : 2;  // bytes per element
   constexpr int KC = 8;                        // k-groups kept in FP32 before an FP64 flush
@@ -980,7 +983,7 @@ __device__ __forceinline__ void contract_mfma(const Args& a, int rb) {
     const int r16 = lane & 15, g = lane >> 4;
     const long long row_base = (long long)rb * RB + wr * 16 * RT;
     const long long kb = (long long)wk * a.KW;
-    const long long ke = min(kb + (long long)a.KW, a.ld);
+    const long long ke = min(kb + (long long)a.KW, a.kn);
     const char* Ab = (const char*)a.A;
     const bool bcol = r16 < NC;
     const char* bp = (const char*)pick2(a.Vq, vin_of(a.stage)) + ((long long)(bcol ? r16 : 0) * a.ld + kb) * ES + g * 16;
@@ -1053,7 +1056,7 @@ __device__ __forceinline__ void contract_mfma(const Args& a, int rb) {
     // of a finished solve must cost no more than their launch).
     if (full > 0) load(a0, b0, 0);
     if (a.ctl->status != kRunning) return;
-    if constexpr (!EW) prefetch_row<FMT>(a, rb, RB, rin);
+    if constexpr (!EW && DP) prefetch_row<FMT>(a, rb, RB, rin);
     while (off < full) {
       if (off + BATCH < full) load(a1, b1, off + BATCH);
       step(a0, b0);
@@ -1084,6 +1087,7 @@ __device__ __forceinline__ void contract_mfma(const Args& a, int rb) {
     }
   }
   __syncthreads();
+  if constexpr (!DP) prefetch_row<FMT>(a, rb, RB, rin);  // grouped kernels: after the stream
   for (int e = threadIdx.x; e < RB * M; e += blockDim.x) {
     const int row = e / M, cc = e % M;
     double p = 0.0;
@@ -1209,6 +1213,18 @@ __device__ __forceinline__ const Args& group_args(const Group& g, const Item& w)
     BODY(group_args(g, w_), (int)w_.blk);                           \
     __syncthreads();                                                \
   }
+// Contraction lists: workgroups are dispatched to the 8 XCDs in turn (block b to XCD
+// b % 8), so the workgroups of XCD x walk their own contiguous range of the list, which
+// the host balances by streamed bytes.  An instance's operand then stays in the L2 of
+// one XCD (two where a range boundary splits it).  Grids are whole multiples of 8.
+#define BS32_GROUP_LOOP_X(BODY)                                                     \
+  const unsigned x_ = blockIdx.x & 7u, per_ = gridDim.x >> 3;                       \
+  const unsigned end_ = g.xs[x_ + 1];                                               \
+  for (unsigned it_ = g.xs[x_] + (blockIdx.x >> 3); it_ < end_; it_ += per_) {      \
+    const Item w_ = g.items[it_];                                                   \
+    BODY(group_args(g, w_), (int)w_.blk);                                           \
+    __syncthreads();                                                                \
+  }
 
 // EW: a single-system kernel with one more wave than the tile's streaming waves,
 // the epilogue wave (see contract_f64); the autotuner tries both forms
@@ -1218,7 +1234,7 @@ __global__ __launch_bounds__(WR* WK * 64 + (EW ? 64 : 0)) void k_contract_f64(Ar
 }
 template <int M, int R, int WR, int WK, int U, bool NT>
 __global__ __launch_bounds__(WR* WK * 64) void k_group_f64(Group g) {
-  BS32_GROUP_LOOP((contract_f64<M, R, WR, WK, U, NT, false>))
+  BS32_GROUP_LOOP_X((contract_f64<M, R, WR, WK, U, NT, false>))
 }
 template <int M, int T, int R, int WR, int WK, int U, bool NT, bool EW>
 __global__ __launch_bounds__(WR* WK * 64 + (EW ? 64 : 0)) void k_contract_f32(Args a) {
@@ -1226,15 +1242,22 @@ __global__ __launch_bounds__(WR* WK * 64 + (EW ? 64 : 0)) void k_contract_f32(Ar
 }
 template <int M, int T, int R, int WR, int WK, int U, bool NT>
 __global__ __launch_bounds__(WR* WK * 64) void k_group_f32(Group g) {
-  BS32_GROUP_LOOP((contract_f32<M, T, R, WR, WK, U, NT, false>))
+  BS32_GROUP_LOOP_X((contract_f32<M, T, R, WR, WK, U, NT, false>))
 }
 template <int FMT, int M, int T, int RT, int WR, int WK, int U, bool NT, bool EW>
 __global__ __launch_bounds__(WR* WK * 64 + (EW ? 64 : 0)) void k_contract_mfma(Args a) {
   contract_mfma<FMT, M, T, RT, WR, WK, U, NT, true, EW>(a, block_row(a));
 }
+// Two workgroups per CU for tiles of at most four waves: with the row epilogue's loads
+// after the stream (DP = false) every such tile fits in 256 registers per lane without
+// spilling.  Tiles of eight waves ask for one.
+template <int RT, int WR, int WK, int U>
+constexpr int group_mfma_blocks() {
+  return WR * WK <= 4 ? 2 : 1;
+}
 template <int FMT, int M, int T, int RT, int WR, int WK, int U, bool NT>
-__global__ __launch_bounds__(WR* WK * 64, 2) void k_group_mfma(Group g) {
-  BS32_GROUP_LOOP((contract_mfma<FMT, M, T, RT, WR, WK, U, NT, false>))
+__global__ __launch_bounds__(WR* WK * 64, (group_mfma_blocks<RT, WR, WK, U>())) void k_group_mfma(Group g) {
+  BS32_GROUP_LOOP_X((contract_mfma<FMT, M, T, RT, WR, WK, U, NT, false>))
 }
 template <bool ATAN, bool G32, bool DENSE, int R, int WV, int UJ>
 __global__ __launch_bounds__(WV * 64) void k_contract_pair(Args a) {
@@ -1985,18 +2008,21 @@ int tile_kalign(int fmt, const Tile& t) {
 // (R, WR, WK, U, NT): the candidate set the autotuner times, per kernel family
 #define BS32_F64_TILES(X)                                                                                   \
   X(1, 4, 1, 4, 0) X(2, 1, 4, 2, 0) X(2, 2, 2, 2, 0) X(4, 1, 4, 2, 0) X(1, 1, 8, 2, 0) X(1, 1, 4, 8, 0)     \
-  X(2, 1, 4, 4, 0) X(1, 1, 8, 4, 0) X(2, 1, 4, 2, 1) X(4, 1, 4, 2, 1) X(1, 1, 4, 8, 1) X(2, 1, 8, 4, 0)
+  X(2, 1, 4, 4, 0) X(1, 1, 8, 4, 0) X(2, 1, 4, 2, 1) X(4, 1, 4, 2, 1) X(1, 1, 4, 8, 1) X(2, 1, 8, 4, 0)     \
+  X(2, 2, 2, 2, 1) X(4, 2, 2, 2, 1)
 #define BS32_F32_TILES(X)                                                                                   \
   X(1, 4, 1, 2, 0) X(1, 1, 4, 2, 0) X(2, 1, 4, 2, 0) X(1, 1, 8, 2, 0) X(1, 1, 4, 4, 0) X(2, 1, 4, 4, 0)     \
   X(1, 1, 8, 4, 0) X(2, 1, 4, 2, 1) X(1, 1, 8, 4, 1)
 #define BS32_MMA_TILES(X)                                                                    \
   X(1, 1, 8, 2, 0) X(1, 1, 8, 4, 0) X(1, 1, 8, 8, 0) X(2, 1, 8, 4, 0) X(1, 1, 4, 8, 0) X(2, 1, 4, 4, 0) \
-  X(1, 1, 8, 4, 1) X(2, 1, 8, 4, 1) X(1, 1, 4, 4, 0) X(1, 1, 4, 8, 1) X(1, 1, 8, 8, 1)
+  X(1, 1, 8, 4, 1) X(2, 1, 8, 4, 1) X(1, 1, 4, 4, 0) X(1, 1, 4, 8, 1) X(1, 1, 8, 8, 1) X(2, 1, 4, 4, 1) \
+  X(1, 1, 4, 4, 1) X(2, 2, 2, 4, 0) X(2, 2, 2, 4, 1) X(2, 4, 1, 4, 0) X(2, 4, 1, 4, 1) X(1, 4, 1, 4, 0)  \
+  X(1, 4, 1, 4, 1) X(2, 8, 1, 4, 1) X(2, 4, 1, 2, 1)
 
 // the matrix-core tiles that also run with an epilogue wave: one 16-row tile per wave and
 // batches of at most four steps (the others would spill with the extra wave's share of
-// the register file)
-#define BS32_MMA_EW_OK(R_, U_) ((R_) == 1 && (U_) <= 4)
+// the register file), and at most 32 rows per block (two lanes per row in one wave)
+#define BS32_MMA_EW_OK(R_, WR_, U_) ((R_) == 1 && (U_) <= 4 && (WR_) <= 2)
 
 // pairwise kernels: (R rows per wave, WV waves, UJ column chunks per step)
 #define BS32_PAIR_TILES(X) X(2, 4, 1) X(4, 4, 1) X(8, 4, 1) X(4, 4, 2)
@@ -2010,8 +2036,11 @@ int tile_kalign(int fmt, const Tile& t) {
 #define BS32_TILE_MMA(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 1},
 #define BS32_TILE_VALU_EW(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 0, 1},
 #define BS32_TILE_MMA_EW(R_, WR_, WK_, U_, NT_) BS32_TILE_MMA_EW_##R_##_##U_(R_, WR_, WK_, U_, NT_)
-#define BS32_TILE_MMA_EW_1_2(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 1, 1},
-#define BS32_TILE_MMA_EW_1_4(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 1, 1},
+#define BS32_TILE_MMA_EW_1_2(R_, WR_, WK_, U_, NT_) BS32_TILE_MMA_EW_W##WR_(R_, WR_, WK_, U_, NT_)
+#define BS32_TILE_MMA_EW_1_4(R_, WR_, WK_, U_, NT_) BS32_TILE_MMA_EW_W##WR_(R_, WR_, WK_, U_, NT_)
+#define BS32_TILE_MMA_EW_W1(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 1, 1},
+#define BS32_TILE_MMA_EW_W2(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 1, 1},
+#define BS32_TILE_MMA_EW_W4(R_, WR_, WK_, U_, NT_)
 #define BS32_TILE_MMA_EW_1_8(R_, WR_, WK_, U_, NT_)
 #define BS32_TILE_MMA_EW_2_2(R_, WR_, WK_, U_, NT_)
 #define BS32_TILE_MMA_EW_2_4(R_, WR_, WK_, U_, NT_)
@@ -2034,6 +2063,9 @@ static const Tile kSharedTiles[] = {BS32_SHARED_TILES(BS32_TILE_SHARED) Tile{1, 
 #undef BS32_TILE_MMA_EW
 #undef BS32_TILE_MMA_EW_1_2
 #undef BS32_TILE_MMA_EW_1_4
+#undef BS32_TILE_MMA_EW_W1
+#undef BS32_TILE_MMA_EW_W2
+#undef BS32_TILE_MMA_EW_W4
 #undef BS32_TILE_MMA_EW_1_8
 #undef BS32_TILE_MMA_EW_2_2
 #undef BS32_TILE_MMA_EW_2_4
@@ -2194,7 +2226,7 @@ template <int FMT, int M, int T>
 hipError_t launch_mma(const Launch& L, const Tile& t) {
 #define X(R_, WR_, WK_, U_, NT_)                                                            \
   if (t.R == R_ && t.WR == WR_ && t.WK == WK_ && t.U == U_ && t.NT == NT_) {                \
-    BS32_LAUNCH_IF(BS32_MMA_EW_OK(R_, U_), (k_contract_mfma<FMT, M, T, R_, WR_, WK_, U_, NT_, true>), \
+    BS32_LAUNCH_IF(BS32_MMA_EW_OK(R_, WR_, U_), (k_contract_mfma<FMT, M, T, R_, WR_, WK_, U_, NT_, true>), \
                    (k_contract_mfma<FMT, M, T, R_, WR_, WK_, U_, NT_, false>),                 \
                    (k_group_mfma<FMT, M, T, R_, WR_, WK_, U_, NT_>), WR_ * WK_ * 64)           \
   }

@@ -104,6 +104,45 @@ def test_batch_reduced_equals_single(bs, mode):
         s.set_options(tile=-1)
 
 
+@pytest.mark.parametrize("mode", [0, 1, 2, 4])
+def test_batch_every_tile_tracks_oracle(bs, orc, mode):
+    """Every grouped contraction tile, forced one by one: a short batch solve of
+    instances of ragged N against the oracle's solve in the same storage mode (a
+    tile that left rows or operand columns unfinished would fail it)."""
+    b, s = bs
+    ws = _members(4, 11, t1=0.3)
+    refs = [orc.bs32_solve(w["kind"], w["n"], w["y0"], 0.0, 0.3, 1e-6, A=w["A"], param=w["param"],
+                           gain=w["gain"], mode=mode)[0] for w in ws]
+    y0 = np.concatenate([w["y0"] for w in ws])
+    bar = 1e-10 if mode == 0 else 2e-5
+    s.set_ensemble(ws)
+    k, checked = 0, 0
+    try:
+        while True:
+            s.set_options(tile=k)
+            say(f"[batch tile] mode {mode} tile {k}")
+            try:
+                y, st, _ = s.solve_batch(y0, 0.0, 0.3, 1e-6, mode=mode)
+            except b.BS32Error as e:
+                if e.code == b.EUNSUPPORTED:  # single-system tile (epilogue wave)
+                    k += 1
+                    continue
+                assert e.code == b.EINVAL and k > 0  # past the last candidate
+                break
+            assert np.all(st == 0), k
+            off = 0
+            for w, ref in zip(ws, refs):
+                m = w["y0"].size
+                rel = np.linalg.norm(y[off:off + m] - ref) / np.linalg.norm(ref)
+                assert rel <= bar, (k, w["n"], rel)
+                off += m
+            k += 1
+            checked += 1
+    finally:
+        s.set_options(tile=-1)
+    assert checked >= 8
+
+
 def test_batch_autotuned_and_failures(bs, orc):
     b, s = bs
     ws = _members(12, 8, t1=1.5)

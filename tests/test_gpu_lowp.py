@@ -141,6 +141,36 @@ def test_every_tile_matches_oracle(bs, orc, mode):
     assert k >= 8
 
 
+@pytest.mark.parametrize("mode", [1, 2, 4])
+def test_every_tile_solve_tracks_oracle(bs, orc, mode):
+    """Every contraction tile, forced one by one, through a short solve (every stage
+    kind, both operand columns, the controller) against the oracle's solve in the same
+    storage mode."""
+    b, s = bs
+    w = workloads.kuramoto(777, seed=77, t1=0.3)
+    s.set_workload(w)
+    ref, rst, _ = orc.bs32_solve(w["kind"], w["n"], w["y0"], 0.0, 0.3, 1e-6, A=w["A"], param=w["param"],
+                                 gain=w["gain"], mode=mode)
+    assert rst["status"] == 0
+    k = 0
+    try:
+        while True:
+            s.set_options(tile=k)
+            say(f"[tile solve] mode {mode} tile {k}")
+            try:
+                y, st = s.solve(w["y0"], 0.0, 0.3, 1e-6, mode=mode)
+            except b.BS32Error as e:
+                assert e.code == b.EINVAL and k > 0  # past the last candidate
+                break
+            rel = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+            assert st["status"] == 0 and rel <= 2e-5, (k, rel)
+            assert abs(st["n_accept"] - rst["n_accept"]) <= 2, k
+            k += 1
+    finally:
+        s.set_options(tile=-1)
+    assert k >= 8
+
+
 def test_lowp_reproducible(bs):
     b, s = bs
     w = workloads.kuramoto(1024, seed=74, t1=1.0)
