@@ -118,6 +118,12 @@ def sources_hash():
     return h.hexdigest()[:16]
 
 
+def group_kernel(name):
+    """The grouped (ensemble) kernel instance of a single-system kernel name: the same
+    tile parameters without the last one (the epilogue wave, single systems only)."""
+    return name.replace("k_contract_", "k_group_").replace(", false>", ">")
+
+
 def traffic_lookup(workload, mode_name, kernel):
     """HBM bytes per launch of the contraction kernel from the committed PMC summary
     (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when the summary has
@@ -787,8 +793,8 @@ def bench_ensemble(args, torch, bs, modes, ref_rtol):
     for m in results:
         results[m]["error_ratio_vs_fp64_median"] = None if errs is None else med_ratio(m)
     roof = roofline(rh["contraction_ms"], pairs_total * BYTES[min(head, 4)],
-                    rh["kernel"].replace("k_contract_", "k_group_") + f" over {B} instances",
-                    traffic_lookup(f"kuramoto_ensemble{B}", rh["name"], rh["kernel"].replace("k_contract_", "k_group_")))
+                    group_kernel(rh["kernel"]) + f" over {B} instances",
+                    traffic_lookup(f"kuramoto_ensemble{B}", rh["name"], group_kernel(rh["kernel"])))
     line = base_line(args, rh["pairs_per_s"], rh["ms_per_step"], DTYPE[min(head, 4)] + "+f64-update",
                      {"workload": f"kuramoto-ensemble B={B} N=logU[256,8192] K=U[0.5,4) t=[0,{t1:g}] "
                                   f"rtol=atol={rtol:g} seed=4000", "precision_mode": rh["name"],
