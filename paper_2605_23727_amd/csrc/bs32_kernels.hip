@@ -1342,6 +1342,70 @@ int shared_cols(int fmt, int m) {
 }
 #endif
 
+// Row epilogues of a shared-coupling product tile: the P tile sP [BM][BN + 1] of row
+// block rb and column block cb is in LDS; BM consecutive threads serve one instance.
+template <int FMT, int M, int BM, int BN, typename PT>
+__device__ __forceinline__ void shared_rows(const Shared& sh, int rb, int cb, const PT* sP, double* sRed0,
+                                            double* sRed1) {
+  constexpr int T = FMT == F_F64 ? 1 : 2;
+  constexpr int C = M * T, IB = BN / C, PP = BN + 1;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int stage = sh.stage;
+  const bool reduce = !(stage == ST_S2 || stage == ST_S3 || stage == ST_RHS);
+  for (int e0 = 0; e0 < BM * IB; e0 += 256) {
+    const int e = e0 + tid;
+    // BM is a multiple of 64, so a wave serves one instance: its index is wave-uniform
+    // and the instance's arguments come through scalar loads
+    const int ib = __builtin_amdgcn_readfirstlane(e / BM), row = e % BM;
+    const int b = cb * IB + ib;
+    double r0 = 0.0, r1 = 0.0;
+    if (b < sh.B) {
+      const Args& a = sh.inst[((size_t)b * kStages + stage) * 2 + sh.par];
+      const Ctl* ctl = a.ctl;
+      const long long i = (long long)rb * BM + row;
+      if (ctl->status == kRunning && i < a.n) {
+        RowIn rin;
+        load_row(a, ctl, i, rin);
+        double P[2] = {0.0, 0.0};
+#pragma unroll
+        for (int mm = 0; mm < M; ++mm) {
+          double p = 0.0;
+#pragma unroll
+          for (int tt = 0; tt < T; ++tt) p += ldexp((double)sP[row * PP + ib * C + mm * T + tt], -tt * sh.vshift);
+          P[mm] = sh.scale * p;
+        }
+        epilogue<sh_opfmt<FMT>(), true>(a, ctl, i, P, rin, &r0, &r1, -1);
+      }
+    }
+    if (!reduce) continue;
+    r0 = wave_nanmax(r0);
+    r1 = wave_nanmax(r1);
+    if (lane == 0) {
+      sRed0[w] = r0;
+      sRed1[w] = r1;
+    }
+    __syncthreads();
+    constexpr int WPI = BM / 64;  // waves per instance in one pass
+    if (tid < 4 && tid % WPI == 0) {
+      const int ibq = (e0 + 64 * tid) / BM;
+      const int bq = cb * IB + ibq;
+      double m0 = sRed0[tid], m1 = sRed1[tid];
+      for (int q = 1; q < WPI; ++q) {
+        m0 = nanmax(m0, sRed0[tid + q]);
+        m1 = nanmax(m1, sRed1[tid + q]);
+      }
+      if (bq < sh.B) {
+        const Args& a = sh.inst[((size_t)bq * kStages + stage) * 2 + sh.par];
+        if (a.ctl->status == kRunning) {
+          a.ep0[rb] = m0;
+          a.ep1[rb] = m1;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <int FMT, int M, int RT, int CT, bool FROMP = false>
 __global__ __launch_bounds__(256) void k_shared_contract(Shared sh) {
   constexpr int ES = FMT == F_F64 ? 8 : FMT == F_F32 ? 4 : 2;  // bytes per element of A (per plane) and operand
@@ -1525,60 +1589,146 @@ __global__ __launch_bounds__(256) void k_shared_contract(Shared sh) {
   }
   __syncthreads();
 
-  // row epilogues: BM consecutive threads serve one instance
-  const bool reduce = !(stage == ST_S2 || stage == ST_S3 || stage == ST_RHS);
-  for (int e0 = 0; e0 < BM * IB; e0 += 256) {
-    const int e = e0 + tid;
-    // BM is a multiple of 64, so a wave serves one instance: its index is wave-uniform
-    // and the instance's arguments come through scalar loads
-    const int ib = __builtin_amdgcn_readfirstlane(e / BM), row = e % BM;
-    const int b = cb * IB + ib;
-    double r0 = 0.0, r1 = 0.0;
-    if (b < sh.B) {
-      const Args& a = sh.inst[((size_t)b * kStages + stage) * 2 + sh.par];
-      const Ctl* ctl = a.ctl;
-      const long long i = (long long)rb * BM + row;
-      if (ctl->status == kRunning && i < a.n) {
-        RowIn rin;
-        load_row(a, ctl, i, rin);
-        double P[2] = {0.0, 0.0};
+  shared_rows<FMT, M, BM, BN>(sh, rb, cb, sP, sRed0, sRed1);
+}
+
+// Shared-coupling product for 16-bit storage as an LDS-tiled matrix product: tiles of
+// BM = 64 RT rows by BN = 16 CT columns, four waves in a 2 x 2 grid (each BM/2 x BN/2,
+// (BM/32) x (BN/32) matrix-core tiles of 16 x 16), 64 elements of k per stage.  Both
+// operands go from memory through registers into LDS (two LDS buffers), and the loads
+// of stage s + 2 are issued before the products of stage s, so two stages of latency
+// are covered.  Every A and operand fragment read from LDS feeds BN/32 or BM/32 matrix-
+// core products.  FP32 accumulation over the whole k (both planes of the BF16 pair go
+// into one accumulator); the P tile then takes the LDS and the row epilogues follow.
+constexpr int kGemmBK = 128;               // bytes of k per stage (64 16-bit elements; a multiple of 64)
+constexpr int kGemmPitch = kGemmBK + 16;   // LDS pitch of one row or operand column
+
+template <int FMT, int RT, int CT>
+constexpr int gemm_lds_bytes() {
+  constexpr int PL = FMT == F_BF16X2 ? 2 : 1, BM = 64 * RT, BN = 16 * CT;
+  constexpr int tiles = 2 * (PL * BM + BN) * kGemmPitch, part = BM * (BN + 1) * 4;
+  return tiles > part ? tiles : part;
+}
+
+template <int FMT, int M, int RT, int CT>
+__global__ __launch_bounds__(256) void k_shared_gemm(Shared sh) {
+  static_assert(FMT == F_BF16 || FMT == F_F16 || FMT == F_BF16X2, "16-bit storage");
+  constexpr int ES = 2, T = 2, C = M * T;
+  constexpr int PL = FMT == F_BF16X2 ? 2 : 1;
+  constexpr int BM = 64 * RT, BN = 16 * CT, IB = BN / C, PP = BN + 1;
+  constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
+  constexpr int SP = kGemmPitch, ABYTES = PL * BM * SP, STB = ABYTES + BN * SP;
+  constexpr int LA = PL * BM * kGemmBK / 16 / 256, LB = BN * kGemmBK / 16 / 256;  // 16-byte loads per thread
+  static_assert(BN % C == 0 && LA * 4096 == PL * BM * kGemmBK && LB * 4096 == BN * kGemmBK, "tile shape");
+  static_assert(kGemmBK % 64 == 0, "whole matrix-core steps of 32 elements per stage");
+  __shared__ __align__(16) char smem[gemm_lds_bytes<FMT, RT, CT>()];
+  __shared__ double sRed0[4], sRed1[4];
+
+  // XCD-aware tile order, as in k_shared_contract
+  const int total = sh.nrb * sh.ncb;
+  const int per = (total + 7) / 8;
+  const int lin = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (lin >= total) return;
+  const int rb = lin / sh.ncb, cb = lin % sh.ncb;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int wm = w >> 1, wn = w & 1;
+  const int stage = sh.stage;
+  {
+    int live = 0;
+    if (tid < IB) {
+      const int b = cb * IB + tid;
+      if (b < sh.B) live = sh.inst[((size_t)b * kStages + stage) * 2 + sh.par].ctl->status == kRunning;
+    }
+    if (!__syncthreads_or(live)) return;
+  }
+
+  const long long ld = sh.ld;
+  const long long plane = sh.np * ld * ES;
+  const char* const Ab = (const char*)sh.A + (long long)rb * BM * ld * ES;
+  const char* const Bb = (const char*)sh.Bop[vin_of(stage)] + (long long)cb * BN * ld * ES;
+  // load unit u = tid + 256 q: row u / SEG of the stacked rows (A: PL planes of BM rows;
+  // operand: BN columns), 16-byte segment u % SEG of the stage's kGemmBK bytes
+  constexpr int SEG = kGemmBK / 16;
+  auto gload = [&](u32x4 (&ra)[LA], u32x4 (&rv)[LB], long long st) {
 #pragma unroll
-        for (int mm = 0; mm < M; ++mm) {
-          double p = 0.0;
+    for (int q = 0; q < LA; ++q) {
+      const int u = tid + 256 * q, r = u / SEG, seg = u % SEG;
+      const int pl = r / BM, row = r % BM;
+      ra[q] = *(const u32x4*)(Ab + pl * plane + (long long)row * ld * ES + st * kGemmBK + seg * 16);
+    }
 #pragma unroll
-          for (int tt = 0; tt < T; ++tt) p += ldexp((double)sP[row * PP + ib * C + mm * T + tt], -tt * sh.vshift);
-          P[mm] = sh.scale * p;
+    for (int q = 0; q < LB; ++q) {
+      const int u = tid + 256 * q, col = u / SEG, seg = u % SEG;
+      rv[q] = *(const u32x4*)(Bb + (long long)col * ld * ES + st * kGemmBK + seg * 16);
+    }
+  };
+  auto sstore = [&](const u32x4 (&ra)[LA], const u32x4 (&rv)[LB], int buf) {
+    char* base = smem + buf * STB;
+#pragma unroll
+    for (int q = 0; q < LA; ++q) {
+      const int u = tid + 256 * q;
+      *(u32x4*)(base + (u / SEG) * SP + (u % SEG) * 16) = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+      const int u = tid + 256 * q;
+      *(u32x4*)(base + ABYTES + (u / SEG) * SP + (u % SEG) * 16) = rv[q];
+    }
+  };
+  f32x4 c[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) c[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  auto compute = [&](int buf) {
+    const char* base = smem + buf * STB;
+#pragma unroll
+    for (int ks = 0; ks < kGemmBK / 64; ++ks) {  // 32 elements of k per matrix-core step
+      u32x4 bf[TN];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bf[j] = *(const u32x4*)(base + ABYTES + (wn * WN + 16 * j + r16) * SP + ks * 64 + g * 16);
+#pragma unroll
+      for (int pl = 0; pl < PL; ++pl)
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          const u32x4 af = *(const u32x4*)(base + (pl * BM + wm * WM + 16 * i + r16) * SP + ks * 64 + g * 16);
+#pragma unroll
+          for (int j = 0; j < TN; ++j) c[i][j] = mma<sh_opfmt<FMT>()>(af, bf[j], c[i][j]);
         }
-        epilogue<sh_opfmt<FMT>(), true>(a, ctl, i, P, rin, &r0, &r1, -1);
-      }
     }
-    if (!reduce) continue;
-    r0 = wave_nanmax(r0);
-    r1 = wave_nanmax(r1);
-    if (lane == 0) {
-      sRed0[w] = r0;
-      sRed1[w] = r1;
-    }
+  };
+  const long long nst = ld * ES / kGemmBK;
+  u32x4 ra0[LA], rv0[LB], ra1[LA], rv1[LB];
+  gload(ra0, rv0, 0);
+  if (nst > 1) gload(ra1, rv1, 1);
+  sstore(ra0, rv0, 0);
+  __syncthreads();
+  for (long long st = 0; st < nst; st += 2) {
+    // stage st is in LDS buffer 0 and stage st + 1 in flight to ra1 / rv1
+    if (st + 2 < nst) gload(ra0, rv0, st + 2);
+    compute(0);
+    if (st + 1 >= nst) break;
+    sstore(ra1, rv1, 1);
     __syncthreads();
-    constexpr int WPI = BM / 64;  // waves per instance in one pass
-    if (tid < 4 && tid % WPI == 0) {
-      const int ibq = (e0 + 64 * tid) / BM;
-      const int bq = cb * IB + ibq;
-      double m0 = sRed0[tid], m1 = sRed1[tid];
-      for (int q = 1; q < WPI; ++q) {
-        m0 = nanmax(m0, sRed0[tid + q]);
-        m1 = nanmax(m1, sRed1[tid + q]);
-      }
-      if (bq < sh.B) {
-        const Args& a = sh.inst[((size_t)bq * kStages + stage) * 2 + sh.par];
-        if (a.ctl->status == kRunning) {
-          a.ep0[rb] = m0;
-          a.ep1[rb] = m1;
-        }
-      }
-    }
+    if (st + 3 < nst) gload(ra1, rv1, st + 3);
+    compute(1);
+    if (st + 2 >= nst) break;
+    sstore(ra0, rv0, 0);
     __syncthreads();
   }
+  __syncthreads();  // every wave is done with the tiles: the LDS now takes P
+
+  float* sP = (float*)smem;
+  // C layout: lane (r16, g) holds column r16 of each 16 x 16 tile, rows 4 g + i
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) sP[(wm * WM + 16 * i + 4 * g + e) * PP + wn * WN + 16 * j + r16] = c[i][j][e];
+  __syncthreads();
+  shared_rows<FMT, M, BM, BN>(sh, rb, cb, sP, sRed0, sRed1);
 }
 
 // elementary controller (reading of the unspecified step-size correction; the
@@ -2030,6 +2180,8 @@ int tile_kalign(int fmt, const Tile& t) {
 // shared-coupling products: (RT 16-row tiles per wave, CT 16-column tiles), four waves;
 // RT = 4 only for 16-bit storage (its FP32 P tile fits the LDS)
 #define BS32_SHARED_TILES(X) X(2, 4) X(1, 8) X(1, 4) X(2, 2) X(4, 4) X(4, 2)
+// LDS-tiled products of 16-bit storage (k_shared_gemm): (RT, CT), tiles of 64 RT x 16 CT
+#define BS32_GEMM_TILES(X) X(2, 8) X(2, 4) X(1, 8)
 
 #if BS32_IN(0)
 #define BS32_TILE_VALU(R_, WR_, WK_, U_, NT_) Tile{R_, WR_, WK_, U_, NT_, 0},
@@ -2054,9 +2206,11 @@ static const Tile kMmaTiles[] = {BS32_MMA_TILES(BS32_TILE_MMA) BS32_MMA_TILES(BS
 static const Tile kPairTiles[] = {BS32_PAIR_TILES(BS32_TILE_PAIR)};
 #undef BS32_TILE_PAIR
 #define BS32_TILE_SHARED(RT_, CT_) Tile{RT_, 4, 1, CT_, 0, 3},
+#define BS32_TILE_GEMM(RT_, CT_) Tile{RT_, 4, 2, CT_, 0, 3},
 static const Tile kSharedTiles[] = {BS32_SHARED_TILES(BS32_TILE_SHARED) Tile{1, 4, 1, 8, 1, 3}, Tile{1, 4, 1, 4, 1, 3},
-                                     Tile{1, 4, 1, 2, 1, 3}};
+                                     Tile{1, 4, 1, 2, 1, 3}, BS32_GEMM_TILES(BS32_TILE_GEMM)};
 #undef BS32_TILE_SHARED
+#undef BS32_TILE_GEMM
 #undef BS32_TILE_VALU
 #undef BS32_TILE_MMA
 #undef BS32_TILE_VALU_EW
@@ -2132,6 +2286,23 @@ static hipError_t launch_shared_t(const Shared* sh, const Tile& t, hipStream_t s
         }
         return hipGetLastError();
       }
+    }
+    return hipErrorInvalidValue;
+  }
+  if (t.WK == 2) {  // LDS-tiled product: 16-bit storage
+    if constexpr (FMT == F_BF16 || FMT == F_F16 || FMT == F_BF16X2) {
+#define G(RT_, CT_)                                                                 \
+  if (t.R == RT_ && t.U == CT_) {                                                   \
+    if constexpr (gemm_lds_bytes<FMT, RT_, CT_>() > 160 * 1024) {                   \
+      return hipErrorInvalidValue;                                                  \
+    } else {                                                                        \
+      if (!sh) return hipSuccess;                                                   \
+      if (total > 0) k_shared_gemm<FMT, M, RT_, CT_><<<grid, 256, 0, s>>>(*sh);    \
+      return hipGetLastError();                                                     \
+    }                                                                               \
+  }
+      BS32_GEMM_TILES(G)
+#undef G
     }
     return hipErrorInvalidValue;
   }
@@ -2304,6 +2475,7 @@ int kernel_name(int fmt, int m, const Tile& t, char* buf, size_t cap) {
   const char* nt = t.NT ? "true" : "false";
   if (t.MM == 3 && t.NT)
     return snprintf(buf, cap, "hipBLASLt product + k_shared_contract<%d, %d, %d, %d, true>", fmt, m, t.R, t.U);
+  if (t.MM == 3 && t.WK == 2) return snprintf(buf, cap, "k_shared_gemm<%d, %d, %d, %d>", fmt, m, t.R, t.U);
   if (t.MM == 3) return snprintf(buf, cap, "k_shared_contract<%d, %d, %d, %d>", fmt, m, t.R, t.U);
   if (t.MM == 2)  // the system kind and weights also select the instance: name the family and tile
     return snprintf(buf, cap, "k_contract_pair<*, %s, *, %d, %d, %d>", fmt == F_F32 ? "true" : "false", t.R, t.WR,

@@ -95,9 +95,10 @@ def test_shared_fp64_matches_oracle(bs, orc, kind, n, B):
 
 LIBRARY_TILE = 6   # hipBLASLt product + the kernel's row epilogues (16-bit storage), 64 x 128 tiles
 LIBRARY_TILES = (6, 7, 8)   # the same with 64 x 128, 64 x 64 and 64 x 32 epilogue tiles
+GEMM_TILES = (9, 10, 11)   # LDS-tiled products of 16-bit storage: 128 x 128, 128 x 64, 64 x 128
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, *LIBRARY_TILES])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, *LIBRARY_TILES, *GEMM_TILES])
 @pytest.mark.parametrize("mode", [0, 1, 2, 3, 8])
 def test_shared_every_tile(bs, orc, tile, mode):
     """Every instantiated product tile in every storage format, on a ragged N and a
@@ -110,13 +111,14 @@ def test_shared_every_tile(bs, orc, tile, mode):
     s.set_options(tile=tile)
     try:
         s.set_shared_ensemble(base["kind"], 333, 37, A=base["A"], params=params, gains=gains)
-        served = (2, 3, 8) if tile in LIBRARY_TILES else (2, 3) if tile >= 4 else (0, 1, 2, 3, 8)
+        served = (2, 3, 8) if tile in LIBRARY_TILES + GEMM_TILES else (2, 3) if tile >= 4 else (0, 1, 2, 3, 8)
         if mode not in served:   # the 256-row tiles serve BF16 and FP16, the library 16-bit storage
             with pytest.raises(b.BS32Error):
                 s.kernel_name(mode, tile)
             return
         name = s.kernel_name(mode, tile)
-        assert name.startswith("hipBLASLt product + k_shared_contract<" if tile in LIBRARY_TILES else "k_shared_contract<")
+        assert name.startswith("hipBLASLt product + k_shared_contract<" if tile in LIBRARY_TILES else
+                               "k_shared_gemm<" if tile in GEMM_TILES else "k_shared_contract<")
         y, st, _ = s.solve_batch(y0.reshape(-1), 0.0, t1, 1e-6, mode=mode)
         assert np.all(st == 0)
         Y = y.reshape(37, -1)
