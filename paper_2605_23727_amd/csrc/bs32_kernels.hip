@@ -1343,66 +1343,93 @@ int shared_cols(int fmt, int m) {
 #endif
 
 // Row epilogues of a shared-coupling product tile: the P tile sP [BM][BN + 1] of row
-// block rb and column block cb is in LDS; BM consecutive threads serve one instance.
+// block rb and column block cb is in LDS.  The workgroup makes BM IB / 256 passes over
+// the (row, instance) pairs, BM consecutive threads per instance (so a wave serves one
+// instance and its arguments come through scalar loads); the row inputs of the next
+// pass are requested before the current pass's epilogues, and the block maxima are
+// gathered per pass and written once at the end.
 template <int FMT, int M, int BM, int BN, typename PT>
-__device__ __forceinline__ void shared_rows(const Shared& sh, int rb, int cb, const PT* sP, double* sRed0,
-                                            double* sRed1) {
+__device__ __forceinline__ void shared_rows(const Shared& sh, int rb, int cb, const PT* sP) {
   constexpr int T = FMT == F_F64 ? 1 : 2;
   constexpr int C = M * T, IB = BN / C, PP = BN + 1;
+  constexpr int NPASS = BM * IB / 256;  // passes over the tile's (row, instance) pairs
+  constexpr int WPI = BM / 64;          // waves per instance in one pass
+  static_assert(NPASS * 256 == BM * IB && BM % 64 == 0, "whole waves per instance and pass");
+  __shared__ double sMax[2][NPASS][4];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int stage = sh.stage;
   const bool reduce = !(stage == ST_S2 || stage == ST_S3 || stage == ST_RHS);
-  for (int e0 = 0; e0 < BM * IB; e0 += 256) {
-    const int e = e0 + tid;
-    // BM is a multiple of 64, so a wave serves one instance: its index is wave-uniform
-    // and the instance's arguments come through scalar loads
-    const int ib = __builtin_amdgcn_readfirstlane(e / BM), row = e % BM;
-    const int b = cb * IB + ib;
-    double r0 = 0.0, r1 = 0.0;
+  struct Pair {
+    const Args* a;
+    long long i;
+    int row, ib;
+    bool live;
+  };
+  auto pair_of = [&](int p) {
+    Pair q;
+    const int e = 256 * p + tid;
+    q.ib = __builtin_amdgcn_readfirstlane(e / BM);
+    q.row = e % BM;
+    q.i = (long long)rb * BM + q.row;
+    q.a = nullptr;
+    q.live = false;
+    const int b = cb * IB + q.ib;
     if (b < sh.B) {
-      const Args& a = sh.inst[((size_t)b * kStages + stage) * 2 + sh.par];
-      const Ctl* ctl = a.ctl;
-      const long long i = (long long)rb * BM + row;
-      if (ctl->status == kRunning && i < a.n) {
-        RowIn rin;
-        load_row(a, ctl, i, rin);
-        double P[2] = {0.0, 0.0};
+      q.a = &sh.inst[((size_t)b * kStages + stage) * 2 + sh.par];
+      q.live = q.a->ctl->status == kRunning && q.i < q.a->n;
+    }
+    return q;
+  };
+  Pair nq = pair_of(0);
+  RowIn nrin;
+  if (nq.live) load_row(*nq.a, nq.a->ctl, nq.i, nrin);
+#pragma unroll 1
+  for (int p = 0; p < NPASS; ++p) {
+    const Pair q = nq;
+    const RowIn rin = nrin;
+    if (p + 1 < NPASS) {
+      nq = pair_of(p + 1);
+      if (nq.live) load_row(*nq.a, nq.a->ctl, nq.i, nrin);
+    }
+    double r0 = 0.0, r1 = 0.0;
+    if (q.live) {
+      double P[2] = {0.0, 0.0};
 #pragma unroll
-        for (int mm = 0; mm < M; ++mm) {
-          double p = 0.0;
+      for (int mm = 0; mm < M; ++mm) {
+        double pv = 0.0;
 #pragma unroll
-          for (int tt = 0; tt < T; ++tt) p += ldexp((double)sP[row * PP + ib * C + mm * T + tt], -tt * sh.vshift);
-          P[mm] = sh.scale * p;
-        }
-        epilogue<sh_opfmt<FMT>(), true>(a, ctl, i, P, rin, &r0, &r1, -1);
+        for (int tt = 0; tt < T; ++tt) pv += ldexp((double)sP[q.row * PP + q.ib * C + mm * T + tt], -tt * sh.vshift);
+        P[mm] = sh.scale * pv;
+      }
+      epilogue<sh_opfmt<FMT>(), true>(*q.a, q.a->ctl, q.i, P, rin, &r0, &r1, -1);
+    }
+    if (reduce) {
+      r0 = wave_nanmax(r0);
+      r1 = wave_nanmax(r1);
+      if (lane == 0) {
+        sMax[0][p][w] = r0;
+        sMax[1][p][w] = r1;
       }
     }
-    if (!reduce) continue;
-    r0 = wave_nanmax(r0);
-    r1 = wave_nanmax(r1);
-    if (lane == 0) {
-      sRed0[w] = r0;
-      sRed1[w] = r1;
+  }
+  if (!reduce) return;
+  __syncthreads();
+  // one thread per (pass, instance): the first wave of the instance's group
+  if (tid < NPASS * 4 && (tid % 4) % WPI == 0) {
+    const int p = tid / 4, w0 = tid % 4;
+    const int bq = cb * IB + (256 * p + 64 * w0) / BM;
+    double m0 = sMax[0][p][w0], m1 = sMax[1][p][w0];
+    for (int q = 1; q < WPI; ++q) {
+      m0 = nanmax(m0, sMax[0][p][w0 + q]);
+      m1 = nanmax(m1, sMax[1][p][w0 + q]);
     }
-    __syncthreads();
-    constexpr int WPI = BM / 64;  // waves per instance in one pass
-    if (tid < 4 && tid % WPI == 0) {
-      const int ibq = (e0 + 64 * tid) / BM;
-      const int bq = cb * IB + ibq;
-      double m0 = sRed0[tid], m1 = sRed1[tid];
-      for (int q = 1; q < WPI; ++q) {
-        m0 = nanmax(m0, sRed0[tid + q]);
-        m1 = nanmax(m1, sRed1[tid + q]);
-      }
-      if (bq < sh.B) {
-        const Args& a = sh.inst[((size_t)bq * kStages + stage) * 2 + sh.par];
-        if (a.ctl->status == kRunning) {
-          a.ep0[rb] = m0;
-          a.ep1[rb] = m1;
-        }
+    if (bq < sh.B) {
+      const Args& a = sh.inst[((size_t)bq * kStages + stage) * 2 + sh.par];
+      if (a.ctl->status == kRunning) {
+        a.ep0[rb] = m0;
+        a.ep1[rb] = m1;
       }
     }
-    __syncthreads();
   }
 }
 
@@ -1418,7 +1445,6 @@ __global__ __launch_bounds__(256) void k_shared_contract(Shared sh) {
   static_assert(BN % C == 0, "whole instances per column block");
   using Acc = typename ShAcc<FMT>::T;
   __shared__ __align__(16) char smem[sh_lds_bytes<FMT, RT, CT, FROMP>()];
-  __shared__ double sRed0[4], sRed1[4];
 
   // XCD-aware tile order: blockIdx.x % 8 selects the XCD
   const int total = sh.nrb * sh.ncb;
@@ -1589,7 +1615,7 @@ __global__ __launch_bounds__(256) void k_shared_contract(Shared sh) {
   }
   __syncthreads();
 
-  shared_rows<FMT, M, BM, BN>(sh, rb, cb, sP, sRed0, sRed1);
+  shared_rows<FMT, M, BM, BN>(sh, rb, cb, sP);
 }
 
 // Shared-coupling product for 16-bit storage as an LDS-tiled matrix product: tiles of
@@ -1622,7 +1648,6 @@ __global__ __launch_bounds__(256) void k_shared_gemm(Shared sh) {
   static_assert(BN % C == 0 && LA * 4096 == PL * BM * kGemmBK && LB * 4096 == BN * kGemmBK, "tile shape");
   static_assert(kGemmBK % 64 == 0, "whole matrix-core steps of 32 elements per stage");
   __shared__ __align__(16) char smem[gemm_lds_bytes<FMT, RT, CT>()];
-  __shared__ double sRed0[4], sRed1[4];
 
   // XCD-aware tile order, as in k_shared_contract
   const int total = sh.nrb * sh.ncb;
@@ -1728,7 +1753,7 @@ __global__ __launch_bounds__(256) void k_shared_gemm(Shared sh) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) sP[(wm * WM + 16 * i + 4 * g + e) * PP + wn * WN + 16 * j + r16] = c[i][j][e];
   __syncthreads();
-  shared_rows<FMT, M, BM, BN>(sh, rb, cb, sP, sRed0, sRed1);
+  shared_rows<FMT, M, BM, BN>(sh, rb, cb, sP);
 }
 
 // elementary controller (reading of the unspecified step-size correction; the
