@@ -1710,17 +1710,20 @@ __global__ __launch_bounds__(256) void k_shared_gemm(Shared sh) {
     const char* base = smem + buf * STB;
 #pragma unroll
     for (int ks = 0; ks < kGemmBK / 64; ++ks) {  // 32 elements of k per matrix-core step
-      u32x4 bf[TN];
-#pragma unroll
-      for (int j = 0; j < TN; ++j) bf[j] = *(const u32x4*)(base + ABYTES + (wn * WN + 16 * j + r16) * SP + ks * 64 + g * 16);
+      u32x4 af[PL][TM];
 #pragma unroll
       for (int pl = 0; pl < PL; ++pl)
 #pragma unroll
-        for (int i = 0; i < TM; ++i) {
-          const u32x4 af = *(const u32x4*)(base + (pl * BM + wm * WM + 16 * i + r16) * SP + ks * 64 + g * 16);
+        for (int i = 0; i < TM; ++i)
+          af[pl][i] = *(const u32x4*)(base + (pl * BM + wm * WM + 16 * i + r16) * SP + ks * 64 + g * 16);
 #pragma unroll
-          for (int j = 0; j < TN; ++j) c[i][j] = mma<sh_opfmt<FMT>()>(af, bf[j], c[i][j]);
-        }
+      for (int j = 0; j < TN; ++j) {
+        const u32x4 bf = *(const u32x4*)(base + ABYTES + (wn * WN + 16 * j + r16) * SP + ks * 64 + g * 16);
+#pragma unroll
+        for (int pl = 0; pl < PL; ++pl)
+#pragma unroll
+          for (int i = 0; i < TM; ++i) c[i][j] = mma<sh_opfmt<FMT>()>(af[pl][i], bf, c[i][j]);
+      }
     }
   };
   const long long nst = ld * ES / kGemmBK;
