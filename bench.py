@@ -105,6 +105,8 @@ def parse():
                     help="MiB of a plain device copy run first (calibrates PMC byte counters)")
     ap.add_argument("--instances", type=int, default=None, help="c4 / f3: ensemble size (512 / 256)")
     ap.add_argument("--no-graph", action="store_true", help="launch attempts directly instead of from HIP graphs")
+    ap.add_argument("--tile-sweep", action="store_true",
+                    help="f3: also time every candidate product of the 16-bit modes (own kernels and the library)")
     ap.add_argument("--method", default="bs32", choices=["bs32", "dp54", "rkf45"],
                     help="single-system configs: the embedded pair (dp54: Dormand-Prince 5(4), rkf45: Fehlberg 4(5); modes 0-4)")
     return ap.parse_args()
@@ -217,47 +219,50 @@ def base_line(args, value, ms_per_step, dtype, config):
 
 
 # vector-ALU issue peak of MI355X in lane-cycles per second: 256 CUs x 4 SIMDs x 16
-# lanes x 2.4 GHz = 39.3e12, one FP32 or FP64 instruction per lane per cycle (packed
-# FP32 is not used: the published 157.3 TFLOP/s FP32 counts packed FMAs, 4 flops per
-# lane-cycle, and 78.6 TFLOP/s FP64 an FMA, 2 flops).  Transcendental instructions
-# (reciprocal, square root, ...) issue at a quarter of that rate and count 4 cycles.
-VALU_PEAK = {"f32": 256 * 4 * 16 * 2.4e9, "f64": 256 * 4 * 16 * 2.4e9}
+# lanes x 2.4 GHz = 39.3e12, one FP64 (or non-packed FP32) instruction per lane per cycle
+# (packed FP32 is not used: the published 157.3 TFLOP/s FP32 counts packed FMAs, and
+# 78.6 TFLOP/s FP64 an FMA, 2 flops, per lane-cycle).  Transcendental instructions issue
+# at a quarter of that rate and count 4 cycles.
+VALU_PEAK = 256 * 4 * 16 * 2.4e9
 
 
-def valu_ops_per_pair(workload, kernel):
-    """VALU issue lane-cycles per pair evaluation of a pairwise kernel instance, from the
-    committed PMC summary ((SQ_INSTS_VALU + 3 SQ_INSTS_VALU_TRANS_F32 + 3
-    SQ_INSTS_VALU_TRANS_F64) x 64 / pairs: a transcendental occupies four issue
-    cycles), or None."""
+def valu_profile(workload, kernel):
+    """(VALU busy %, VALU issue lane-cycles per pair) of a pairwise kernel instance from
+    the committed PMC summary, or (None, None).  Lane-cycles per pair: (SQ_INSTS_VALU +
+    3 SQ_INSTS_VALU_TRANS_F32 + 3 SQ_INSTS_VALU_TRANS_F64) x 64 / pairs; busy: the
+    VALUBusy counter."""
     path = os.path.join(ROOT, "profiles", f"valu_{workload}.md")
     if not os.path.exists(path):
-        return None
+        return None, None
     text = open(path).read()
     m = re.search(r"kernel sources sha256: ([0-9a-f]+)", text)
     if not m or m.group(1) != sources_hash():
-        return None
+        return None, None
     for line in text.splitlines():
         cells = [c.strip().strip("`") for c in line.strip().strip("|").split("|")]
-        if len(cells) >= 3 and cells[0] == kernel:
+        if len(cells) >= 8 and cells[0] == kernel:
             try:
-                return float(cells[-1])
+                return float(cells[-2]), float(cells[-1])
             except ValueError:
-                return None
-    return None
+                return None, None
+    return None, None
 
 
 def alu_roofline(workload, rh, n):
-    """Pairwise kernels are bound by the vector ALUs: achieved = pair evaluations per
-    launch x VALU lane-operations per pair / launch time, against the FP32 or FP64
-    VALU peak (the pair term's precision)."""
-    prec = "f32" if rh["name"].startswith("paper") else "f64"
-    ops = valu_ops_per_pair(workload, rh["kernel"])
+    """Pairwise kernels are bound by the vector ALUs.  The fraction is the hardware's
+    VALU busy share during the kernel (VALUBusy); achieved = that share of the issue
+    peak.  The instruction-count estimate (pair evaluations per second x VALU issue
+    lane-cycles per pair) is reported beside it: for FP32 it exceeds the 16-lane issue
+    rate, because some FP32 instructions take fewer than four cycles per wave."""
+    busy, ops = valu_profile(workload, rh["kernel"])
     pairs_per_s = n * n / (rh["contraction_ms"] * 1e-3)
-    ach = None if ops is None else pairs_per_s * ops
+    ach = None if busy is None else busy / 100.0 * VALU_PEAK
     return dict(bound="alu", achieved=None if ach is None else round(ach / 1e12, 3),
-                peak=round(VALU_PEAK[prec] / 1e12, 2), unit="T VALU lane-cycles/s",
-                frac=None if ach is None else round(ach / VALU_PEAK[prec], 4), traffic=None, kernel=rh["kernel"],
-                pair_evaluations_per_s=pairs_per_s, valu_ops_per_pair=ops, avg_launch_ms=rh["contraction_ms"])
+                peak=round(VALU_PEAK / 1e12, 2), unit="T VALU lane-cycles/s (busy)",
+                frac=None if busy is None else round(busy / 100.0, 4), traffic=None, kernel=rh["kernel"],
+                pair_evaluations_per_s=pairs_per_s, valu_issue_lane_cycles_per_pair=ops,
+                instruction_estimate_t_per_s=None if ops is None else round(pairs_per_s * ops / 1e12, 3),
+                avg_launch_ms=rh["contraction_ms"])
 
 
 MALL_BYTES = 256 << 20  # Infinity Cache of MI355X
@@ -820,6 +825,8 @@ def bench_ensemble(args, torch, bs, modes, ref_rtol):
         "roofline": roof,
         "cpu_baseline": None,
     })
+    if sweep:
+        line["tile_sweep"] = sweep
     s.close()
     return line
 
@@ -879,6 +886,31 @@ def bench_shared(args, torch, bs, modes, ref_rtol):
             kernel=s.kernel_name(mode, tot["tile"]), y=out.clone())
         log(f"  {results[mode]['time_to_t_end_s'] * 1e3:.1f} ms, {tot['n_accept']} accepted in all, product "
             f"{kms * 1e3:.1f} us ({results[mode]['contraction_tflops']:.1f} TFLOP/s), {results[mode]['kernel']}")
+    # every candidate product of the 16-bit modes, forced one by one: the project's own
+    # kernels beside the library product (HIP events, 10 launches each)
+    sweep = {}
+    if args.tile_sweep:
+        for mode in [m for m in results if m in (2, 3, 8)]:
+            rows = []
+            for i in range(64):
+                try:
+                    s.set_options(tile=i)
+                    name = s.kernel_name(mode, i)
+                    s.time_contraction(mode, 2)
+                    us = 1e3 * min(s.time_contraction(mode, 10) for _ in range(2))
+                except bs.BS32Error as e:
+                    if e.code == bs.EINVAL:
+                        break
+                    continue
+                rows.append({"tile": i, "kernel": name, "product_us": us})
+            s.set_options(tile=-1)
+            rows.sort(key=lambda r: r["product_us"])
+            sweep[bs.MODE_NAMES[mode]] = rows
+            own = [r for r in rows if not r["kernel"].startswith("hipBLASLt")]
+            lib = [r for r in rows if r["kernel"].startswith("hipBLASLt")]
+            if own and lib:
+                log(f"  {bs.MODE_NAMES[mode]}: fastest own product {own[0]['product_us']:.1f} us ({own[0]['kernel']}), "
+                    f"library {lib[0]['product_us']:.1f} us")
     # errors on the first 16 instances against an FP64 batch at ref_rtol
     errs = None
     if not args.no_ref:
