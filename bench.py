@@ -105,6 +105,9 @@ def parse():
                     help="MiB of a plain device copy run first (calibrates PMC byte counters)")
     ap.add_argument("--instances", type=int, default=None, help="c4 / f3: ensemble size (512 / 256)")
     ap.add_argument("--no-graph", action="store_true", help="launch attempts directly instead of from HIP graphs")
+    ap.add_argument("--persistent", action="store_true",
+                    help="c4: one persistent launch per chunk of attempts (device task queue) instead of one "
+                         "grouped launch per stage")
     ap.add_argument("--tile-sweep", action="store_true",
                     help="f3: also time every candidate product of the 16-bit modes (own kernels and the library)")
     ap.add_argument("--method", default="bs32", choices=["bs32", "dp54", "rkf45"],
@@ -730,6 +733,8 @@ def bench_ensemble(args, torch, bs, modes, ref_rtol):
     y0 = torch.cat([m["y0"] for m in members]).contiguous()
     offs = np.concatenate([[0], np.cumsum(ns)])
     s = bs.Solver(0)
+    if args.persistent:
+        s.set_options(ensemble_launch=1)
     torch.cuda.synchronize()
     t_setup = time.perf_counter()
     s.set_ensemble(members)
@@ -803,6 +808,7 @@ def bench_ensemble(args, torch, bs, modes, ref_rtol):
     line = base_line(args, rh["pairs_per_s"], rh["ms_per_step"], DTYPE[min(head, 4)] + "+f64-update",
                      {"workload": f"kuramoto-ensemble B={B} N=logU[256,8192] K=U[0.5,4) t=[0,{t1:g}] "
                                   f"rtol=atol={rtol:g} seed=4000", "precision_mode": rh["name"],
+                      "ensemble_launch": "persistent" if args.persistent else "grouped",
                       "global_batch": B, "seq_len": None})
     line.update({
         "time_to_t_end_s": rh["time_to_t_end_s"],
@@ -825,8 +831,6 @@ def bench_ensemble(args, torch, bs, modes, ref_rtol):
         "roofline": roof,
         "cpu_baseline": None,
     })
-    if sweep:
-        line["tile_sweep"] = sweep
     s.close()
     return line
 
@@ -984,6 +988,8 @@ def bench_shared(args, torch, bs, modes, ref_rtol):
         "roofline": roof,
         "cpu_baseline": None,
     })
+    if sweep:
+        line["tile_sweep"] = sweep
     s.close()
     return line
 

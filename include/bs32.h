@@ -153,7 +153,11 @@ typedef struct {
   int32_t controller;    /* 0 standard, 1 learned proposer (needs bs32_set_controller) */
   int32_t tile;          /* contraction tile configuration; -1 = autotuned default */
   int32_t method;        /* bs32_method: the embedded pair (default BS32_METHOD_BS32) */
-  int32_t reserved;
+  int32_t ensemble_launch; /* batches of independent systems (bs32_set_ensemble, not shared
+                            couplings): 0 (default) one grouped launch per stage of an attempt;
+                            1 one persistent launch per chunk of attempts, in which every
+                            instance advances through its own stages from a device task
+                            queue (contraction tiles of four waves only) */
 } bs32_options;
 
 /* Embedded Runge-Kutta pair of bs32_solve.  The paper's method is the

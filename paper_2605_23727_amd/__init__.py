@@ -57,7 +57,7 @@ class Options(C.Structure):
                 ("h_max", C.c_double), ("h0", C.c_double), ("safety", C.c_double), ("facmin", C.c_double),
                 ("facmax", C.c_double), ("fixed_step", C.c_int32), ("use_graph", C.c_int32),
                 ("trace", C.c_int32), ("trace_cap", C.c_int32), ("controller", C.c_int32),
-                ("tile", C.c_int32), ("method", C.c_int32), ("reserved", C.c_int32)]
+                ("tile", C.c_int32), ("method", C.c_int32), ("ensemble_launch", C.c_int32)]
 
 
 class TraceRec(C.Structure):

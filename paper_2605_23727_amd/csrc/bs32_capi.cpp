@@ -653,6 +653,8 @@ bs32_status bs32_set_options(bs32_ctx* c, const bs32_options* o) {
   if (o->controller == 1 && !c->mlp_w) return fail(c, BS32_ESTATE, "learned controller needs bs32_set_controller");
   if (o->method != BS32_METHOD_BS32 && o->method != BS32_METHOD_DP54 && o->method != BS32_METHOD_RKF45)
     return fail(c, BS32_EINVAL, "unknown method %d", o->method);
+  if (o->ensemble_launch != 0 && o->ensemble_launch != 1)
+    return fail(c, BS32_EINVAL, "ensemble_launch must be 0 or 1");
   c->opt = *o;
   free_graphs(c);
   return BS32_OK;

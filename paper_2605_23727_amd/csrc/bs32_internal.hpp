@@ -163,6 +163,31 @@ struct Group {
   int stage, par;
 };
 
+// Persistent ensemble launch: one kernel runs `attempts` attempts of every listed
+// instance.  An instance's work is a sequence of tasks, per attempt TC tasks of each
+// of the stages S2, S3, S4 (a task: G consecutive row tiles of the T) and then FC
+// finalize tasks (GF consecutive slices of 256 agents of the F), Q = 3 TC + FC tasks;
+// workgroups claim the next task of an instance from its counter `tick` and may start
+// it once `comp` (tasks completed) has reached the first task of its phase.
+struct PSched {
+  unsigned b;       // instance
+  unsigned T, G;    // row tiles of a stage; row tiles per task
+  unsigned F, GF;   // finalize slices; slices per task
+  unsigned TC, FC;  // tasks per stage, finalize tasks
+  unsigned Q;       // tasks per attempt, 3 TC + FC
+};
+struct PGroup {
+  const Args* inst;       // [(instance * kStages + stage) * 2 + parity]
+  const PSched* sched;    // listed instances
+  const unsigned* count;  // number of listed instances
+  const unsigned* xs;     // listed-instance ranges of the 8 XCDs, xs[x] .. xs[x + 1]
+  unsigned* tick;         // [listed] tasks claimed (zeroed before each launch)
+  unsigned* comp;         // [listed] tasks completed (zeroed before each launch)
+  unsigned* abort;        // set when a wait exceeded its bound: every workgroup leaves
+  int attempts;           // attempts of this launch
+  int par0;               // control parity of the first attempt
+};
+
 // Shared-coupling ensembles: B instances with one coupling matrix; the stage
 // contraction of all of them is one matrix product A [V_1 ... V_B].
 struct Shared {
@@ -211,6 +236,10 @@ hipError_t launch_set_status(Ctl* c, int code, hipStream_t s);
 hipError_t launch_contract(const Args& a, int fmt, const Tile& t, hipStream_t s);
 hipError_t launch_group_contract(const Group& g, int m, int fmt, const Tile& t, unsigned grid, hipStream_t s);
 hipError_t launch_group_prep(const Group& g, unsigned grid, hipStream_t s);
+// persistent ensemble launch (tiles of four waves; see PGroup); zeroes the counters first
+hipError_t launch_persistent(const PGroup& p, int m, int fmt, const Tile& t, unsigned grid, unsigned ncounters,
+                             hipStream_t s);
+bool tile_persistent_ok(int fmt, int m, const Tile& t);
 hipError_t launch_group_finalize(const Group& g, unsigned grid, hipStream_t s);
 hipError_t launch_shared_contract(const Shared& sh, int m, int fmt, const Tile& t, hipStream_t s);
 

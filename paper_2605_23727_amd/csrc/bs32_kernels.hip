@@ -2023,6 +2023,147 @@ __device__ __forceinline__ void finalize_block(const Args& a, int blk) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Persistent ensemble launch (PGroup): every workgroup repeatedly claims the next task
+// of a listed instance, waits until the task's phase may start, runs it (a row tile of
+// S2, S3 or S4 with the grouped contraction, or a finalize slice) and counts it done.
+// Instances advance independently, each through its own control blocks.  Claims go to
+// instances of the workgroup's own XCD first (their operand stays in that L2), then to
+// any.  A task's inputs were written by other workgroups, possibly on other XCDs: the
+// completion count is an agent-scope release by thread 0 after the workgroup barrier
+// (the barrier completes every wave's stores; the release writes the XCD's L2 back),
+// and the start an agent-scope acquire by thread 0 before the barrier (it invalidates
+// the CU's vector cache and the XCD's L2, which every wave of the workgroup reads
+// through).  Every wait is bounded; a wait that exceeds its bound sets the abort word,
+// and every workgroup then leaves.
+// ---------------------------------------------------------------------------
+// bound of one wait (for a phase to open, or for any open task): 10 s of the
+// constant-rate clock (100 MHz); the longest legitimate wait is one phase of one
+// instance, milliseconds for the sizes here
+constexpr unsigned long long kPersWaitTicks = 1000000000ULL;
+
+__device__ __forceinline__ unsigned pers_phase_start(unsigned k, const PSched& sc) {
+  const unsigned a = k / sc.Q, r = k - a * sc.Q;
+  const unsigned off = r < sc.TC ? 0u : r < 2 * sc.TC ? sc.TC : r < 3 * sc.TC ? 2 * sc.TC : 3 * sc.TC;
+  return a * sc.Q + off;
+}
+
+template <class CONTRACT>
+__device__ __forceinline__ void pers_loop(const PGroup& p, CONTRACT contract) {
+  __shared__ int s_li;
+  __shared__ unsigned s_k;
+  const int tid = threadIdx.x;
+  const unsigned n = *p.count;
+  const unsigned xcd = blockIdx.x & 7u;
+  const unsigned lo = min(p.xs[xcd], n), hi = min(p.xs[xcd + 1], n);
+  unsigned cursor = blockIdx.x >> 3;
+  unsigned long long idle_since = 0;  // thread 0: start of the current wait for an open task
+  while (true) {
+    if (tid == 0) {
+      int li_sel = -1;
+      unsigned k_sel = 0;
+      bool all_claimed = true;
+      for (int pass = 0; pass < 2 && li_sel < 0; ++pass) {
+        const unsigned base = pass == 0 ? lo : 0u, len = pass == 0 ? hi - lo : n;
+        for (unsigned q = 0; q < len; ++q) {
+          const unsigned li = base + (cursor + q) % len;
+          const PSched sc = p.sched[li];
+          const unsigned total = sc.Q * (unsigned)p.attempts;
+          const unsigned t = __hip_atomic_load(&p.tick[li], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (t >= total) continue;
+          all_claimed = false;
+          if (__hip_atomic_load(&p.comp[li], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < pers_phase_start(t, sc))
+            continue;  // its next phase is not open yet
+          const unsigned k = __hip_atomic_fetch_add(&p.tick[li], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (k >= total) continue;
+          li_sel = (int)li;
+          k_sel = k;
+          cursor = (cursor + q) % (len ? len : 1u);
+          break;
+        }
+      }
+      if (__hip_atomic_load(p.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) li_sel = -2;
+      else if (li_sel < 0 && all_claimed) li_sel = -2;
+      if (li_sel >= 0) {  // wait until the task's phase has opened
+        const unsigned need = pers_phase_start(k_sel, p.sched[li_sel]);
+        const unsigned long long w0 = wall_clock64();
+        while (__hip_atomic_load(&p.comp[li_sel], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+          if (wall_clock64() - w0 > kPersWaitTicks ||
+              __hip_atomic_load(p.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            __hip_atomic_store(p.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            li_sel = -2;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
+      s_li = li_sel;
+      s_k = k_sel;
+    }
+    __syncthreads();
+    const int li = s_li;
+    const unsigned k = s_k;
+    __syncthreads();  // every thread has read the choice before thread 0 makes the next
+    if (li == -2) return;
+    if (li == -1) {  // nothing open now: other instances' phases are still running
+      if (tid == 0) {
+        const unsigned long long now = wall_clock64();
+        if (idle_since == 0) idle_since = now;
+        else if (now - idle_since > kPersWaitTicks)
+          __hip_atomic_store(p.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_sleep(32);
+      }
+      continue;
+    }
+    if (tid == 0) idle_since = 0;
+    const PSched sc = p.sched[li];
+    const unsigned a = k / sc.Q, r = k - a * sc.Q;
+    const int par = (p.par0 + (int)a) & 1;
+    if (r < 3 * sc.TC) {
+      const int st = r < sc.TC ? ST_S2 : r < 2 * sc.TC ? ST_S3 : ST_S4;
+      const Args& args = p.inst[((size_t)sc.b * kStages + st) * 2 + par];
+      const unsigned j0 = (r % sc.TC) * sc.G, j1 = min(j0 + sc.G, sc.T);
+      for (unsigned j = j0; j < j1; ++j) {
+        contract(args, (int)j);
+        __syncthreads();
+      }
+    } else {
+      const Args& args = p.inst[((size_t)sc.b * kStages + ST_S4) * 2 + par];
+      const unsigned j0 = (r - 3 * sc.TC) * sc.GF, j1 = min(j0 + sc.GF, sc.F);
+      for (unsigned j = j0; j < j1; ++j) {
+        finalize_block(args, (int)j);
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+    if (tid == 0) __hip_atomic_fetch_add(&p.comp[li], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// the persistent kernels of the grouped tile families (four waves: the finalize slices
+// take 256 threads)
+template <int M, int R, int WR, int WK, int U, bool NT>
+__global__ __launch_bounds__(256) void k_pers_f64(PGroup p) {
+  static_assert(WR * WK == 4, "four waves");
+  pers_loop(p, [](const Args& a, int rb) { contract_f64<M, R, WR, WK, U, NT, false>(a, rb); });
+}
+template <int M, int T, int R, int WR, int WK, int U, bool NT>
+__global__ __launch_bounds__(256) void k_pers_f32(PGroup p) {
+  static_assert(WR * WK == 4, "four waves");
+  pers_loop(p, [](const Args& a, int rb) { contract_f32<M, T, R, WR, WK, U, NT, false>(a, rb); });
+}
+template <int FMT, int M, int T, int RT, int WR, int WK, int U, bool NT>
+__global__ __launch_bounds__(256, 2) void k_pers_mfma(PGroup p) {
+  static_assert(WR * WK == 4, "four waves");
+  pers_loop(p, [](const Args& a, int rb) { contract_mfma<FMT, M, T, RT, WR, WK, U, NT, false>(a, rb); });
+}
+#if BS32_IN(0)
+__global__ void k_zero_u32(unsigned* p, unsigned n) {
+  const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+#endif
+
 #if BS32_IN(0)
 __global__ __launch_bounds__(256) void k_finalize(Args a) { finalize_block(a, blockIdx.x); }
 __global__ __launch_bounds__(256) void k_group_finalize(Group g) { BS32_GROUP_LOOP(finalize_block) }
@@ -2284,6 +2425,7 @@ struct Launch {
   unsigned ggrid;
   hipStream_t s;
   bool dry;
+  const PGroup* p = nullptr;  // persistent ensemble launch (grid ggrid)
 };
 // the launchers of each kernel family (each defined in its own part)
 template <int M>
@@ -2371,8 +2513,18 @@ hipError_t launch_shared_contract(const Shared& sh, int m, int fmt, const Tile& 
 #endif
 // THREADS: the tile's streaming waves; a single-system kernel with an epilogue wave
 // (tile EW) has one more, and the grouped kernels have none
-#define BS32_LAUNCH(SINGLE_EW, SINGLE, GROUP, THREADS) BS32_LAUNCH_IF(true, SINGLE_EW, SINGLE, GROUP, THREADS)
-#define BS32_LAUNCH_IF(EWOK, SINGLE_EW, SINGLE, GROUP, THREADS)                                  \
+#define BS32_LAUNCH(SINGLE_EW, SINGLE, GROUP, PERS, THREADS) \
+  BS32_LAUNCH_IF(true, SINGLE_EW, SINGLE, GROUP, PERS, THREADS)
+#define BS32_LAUNCH_IF(EWOK, SINGLE_EW, SINGLE, GROUP, PERS, THREADS)                            \
+  if (L.p) {                                                                                     \
+    if (t.EW) return hipErrorInvalidValue;                                                       \
+    if constexpr ((THREADS) == 256) {                                                            \
+      if (!L.dry) PERS<<<L.ggrid, 256, 0, L.s>>>(*L.p);                                           \
+      return L.dry ? hipSuccess : hipGetLastError();                                             \
+    } else {                                                                                     \
+      return hipErrorInvalidValue;                                                               \
+    }                                                                                            \
+  }                                                                                              \
   if (L.g && t.EW) return hipErrorInvalidValue;                                                  \
   if constexpr (!(EWOK)) {                                                                       \
     if (t.EW) return hipErrorInvalidValue;                                                       \
@@ -2395,7 +2547,7 @@ hipError_t launch_f64(const Launch& L, const Tile& t) {
 #define X(R_, WR_, WK_, U_, NT_)                                                                 \
   if (t.R == R_ && t.WR == WR_ && t.WK == WK_ && t.U == U_ && t.NT == NT_) {                     \
     BS32_LAUNCH((k_contract_f64<M, R_, WR_, WK_, U_, NT_, true>), (k_contract_f64<M, R_, WR_, WK_, U_, NT_, false>), \
-                (k_group_f64<M, R_, WR_, WK_, U_, NT_>), WR_ * WK_ * 64)                          \
+                (k_group_f64<M, R_, WR_, WK_, U_, NT_>), (k_pers_f64<M, R_, WR_, WK_, U_, NT_>), WR_ * WK_ * 64) \
   }
   BS32_F64_TILES(X)
 #undef X
@@ -2411,7 +2563,8 @@ hipError_t launch_f32(const Launch& L, const Tile& t) {
   if (t.R == R_ && t.WR == WR_ && t.WK == WK_ && t.U == U_ && t.NT == NT_) {                           \
     BS32_LAUNCH((k_contract_f32<M, 2, R_, WR_, WK_, U_, NT_, true>),                                   \
                 (k_contract_f32<M, 2, R_, WR_, WK_, U_, NT_, false>),                                  \
-                (k_group_f32<M, 2, R_, WR_, WK_, U_, NT_>), WR_ * WK_ * 64)                             \
+                (k_group_f32<M, 2, R_, WR_, WK_, U_, NT_>), (k_pers_f32<M, 2, R_, WR_, WK_, U_, NT_>),  \
+                WR_ * WK_ * 64)                                                                        \
   }
   BS32_F32_TILES(X)
 #undef X
@@ -2427,7 +2580,8 @@ hipError_t launch_mma(const Launch& L, const Tile& t) {
   if (t.R == R_ && t.WR == WR_ && t.WK == WK_ && t.U == U_ && t.NT == NT_) {                \
     BS32_LAUNCH_IF(BS32_MMA_EW_OK(R_, WR_, U_), (k_contract_mfma<FMT, M, T, R_, WR_, WK_, U_, NT_, true>), \
                    (k_contract_mfma<FMT, M, T, R_, WR_, WK_, U_, NT_, false>),                 \
-                   (k_group_mfma<FMT, M, T, R_, WR_, WK_, U_, NT_>), WR_ * WK_ * 64)           \
+                   (k_group_mfma<FMT, M, T, R_, WR_, WK_, U_, NT_>),                           \
+                   (k_pers_mfma<FMT, M, T, R_, WR_, WK_, U_, NT_>), WR_ * WK_ * 64)            \
   }
   BS32_MMA_TILES(X)
 #undef X
@@ -2527,6 +2681,26 @@ hipError_t launch_contract(const Args& a, int fmt, const Tile& t, hipStream_t s)
 }
 hipError_t launch_group_contract(const Group& g, int m, int fmt, const Tile& t, unsigned grid, hipStream_t s) {
   return dispatch(Launch{nullptr, &g, grid, s, false}, m, fmt, t);
+}
+hipError_t launch_persistent(const PGroup& p, int m, int fmt, const Tile& t, unsigned grid, unsigned ncounters,
+                             hipStream_t s) {
+  if (!tile_persistent_ok(fmt, m, t) || grid == 0) return hipErrorInvalidValue;
+  // the counters: tick [ncounters] followed by comp [ncounters]
+  if (p.comp != p.tick + ncounters) return hipErrorInvalidValue;
+  const unsigned nz = 2 * ncounters;
+  if (nz) k_zero_u32<<<(nz + 255) / 256, 256, 0, s>>>(p.tick, nz);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  Launch L{nullptr, nullptr, grid, s, false};
+  L.p = &p;
+  return dispatch(L, m, fmt, t);
+}
+bool tile_persistent_ok(int fmt, int m, const Tile& t) {
+  if (t.MM > 1 || t.EW || t.WR * t.WK != 4) return false;
+  PGroup p{};
+  Launch L{nullptr, nullptr, 0, nullptr, true};
+  L.p = &p;
+  return dispatch(L, m, fmt, t) == hipSuccess;
 }
 hipError_t launch_group_prep(const Group& g, unsigned grid, hipStream_t s) {
   k_group_prep<<<grid, 256, 0, s>>>(g);

@@ -143,6 +143,57 @@ def test_batch_every_tile_tracks_oracle(bs, orc, mode):
     assert checked >= 8
 
 
+# (mode, tile index) pairs with four-wave tiles: FP64 (1,4,1,4) and (4,2,2,2, non-temporal);
+# FP32 matrix cores (2,4,1,4, non-temporal); BF16 (2,4,1,2, non-temporal) and (1,4,1,4)
+PERSISTENT_CASES = [(0, 0), (0, 13), (1, 25), (2, 20), (2, 17)]
+
+
+@pytest.mark.parametrize("mode,tile", PERSISTENT_CASES)
+def test_persistent_launch_equals_grouped(bs, mode, tile):
+    """One persistent launch per chunk of attempts (instances claim their own row tiles
+    and finalize slices from device counters) gives every instance exactly the result
+    of the grouped launches: same kernels, same summation order, same decisions."""
+    b, s = bs
+    ws = _members(9, 12, t1=1.2)
+    t1 = np.array([w["t1"] for w in ws])
+    t1[2] = 0.0   # empty interval
+    t1[4] = 0.35  # finishes early
+    t1[7] = 0.8
+    y0 = np.concatenate([w["y0"] for w in ws])
+    say(f"[persistent] mode {mode} tile {tile} n={[w['n'] for w in ws]}")
+    out = {}
+    try:
+        s.set_ensemble(ws)
+        for launch in (0, 1):
+            s.set_options(tile=tile, ensemble_launch=launch)
+            y, st, tot = s.solve_batch(y0, 0.0, t1, 1e-6, mode=mode)
+            assert np.all(st == 0), (launch, st)
+            out[launch] = (y, [s.batch_stats(q) for q in range(len(ws))], tot)
+    finally:
+        s.set_options(tile=-1, ensemble_launch=0)
+    assert np.array_equal(out[0][0], out[1][0])
+    for q in range(len(ws)):
+        g, p = out[0][1][q], out[1][1][q]
+        assert (g["n_accept"], g["n_reject"], g["n_fev"]) == (p["n_accept"], p["n_reject"], p["n_fev"]), q
+    assert out[0][2]["n_fev"] == out[1][2]["n_fev"]
+
+
+def test_persistent_launch_rejects_other_tiles(bs):
+    """Tiles of other than four waves have no persistent form: a forced one is refused."""
+    b, s = bs
+    ws = _members(3, 13, t1=0.2)
+    s.set_ensemble(ws)
+    try:
+        s.set_options(tile=1, ensemble_launch=1)   # BF16 (1,1,8,4): eight waves
+        with pytest.raises(b.BS32Error) as e:
+            s.solve_batch(np.concatenate([w["y0"] for w in ws]), 0.0, 0.2, 1e-6, mode=2)
+        assert e.value.code == b.EUNSUPPORTED
+    finally:
+        s.set_options(tile=-1, ensemble_launch=0)
+    with pytest.raises(b.BS32Error):
+        s.set_options(ensemble_launch=2)
+
+
 def test_batch_autotuned_and_failures(bs, orc):
     b, s = bs
     ws = _members(12, 8, t1=1.5)
