@@ -2048,6 +2048,11 @@ __device__ __forceinline__ unsigned pers_phase_start(unsigned k, const PSched& s
   return a * sc.Q + off;
 }
 
+// the finalize slices as a call: compiled apart, its registers do not add to the
+// contraction loop's (which would spill otherwise); only the few values live across
+// the call are saved around it
+__device__ __attribute__((noinline)) void pers_finalize(const Args& a, int blk) { finalize_block(a, blk); }
+
 template <class CONTRACT>
 __device__ __forceinline__ void pers_loop(const PGroup& p, CONTRACT contract) {
   __shared__ int s_li;
@@ -2131,7 +2136,7 @@ __device__ __forceinline__ void pers_loop(const PGroup& p, CONTRACT contract) {
       const Args& args = p.inst[((size_t)sc.b * kStages + ST_S4) * 2 + par];
       const unsigned j0 = (r - 3 * sc.TC) * sc.GF, j1 = min(j0 + sc.GF, sc.F);
       for (unsigned j = j0; j < j1; ++j) {
-        finalize_block(args, (int)j);
+        pers_finalize(args, (int)j);
         __syncthreads();
       }
     }

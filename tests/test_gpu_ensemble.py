@@ -178,6 +178,31 @@ def test_persistent_launch_equals_grouped(bs, mode, tile):
     assert out[0][2]["n_fev"] == out[1][2]["n_fev"]
 
 
+@pytest.mark.parametrize("mode,tile", [(1, 25), (0, 13)])
+def test_persistent_launch_large_instances(bs, mode, tile):
+    """Instances large enough that a stage spans several tasks (runs of row tiles of
+    about 4 MB) and the finalize several runs of slices, mixed with small ones: the
+    persistent launch still equals the grouped launches bit for bit."""
+    b, s = bs
+    g = np.random.default_rng(14)
+    ns = [8192, 33, 4100, 700, 2500, 64, 8191, 300]
+    ws = [workloads.kuramoto(n, seed=1400 + q, K=float(g.uniform(0.5, 4.0)), t1=0.15) for q, n in enumerate(ns)]
+    y0 = np.concatenate([w["y0"] for w in ws])
+    say(f"[persistent large] mode {mode} tile {tile} n={ns}")
+    out = {}
+    try:
+        s.set_ensemble(ws)
+        for launch in (0, 1):
+            s.set_options(tile=tile, ensemble_launch=launch)
+            y, st, _ = s.solve_batch(y0, 0.0, 0.15, 1e-6, mode=mode)
+            assert np.all(st == 0), (launch, st)
+            out[launch] = (y, [s.batch_stats(q)["n_fev"] for q in range(len(ws))])
+    finally:
+        s.set_options(tile=-1, ensemble_launch=0)
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1] == out[1][1]
+
+
 def test_persistent_launch_rejects_other_tiles(bs):
     """Tiles of other than four waves have no persistent form: a forced one is refused."""
     b, s = bs
