@@ -203,6 +203,32 @@ def test_persistent_launch_large_instances(bs, mode, tile):
     assert out[0][1] == out[1][1]
 
 
+def test_persistent_launch_learned_controller(bs):
+    """The learned proposer runs inside the finalize tasks of the persistent launch
+    (one workgroup's forward pass per finalize slice) exactly as in the grouped
+    finalize launch: same steps, same solutions."""
+    from tests import mlp_cases as mc
+    b, s = bs
+    ws = _members(6, 15, t1=1.0)
+    y0 = np.concatenate([w["y0"] for w in ws])
+    say(f"[persistent learned] n={[w['n'] for w in ws]}")
+    out = {}
+    try:
+        s.set_ensemble(ws)
+        s.set_controller(1, mc.random_net(5, scale=0.3))
+        for launch in (0, 1):
+            s.set_options(tile=25, ensemble_launch=launch)
+            y, st, _ = s.solve_batch(y0, 0.0, 1.0, 1e-6, mode=1)
+            assert np.all(st == 0), (launch, st)
+            out[launch] = (y, [(s.batch_stats(q)["n_accept"], s.batch_stats(q)["n_learned"]) for q in range(len(ws))])
+    finally:
+        s.set_controller(0)
+        s.set_options(tile=-1, ensemble_launch=0)
+    assert sum(nl for _, nl in out[0][1]) > 0
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1] == out[1][1]
+
+
 def test_persistent_launch_rejects_other_tiles(bs):
     """Tiles of other than four waves have no persistent form: a forced one is refused."""
     b, s = bs
