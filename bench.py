@@ -105,6 +105,9 @@ def parse():
                     help="MiB of a plain device copy run first (calibrates PMC byte counters)")
     ap.add_argument("--instances", type=int, default=None, help="c4 / f3: ensemble size (512 / 256)")
     ap.add_argument("--no-graph", action="store_true", help="launch attempts directly instead of from HIP graphs")
+    ap.add_argument("--label-target", type=float, default=0.9,
+                    help="c5: where the training labels aim the next error estimate, as a fraction of the "
+                         "tolerance (the library's labels aim at 0.8; 0.9 measured best: 0.95 rejects often)")
     ap.add_argument("--persistent", action="store_true",
                     help="c4: one persistent launch per chunk of attempts (device task queue) instead of one "
                          "grouped launch per stage")
@@ -1029,6 +1032,10 @@ def bench_learned(args, torch, bs, ref_rtol):
 
     t_train = time.perf_counter()
     F, Y = training_set(bs, workloads, log)
+    # the library's labels aim the next estimate at 0.8 Rel; another aim shifts every
+    # label by (1/3) log(aim / 0.8) (the estimate grows like h^3)
+    if args.label_target != 0.8:
+        Y = Y + np.float32(math.log(args.label_target / 0.8) / 3.0)
     s = bs.Solver(0)
     W, losses = s.mlp_train(F, Y, epochs=60, batch=256, lr=1e-3, seed=0)
     train_s = time.perf_counter() - t_train
@@ -1093,7 +1100,7 @@ def bench_learned(args, torch, bs, ref_rtol):
         "standard_time_to_t_end_s": k["standard"]["time_to_t_end_s"],
         "speedup_vs_standard": k["speedup_vs_standard"],
         "systems": per,
-        "training": {"samples": int(len(F)), "epochs": 60, "batch": 256, "lr": 1e-3,
+        "training": {"samples": int(len(F)), "epochs": 60, "batch": 256, "lr": 1e-3, "label_target": args.label_target,
                      "loss_first": float(losses[0]), "loss_last": float(losses[-1]), "seconds": train_s},
         "reference_rtol": None if args.no_ref else ref_rtol,
         "roofline": roofline(k["contraction_ms"], n * n * 8, k["kernel"],
