@@ -145,7 +145,7 @@ def test_batch_every_tile_tracks_oracle(bs, orc, mode):
 
 # (mode, tile index) pairs with four-wave tiles: FP64 (1,4,1,4) and (4,2,2,2, non-temporal);
 # FP32 matrix cores (2,4,1,4, non-temporal); BF16 (2,4,1,2, non-temporal) and (1,4,1,4)
-PERSISTENT_CASES = [(0, 0), (0, 13), (1, 25), (2, 20), (2, 17)]
+PERSISTENT_CASES = [(0, 0), (0, 13), (1, 25), (2, 20), (2, 17), (3, 16), (4, 16), (4, 20)]
 
 
 @pytest.mark.parametrize("mode,tile", PERSISTENT_CASES)
