@@ -2047,6 +2047,11 @@ __device__ __forceinline__ unsigned pers_phase_start(unsigned k, const PSched& s
   const unsigned off = r < sc.TC ? 0u : r < 2 * sc.TC ? sc.TC : r < 3 * sc.TC ? 2 * sc.TC : 3 * sc.TC;
   return a * sc.Q + off;
 }
+// first ticket after the phase that starts at ticket s
+__device__ __forceinline__ unsigned pers_phase_end(unsigned s, const PSched& sc) {
+  const unsigned r = s % sc.Q;
+  return s + (r < 3 * sc.TC ? sc.TC : sc.Q - 3 * sc.TC);
+}
 
 // the finalize slices as a call: compiled apart, its registers do not add to the
 // contraction loop's (which would spill otherwise); only the few values live across
@@ -2063,11 +2068,36 @@ __device__ __forceinline__ void pers_loop(const PGroup& p, CONTRACT contract) {
   const unsigned lo = min(p.xs[xcd], n), hi = min(p.xs[xcd + 1], n);
   unsigned cursor = blockIdx.x >> 3;
   unsigned long long idle_since = 0;  // thread 0: start of the current wait for an open task
+  // thread 0: a run of tasks of one instance and phase whose completions are not yet
+  // counted.  The release that counts them writes the XCD's L2 back and costs about as
+  // much as a task's other overheads together, so a run takes the instance's next ticket
+  // directly while its phase has one left and counts the run with one release; the
+  // release follows at once when the phase has no ticket left, and always comes before
+  // any wait, so a workgroup never waits while holding completions others may wait for.
+  int pend_li = -1;
+  unsigned pend_need = 0, pend_n = 0;
   while (true) {
     if (tid == 0) {
       int li_sel = -1;
       unsigned k_sel = 0;
       bool all_claimed = true;
+      if (pend_n) {  // continue the run
+        const PSched sc = p.sched[pend_li];
+        const unsigned total = sc.Q * (unsigned)p.attempts;
+        const unsigned end = min(pers_phase_end(pend_need, sc), total);
+        if (__hip_atomic_load(&p.tick[pend_li], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < end) {
+          const unsigned k = __hip_atomic_fetch_add(&p.tick[pend_li], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (k < total) {  // a later phase's ticket if others took the last ones: released below, then waited for
+            li_sel = pend_li;
+            k_sel = k;
+            all_claimed = false;
+          }
+        }
+        if (li_sel < 0) {  // the phase has no ticket left: count the run now
+          __hip_atomic_fetch_add(&p.comp[pend_li], pend_n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          pend_n = 0;
+        }
+      }
       for (int pass = 0; pass < 2 && li_sel < 0; ++pass) {
         const unsigned base = pass == 0 ? lo : 0u, len = pass == 0 ? hi - lo : n;
         for (unsigned q = 0; q < len; ++q) {
@@ -2089,8 +2119,16 @@ __device__ __forceinline__ void pers_loop(const PGroup& p, CONTRACT contract) {
       }
       if (__hip_atomic_load(p.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) li_sel = -2;
       else if (li_sel < 0 && all_claimed) li_sel = -2;
-      if (li_sel >= 0) {  // wait until the task's phase has opened
-        const unsigned need = pers_phase_start(k_sel, p.sched[li_sel]);
+      const unsigned need = li_sel >= 0 ? pers_phase_start(k_sel, p.sched[li_sel]) : 0u;
+      const bool same = li_sel >= 0 && li_sel == pend_li && need == pend_need;
+      if (!same && pend_n) {
+        __hip_atomic_fetch_add(&p.comp[pend_li], pend_n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        pend_n = 0;
+      }
+      if (li_sel >= 0 && !same) {  // wait until the task's phase has opened (the run's next
+        // task needs neither: its phase is open and its inputs already acquired)
+        pend_li = li_sel;
+        pend_need = need;
         const unsigned long long w0 = wall_clock64();
         while (__hip_atomic_load(&p.comp[li_sel], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
           if (wall_clock64() - w0 > kPersWaitTicks ||
@@ -2140,8 +2178,8 @@ __device__ __forceinline__ void pers_loop(const PGroup& p, CONTRACT contract) {
         __syncthreads();
       }
     }
-    __syncthreads();
-    if (tid == 0) __hip_atomic_fetch_add(&p.comp[li], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();  // every wave's stores of the task are done before thread 0 counts it
+    if (tid == 0) pend_n += 1;
   }
 }
 
